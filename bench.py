@@ -1,0 +1,138 @@
+"""Throughput of the manufactured-solution PIC/DSMC time step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|...]
+
+A step is one pass of the whole path: collision call A, half kick, drift, cell
+sort, deposit, Poisson CG, gradient, collision call B, half kick.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line with the
+whole-job particle-steps/s, the roofline of the dominant kernel (algorithmic
+bytes per launch over its mean launch time, from HIP events recorded on the
+library's stream during the timed region) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(stage, prob, disc, precision, cg_iters):
+    """Algorithmic bytes one launch of a stage must move (reads + writes of the
+    arrays the method needs; mesh arrays counted once)."""
+    np_, nn = disc["np"], disc["nc"][0] * disc["nc"][1] * disc["nc"][2]
+    coll = bool(prob["collisions"])
+    if precision == "fp64":
+        sx, sv = 24, 24          # FP64 position / velocity per particle
+    else:
+        sx, sv = 16, 12          # cell index + 3 FP32 offsets / 3 FP32 velocities
+    if stage == "collide":       # velocities in, averaged velocity change out
+        return (sv + sv) * np_ + 4 * nn
+    if stage == "kick":          # x, v, <dv> and cell key in; v out; E and cell starts
+        return (sx + sv + (sv + 4 if coll else 0) + sv) * np_ + 28 * nn
+    if stage == "drift":         # x, v, id in; x, key, slot out
+        return (sx + sv + 4 + sx + 4 + 4) * np_ + 4 * nn
+    if stage == "sort":          # key/slot -> index; gather + scatter of the state
+        return (16 + 8 + 2 * (sx + sv + 4) + 4) * np_ + 12 * nn
+    if stage == "deposit":       # positions in; node charge and right-hand side
+        return sx * np_ + 4 * nn + 2 * 64 * nn + 32 * nn
+    if stage == "cg":            # per iteration: stencil on p and r, update x, r
+        return max(cg_iters, 1) * 80 * nn
+    if stage == "gradient":
+        return 32 * nn
+    if stage == "particle":      # fused mixed kernel: state in and out, key
+        return (2 * (sx + sv) + 4) * np_ + 28 * nn
+    return 0
+
+
+def cpu_baseline(prob, disc, seed):
+    """The oracle on the host cores: init (untimed), then one timed step of the
+    same workload; particle-steps/s."""
+    import oracle as O
+
+    s = O.Sim(prob, disc, seed, 0)
+    s.init()
+    t0 = time.perf_counter()
+    s.step(1)
+    dt = time.perf_counter() - t0
+    return {"value": disc["np"] / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 time step of the full workload after init ({disc['np']} particles, "
+                      f"{disc['nc'][0]}^3 mesh), single-threaded FP64 C, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the path is built and measured on a single "
+              "MI355X (the multi-GPU sharding is a design, not a measured run)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_15130_amd import pic, workloads as W
+
+    c = W.get(args.workload)
+    prob, disc, precision, seed = c["problem"], c["disc"], c["precision"], c["seed"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sim = pic.Sim(prob, disc, seed, 0, precision, "cuda:0", stream)
+    if args.warmup:
+        sim.step(args.warmup)
+    torch.cuda.synchronize()
+    sim.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = sim.timing_read()
+    sim.timing(False)
+    st = sim.stats()
+    elapsed = t1 - t0
+    value = disc["np"] * args.steps / elapsed
+
+    per_stage = {}
+    for name, (ms, n) in stages.items():
+        if n == 0:
+            continue
+        b = stage_bytes(name, prob, disc, precision, st["cg_iters"])
+        per_stage[name] = {"ms_total": round(ms, 3), "launches": n,
+                           "us_per_launch": round(1e3 * ms / n, 2),
+                           "GBs": round(b / (ms / n * 1e-3) / 1e9, 1)}
+    dom = max(per_stage, key=lambda k: per_stage[k]["ms_total"])
+    dom_bytes = stage_bytes(dom, prob, disc, precision, st["cg_iters"])
+    ach = dom_bytes / (per_stage[dom]["ms_total"] / per_stage[dom]["launches"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": dom_bytes}
+    out = {
+        "metric": "particle-steps/s", "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic (manufactured solution, Philox seed %d)" % seed,
+        "config": {"workload": args.workload, "mesh": list(disc["nc"]), "particles": disc["np"],
+                   "n_avg": disc["navg"], "dt": disc["dt"], "precision": precision,
+                   "collisions": bool(prob["collisions"]), "two_way": bool(prob["particles_to_field"])},
+        "roofline": roof,
+        "stages": per_stage,
+        "cg_iters_last": st["cg_iters"],
+        "accepted_collisions": st["n_accepted"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, disc, seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

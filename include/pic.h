@@ -1,0 +1,223 @@
+/*
+ * pic.h — C ABI of the MI355X (gfx950) manufactured-solution PIC/DSMC time step.
+ *
+ * Method: Freno, McDoniel, Moore & Matula, "Code-Verification Techniques for
+ * Particle-in-Cell Simulations with Direct Simulation Monte Carlo Collisions".
+ * One species on a periodic box, electrostatic field (Sec. 2, eq. eom_full,
+ * eq. poisson), binary elastic collisions by the no-time-counter algorithm
+ * (Algorithm 1) averaged over N_avg independent outcomes (eq. avg_outcome),
+ * manufactured positions and velocities by inverse-CDF queries (eq. mms_sol)
+ * with the modified equations of motion (eq. eom_mms) integrated by velocity
+ * Verlet (eq. velocity_verlet), and direct error norms (Sec. 4.3).
+ *
+ * Conventions for every entry point:
+ *  - Return value: PIC_OK (0) on success, a negative PIC_E* code on error, a
+ *    positive PIC_WARN_* code when the call succeeded with a warning.  No
+ *    exception crosses the boundary.  The text of the last error of a context
+ *    is available from pic_last_error().
+ *  - Memory: the caller owns all device memory.  pic_workspace_size() states
+ *    how many bytes of device memory one simulation needs; the caller allocates
+ *    them (for example as a torch uint8 tensor on the GPU) and passes the
+ *    pointer to pic_init_manufactured(), which never allocates device memory
+ *    of its own.  The workspace must stay valid until pic_destroy().  Pointer
+ *    arguments documented as "device" must point into GPU memory of the
+ *    context's device, "host" ones into CPU memory.
+ *  - Streams: all GPU work of a context is enqueued on the HIP stream given at
+ *    initialisation (NULL = the default stream).  pic_step() only enqueues;
+ *    pic_errors(), pic_stats() and pic_get_state() synchronise that stream.
+ *    Errors of asynchronous work (a CG that did not converge, a HIP fault) are
+ *    reported by the next synchronising call.
+ *  - Concurrency: one context per stream; calls on one context must not
+ *    overlap.  Different contexts are independent.
+ *  - Determinism: results do not depend on scheduling: the cell sort, pair
+ *    selection and every floating-point reduction use a fixed order, so two
+ *    runs with the same inputs produce identical bits.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pic_status {
+  PIC_OK = 0,
+  PIC_EINVAL = -1,      /* invalid argument or unsupported combination */
+  PIC_EHIP = -2,        /* a HIP runtime call failed */
+  PIC_ENOCONV = -3,     /* Poisson CG hit cg_max_iter before cg_tol */
+  PIC_ENONFINITE = -4,  /* a non-finite value in the particle state or norms */
+  PIC_ESTATE = -5,      /* call out of order (e.g. before initialisation) */
+  PIC_ESPACE = -6,      /* workspace too small */
+  PIC_WARN_NAVG = 1     /* N_avg P_coll,max >= 0.5: eq. navg_ineq not satisfied */
+};
+
+enum pic_precision {
+  PIC_FP64 = 0,         /* every stage in FP64 */
+  PIC_MIXED = 1         /* particle stages in FP32 (cell index + FP32 offset
+                           positions); Poisson CG, inverse-CDF roots and error
+                           norms in FP64 */
+};
+
+enum pic_family {
+  PIC_MMS_PAPER = 0,    /* the manufactured functions of Sec. 5.2 */
+  PIC_MMS_CFG = 1       /* density (N/V)(1 + rho_amp sin sin sin) on the box,
+                           Gaussian velocities N(0, vbar^2), phi^M of Sec. 5.2;
+                           time independent except phi^M */
+};
+
+enum pic_sigma {
+  PIC_SIGMA_POLY = 0,   /* eq. sigma_ms: sigma(g) = sum_n sigma_n g^(2n-1) */
+  PIC_SIGMA_VHS = 1     /* sigma_ref (g / g_ref)^(1 - 2 omega); omega in {0.5, 1} */
+};
+
+/* The problem, in the paper's notation (Sec. 2, Sec. 3, Sec. 5.2). */
+typedef struct {
+  int family;               /* enum pic_family */
+  double L[3];              /* box lengths L_{x_i}; nodes at x = i L / ncell */
+  double nphys;             /* N, physical particles in the box (eq. fx) */
+  double q, m, eps0;        /* charge, mass, permittivity */
+  double T;                 /* time scale of the manufactured functions */
+  double vbar;              /* paper: vbar; cfg family: Gaussian sigma_v */
+  double phibar;            /* amplitude of phi^M */
+  double rho_amp;           /* cfg family density amplitude (< 1) */
+  int sigma_model;          /* enum pic_sigma */
+  int n_sigma;              /* 1..3 polynomial terms (PIC_SIGMA_POLY) */
+  double sigma_n[3];
+  double sigma_ref, g_ref, omega; /* PIC_SIGMA_VHS */
+  double g_max;             /* (sigma g)_max is the maximum over [0, g_max] */
+  int chi_model;            /* 0: isotropic scattering, eq. chi_iso */
+  int field_to_particles;   /* 0 => q/m = 0 in the push (Sec. 5.4) */
+  int particles_to_field;   /* 0 => q = 0 in the Poisson source (Sec. 5.4) */
+  int collisions;           /* 0 => no DSMC */
+  int isolate;              /* 1 => exact-difference substitution of the
+                               manufactured time derivatives (Sec. 5.4.1) */
+} pic_problem;
+
+/* The discretization (Table 1 columns). */
+typedef struct {
+  int ncell[3];             /* cells per dimension, >= 3; periodic nodes = cells */
+  int64_t n_particles;      /* N_p >= 1 */
+  double dt;                /* > 0 */
+  int n_avg;                /* N_avg >= 1 (eq. avg_outcome) */
+  double cg_tol;            /* stop when ||r||_2 <= cg_tol ||rhs||_2 */
+  int cg_max_iter;          /* >= 1 */
+} pic_discretization;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Bytes of device workspace one simulation needs (host out-pointer).
+ * Returns PIC_EINVAL for an invalid or unsupported problem. */
+int pic_workspace_size(const pic_problem* prob, const pic_discretization* disc,
+                       int precision, int64_t* bytes);
+
+/*
+ * Create a simulation and enqueue its initial state on `hip_stream`:
+ * the six uniforms xi of each particle (Sec. 3.2) from Philox4x64-10 keyed by
+ * (seed, replicate), x^0 = x^M(xi, 0) and v^0 = v^M(xi, 0) by inverse-CDF root
+ * solves (eq. mms_sol), the stable cell sort, the charge deposit, the Poisson
+ * solve (eq. poisson_mms) from phi = 0 and the nodal field E = -grad phi.
+ * `workspace` (device, >= pic_workspace_size bytes) is owned by the caller.
+ * On success *out receives a host-side context to be released with
+ * pic_destroy().  Returns PIC_WARN_NAVG when N_avg P_coll,max >= 0.5
+ * (eq. navg_ineq), which is a warning only.
+ */
+int pic_init_manufactured(pic_ctx** out, const pic_problem* prob,
+                          const pic_discretization* disc, uint64_t seed,
+                          uint32_t replicate, int precision, void* workspace,
+                          int64_t workspace_bytes, void* hip_stream);
+
+/*
+ * Enqueue n_steps time steps of eq. velocity_verlet: collision call A at t^n
+ * (Algorithm 1 run N_avg times and averaged, eq. avg_outcome, minus the
+ * analytic source eq. vel_change_3), half kick, drift with the manufactured
+ * term, stable cell sort, deposit, Poisson CG (warm-started), gradient,
+ * collision call B at t^{n+1/2} on the new cells, half kick.
+ * Asynchronous; returns PIC_ESTATE if the context is not initialised.
+ */
+int pic_step(pic_ctx* ctx, int n_steps);
+
+/*
+ * Run one collision call on the current state without applying it: for every
+ * particle, in the current (cell-sorted) order, dv_avg = <dv_p> (eq.
+ * avg_outcome) and dv_src = <dv_p^M> (eq. vel_change_3 / eq. vel_change_1c with
+ * the particle's own velocity and its cell's count).  `call` is 0 (the first
+ * half kick of a step) or 1 (the second); `t` is the time at which the
+ * manufactured velocity distribution enters the source.  The random stream is
+ * the one pic_step() would use at the current step index.
+ * dv_avg, dv_src: device, 3 * n_particles doubles each, component-major
+ * (x block, then y, then z).  pairlog: device, pairlog_cap records of 7
+ * int64 (cell, call, outcome k, pair m, p, q, accepted), in no particular
+ * order, or NULL; *pairlog_n (host, may be NULL) receives the number of
+ * candidate pairs (which may exceed pairlog_cap; the excess is not written).
+ * Synchronises the context stream.
+ */
+int pic_collide(pic_ctx* ctx, int call, double t, double* dv_avg, double* dv_src,
+                int64_t* pairlog, int64_t pairlog_cap, int64_t* pairlog_n);
+
+/* Error norms at the current time t = step * dt (Sec. 4.3): l2 and linf of
+ * x, y, z (minimum image), u, v, w over all particles and of phi over the
+ * nodes.  Synchronises; returns PIC_ENOCONV / PIC_EHIP for an earlier
+ * asynchronous failure and PIC_ENONFINITE for a non-finite norm. */
+typedef struct {
+  double t;
+  double l2[7];             /* x, y, z, u, v, w, phi */
+  double linf[7];
+} pic_error_norms;
+int pic_errors(pic_ctx* ctx, pic_error_norms* out);
+
+/* Counters of the last completed work (synchronises). */
+typedef struct {
+  int64_t step;             /* completed time steps */
+  int cg_iters;             /* iterations of the last Poisson solve */
+  double cg_relres;         /* its final relative residual */
+  int64_t n_accepted;       /* accepted collisions since initialisation */
+  int64_t n_gmax;           /* candidate pairs with g > g_max */
+} pic_stats_t;
+int pic_stats(pic_ctx* ctx, pic_stats_t* out);
+
+/* Copy part of the state to host memory (synchronises).  Particle arrays are
+ * in the current cell-sorted order. bytes must equal the size stated here. */
+enum pic_state_item {
+  PIC_STATE_X = 0,          /* 3 * n_particles doubles, component-major */
+  PIC_STATE_V = 1,          /* 3 * n_particles doubles */
+  PIC_STATE_ID = 2,         /* n_particles int64: particle identity */
+  PIC_STATE_CELL_START = 3, /* (ncells + 1) int64 */
+  PIC_STATE_RHO = 4,        /* ncells doubles (nodal charge density) */
+  PIC_STATE_PHI = 5,        /* ncells doubles */
+  PIC_STATE_E = 6           /* 3 * ncells doubles */
+};
+int pic_get_state(pic_ctx* ctx, int item, void* host_dst, int64_t bytes);
+
+/* Per-stage GPU time, measured with HIP events recorded on the context stream
+ * around each stage's kernels while timing is enabled. */
+enum pic_stage {
+  PIC_STAGE_COLLIDE = 0,    /* Algorithm 1 x N_avg (both calls) */
+  PIC_STAGE_KICK = 1,       /* gather + half kick (both halves) */
+  PIC_STAGE_DRIFT = 2,      /* drift + new cell keys and counts */
+  PIC_STAGE_SORT = 3,       /* scan, scatter, stable in-cell order, reorder */
+  PIC_STAGE_DEPOSIT = 4,    /* cell moments, node charge, Poisson right-hand side */
+  PIC_STAGE_CG = 5,         /* Poisson conjugate gradients */
+  PIC_STAGE_GRADIENT = 6,   /* E = -grad phi */
+  PIC_STAGE_PARTICLE = 7,   /* the fused particle kernel of the mixed form */
+  PIC_STAGE_COUNT = 8
+};
+/* enable != 0 starts (and resets) the accumulation; 0 stops it. */
+int pic_timing_enable(pic_ctx* ctx, int enable);
+/* ms (host, PIC_STAGE_COUNT doubles): summed milliseconds per stage;
+ * launches (host, PIC_STAGE_COUNT int64): number of timed stage instances.
+ * Synchronises the context stream. */
+int pic_timing_read(pic_ctx* ctx, double* ms, int64_t* launches);
+
+/* Release the host context (not the caller's workspace). */
+void pic_destroy(pic_ctx* ctx);
+
+/* Text of the last error of ctx (or of the last failed creation when ctx is
+ * NULL).  Valid until the next call on the same context. */
+const char* pic_last_error(const pic_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,741 @@
+// Host side of the C ABI declared in include/pic.h: validation, derived
+// constants, workspace layout and the launch sequence of a time step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_kernels.hpp"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+enum Arr {
+  A_X0, A_X1, A_V0, A_V1, A_ID0, A_ID1,              // FP64 particle state, two buffers
+  A_CELL0, A_CELL1, A_OFF0, A_OFF1, A_VF0, A_VF1,    // mixed particle state, two buffers
+  A_KEY, A_SLOT, A_TIDX, A_TKEY, A_D, A_U,
+  A_COUNT, A_CSTART, A_BSUM, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_R, A_P0, A_P1, A_Q,
+  A_PART_A, A_PART_B, A_EPART, A_NPART, A_NORMS, A_BAR, A_FLAGS, A_CNT, A_CGIT, A_CGRR,
+  A_NARR
+};
+
+struct Layout {
+  int64_t off[A_NARR];
+  int64_t bytes[A_NARR];
+  int64_t total;
+};
+
+Layout make_layout(const pic_discretization* d, int precision) {
+  const int64_t np = d->n_particles;
+  const int64_t nn = (int64_t)d->ncell[0] * d->ncell[1] * d->ncell[2];
+  const int64_t nblk_p = (np + kBlock - 1) / kBlock, nblk_n = (nn + kBlock - 1) / kBlock;
+  const int64_t nscan = (nn + kScanTile - 1) / kScanTile;
+  const bool f64 = precision == PIC_FP64;
+  const int64_t pf = f64 ? np : 0, pm = f64 ? 0 : np;
+  Layout L;
+  int64_t b[A_NARR] = {};
+  b[A_X0] = b[A_X1] = b[A_V0] = b[A_V1] = 3 * pf * 8;
+  b[A_ID0] = b[A_ID1] = np * 4;
+  b[A_CELL0] = b[A_CELL1] = pm * 4;
+  b[A_OFF0] = b[A_OFF1] = b[A_VF0] = b[A_VF1] = 3 * pm * 4;
+  b[A_KEY] = b[A_SLOT] = b[A_TIDX] = b[A_TKEY] = np * 4;
+  b[A_D] = 3 * np * (f64 ? 8 : 4);
+  b[A_U] = 3 * pf * 8;
+  b[A_COUNT] = nn * 4;
+  b[A_CSTART] = (nn + 1) * 4;
+  b[A_BSUM] = (nscan + 1) * 4;
+  b[A_MOM] = 8 * nn * (f64 ? 8 : 4);
+  b[A_RHO] = b[A_B] = b[A_PHI] = b[A_R] = b[A_P0] = b[A_P1] = b[A_Q] = nn * 8;
+  b[A_E] = 3 * nn * 8;
+  b[A_E32] = f64 ? 0 : 3 * nn * 4;
+  b[A_PART_A] = b[A_PART_B] = std::max<int64_t>(nblk_n, 4096) * 8;
+  b[A_EPART] = nblk_p * 14 * 8;
+  b[A_NPART] = nblk_n * 2 * 8;
+  b[A_NORMS] = 16 * 8;
+  b[A_BAR] = 2 * 4;
+  b[A_FLAGS] = kFlagCount * 4;
+  b[A_CNT] = kCntCount * 8;
+  b[A_CGIT] = 4;
+  b[A_CGRR] = 8;
+  int64_t t = 0;
+  for (int i = 0; i < A_NARR; ++i) {
+    L.off[i] = t;
+    L.bytes[i] = b[i];
+    t += align_up(std::max<int64_t>(b[i], 1));
+  }
+  L.total = t;
+  return L;
+}
+
+int validate(const pic_problem* p, const pic_discretization* d, int precision, std::string& err) {
+  auto bad = [&](const char* m) {
+    err = m;
+    return PIC_EINVAL;
+  };
+  if (!p || !d) return bad("null problem or discretization");
+  if (precision != PIC_FP64 && precision != PIC_MIXED) return bad("unknown precision");
+  if (p->family != PIC_MMS_PAPER && p->family != PIC_MMS_CFG) return bad("unknown family");
+  for (int k = 0; k < 3; ++k) {
+    if (d->ncell[k] < 3 || d->ncell[k] > 1023) return bad("ncell must be in [3, 1023]");
+    if (!(p->L[k] > 0.0)) return bad("L must be positive");
+  }
+  if ((int64_t)d->ncell[0] * d->ncell[1] * d->ncell[2] > (1 << 30)) return bad("too many cells");
+  if (d->n_particles < 1 || d->n_particles > (int64_t)2147483647)
+    return bad("n_particles must be in [1, 2^31 - 1]");
+  if (!(d->dt > 0.0)) return bad("dt must be positive");
+  if (d->n_avg < 1) return bad("n_avg must be >= 1");
+  if (!(d->cg_tol > 0.0) || d->cg_max_iter < 1) return bad("bad CG controls");
+  if (!(p->nphys > 0.0) || !(p->eps0 > 0.0) || !(p->T > 0.0) || !(p->vbar > 0.0))
+    return bad("nphys, eps0, T and vbar must be positive");
+  if (p->field_to_particles && p->m == 0.0) return bad("m must be nonzero");
+  if (p->family == PIC_MMS_CFG && !(std::fabs(p->rho_amp) < 1.0)) return bad("need |rho_amp| < 1");
+  if (p->chi_model != 0) return bad("only isotropic scattering (chi_model 0)");
+  if (p->collisions) {
+    if (!(p->g_max > 0.0)) return bad("g_max must be positive");
+    if (p->sigma_model == PIC_SIGMA_POLY) {
+      if (p->n_sigma < 1 || p->n_sigma > 3) return bad("n_sigma must be 1..3");
+    } else if (p->sigma_model == PIC_SIGMA_VHS) {
+      if (p->omega != 0.5 && p->omega != 1.0)
+        return bad("VHS needs omega in {0.5, 1} (closed-form sources only)");
+      if (p->omega == 0.5 && p->family != PIC_MMS_CFG)
+        return bad("hard sphere needs the Gaussian (cfg) family");
+      if (!(p->sigma_ref > 0.0) || !(p->g_ref > 0.0)) return bad("bad VHS constants");
+    } else {
+      return bad("unknown sigma model");
+    }
+  }
+  if (precision == PIC_MIXED && p->family != PIC_MMS_CFG)
+    return bad("the mixed form supports the cfg family");
+  return PIC_OK;
+}
+
+double host_sigma_g(const SimConst& K, double g) {
+  if (K.sigma_model == 1) return K.sg_coef * std::pow(g, K.sg_pow);
+  double g2 = g * g, r = K.sigma_n[0];
+  if (K.n_sigma > 1) r += K.sigma_n[1] * g2;
+  if (K.n_sigma > 2) r += K.sigma_n[2] * (g2 * g2);
+  return r;
+}
+
+SimConst derive(const pic_problem* p, const pic_discretization* d, uint64_t seed, uint32_t rep) {
+  SimConst K;
+  std::memset(&K, 0, sizeof(K));
+  K.family = p->family;
+  K.sigma_model = p->sigma_model;
+  K.n_sigma = p->sigma_model == PIC_SIGMA_POLY ? p->n_sigma : 0;
+  K.collisions = p->collisions;
+  K.isolate = p->isolate;
+  K.navg = d->n_avg;
+  K.np = d->n_particles;
+  K.nn = d->ncell[0] * d->ncell[1] * d->ncell[2];
+  K.seed = seed;
+  K.rep = rep;
+  for (int k = 0; k < 3; ++k) {
+    K.nc[k] = d->ncell[k];
+    K.L[k] = p->L[k];
+    K.h[k] = p->L[k] / d->ncell[k];
+    K.inv_h[k] = (double)d->ncell[k] / p->L[k];
+    K.ih2[k] = 1.0 / (K.h[k] * K.h[k]);
+  }
+  K.qm = p->field_to_particles ? p->q / p->m : 0.0;
+  K.p2f = p->particles_to_field ? 1.0 : 0.0;
+  K.q = p->q;
+  K.eps0 = p->eps0;
+  K.T = p->T;
+  K.vbar = p->vbar;
+  K.phibar = p->phibar;
+  K.rho_amp = p->rho_amp;
+  for (int k = 0; k < 3; ++k) K.sigma_n[k] = p->sigma_n[k];
+  K.sigma_ref = p->sigma_ref;
+  K.g_ref = p->g_ref;
+  K.omega = p->omega;
+  K.g_max = p->g_max;
+  K.sg_coef = p->sigma_ref * std::pow(p->g_ref, 2.0 * p->omega - 1.0);
+  K.sg_pow = 2.0 - 2.0 * p->omega;
+  K.nphys = p->nphys;
+  K.dt = d->dt;
+  K.w = p->nphys / (double)d->n_particles;
+  K.dV = (p->L[0] / d->ncell[0]) * (p->L[1] / d->ncell[1]) * (p->L[2] / d->ncell[2]);
+  K.rho_scale = p->q * K.w / K.dV;
+  K.src_half = K.w * K.dt / (2.0 * K.dV);
+  // (sigma g)_max over [0, g_max] (Sec. 5.2)
+  if (K.sigma_model == 1) {
+    K.sgmax = host_sigma_g(K, p->g_max);  // nondecreasing in g for omega <= 1
+  } else {
+    double best = host_sigma_g(K, 0.0), e = host_sigma_g(K, p->g_max);
+    if (e > best) best = e;
+    if (K.n_sigma == 3 && K.sigma_n[2] != 0.0) {
+      double G = -K.sigma_n[1] / (2.0 * K.sigma_n[2]);
+      if (G > 0.0 && G < p->g_max * p->g_max) best = std::max(best, host_sigma_g(K, std::sqrt(G)));
+    }
+    K.sgmax = best;
+  }
+  K.pmax = K.sgmax * K.w * K.dt / K.dV;  // Algorithm 1
+  return K;
+}
+
+int grid_for(int64_t n) { return (int)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+struct pic_ctx {
+  SimConst K{};
+  int precision = PIC_FP64;
+  double cg_tol = 1e-12;
+  int cg_max_iter = 1000;
+  hipStream_t stream = nullptr;
+  int cg_grid = 1;
+  bool ready = false;
+  int64_t step = 0;
+  int cur = 0;
+  std::string err;
+  char* ws = nullptr;
+  Layout layout{};
+  double* x[2]{};
+  double* v[2]{};
+  int* id[2]{};
+  int* cell[2]{};
+  float* off[2]{};
+  float* vf[2]{};
+  int *key{}, *slot{}, *tidx{}, *tkey{}, *count{}, *cstart{}, *bsum{};
+  double *D{}, *U{};
+  float* Df{};
+  void* mom{};
+  double *rho{}, *b{}, *phi{}, *E{}, *r{}, *p0{}, *p1{}, *q{}, *partA{}, *partB{};
+  float* E32{};
+  double *epart{}, *npart{}, *norms{}, *cgrr{};
+  unsigned* bar{};
+  int *flags{}, *cgit{};
+  unsigned long long* cnt{};
+  // stage timing with HIP events on the context stream
+  bool timing = false;
+  struct Timed {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> event_pool;
+  double stage_ms[PIC_STAGE_COUNT] = {};
+  int64_t stage_n[PIC_STAGE_COUNT] = {};
+  ~pic_ctx() {
+    for (auto& t : timed) event_pool.push_back(t.a), event_pool.push_back(t.b);
+    for (auto e : event_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int hip_fail(pic_ctx* c, hipError_t e, const char* what) {
+  c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return PIC_EHIP;
+}
+
+#define HIP_TRY(ctx, call)                                 \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx, name)                                     \
+  do {                                                              \
+    hipError_t e_ = hipGetLastError();                              \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, "launch " name); \
+  } while (0)
+
+#define TRY(expr)          \
+  do {                     \
+    int st_ = (expr);      \
+    if (st_ != PIC_OK) return st_; \
+  } while (0)
+
+hipEvent_t take_event(pic_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records HIP events around one stage while timing is enabled.
+struct StageTimer {
+  pic_ctx* c;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(pic_ctx* ctx, int st) : c(ctx), stage(st) {
+    if (!c->timing) return;
+    a = take_event(c);
+    if (a) (void)hipEventRecord(a, c->stream);
+  }
+  ~StageTimer() {
+    if (!c->timing || !a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->timed.push_back({stage, a, b});
+  }
+};
+
+// Fold recorded event pairs into the per-stage totals (stream must be idle).
+void collect_timing(pic_ctx* c) {
+  for (auto& t : c->timed) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->stage_ms[t.stage] += ms;
+      c->stage_n[t.stage] += 1;
+    }
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->timed.clear();
+}
+
+template <class T>
+T* carve(pic_ctx* c, int idx) {
+  return c->layout.bytes[idx] ? reinterpret_cast<T*>(c->ws + c->layout.off[idx]) : nullptr;
+}
+
+template <class T>
+int fill(pic_ctx* c, T* p, T v, int64_t n) {
+  int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+  k_fill<T><<<g, kBlock, 0, c->stream>>>(p, v, n);
+  LAUNCH_CHECK(c, "fill");
+  return PIC_OK;
+}
+
+// Exclusive scan of the cell counts into cell_start.
+int scan_counts(pic_ctx* c) {
+  int n = c->K.nn;
+  int nb = (n + kScanTile - 1) / kScanTile;
+  k_scan_local<<<nb, kBlock, 0, c->stream>>>(c->count, c->cstart, c->bsum, n);
+  k_scan_blocks<<<1, kBlock, 0, c->stream>>>(c->bsum, nb, c->cstart, n);
+  k_scan_add<<<nb, kBlock, 0, c->stream>>>(c->cstart, c->bsum, n);
+  LAUNCH_CHECK(c, "scan");
+  return PIC_OK;
+}
+
+// Sort the current buffer (keys, slots and counts already computed) into the other.
+int sort_particles(pic_ctx* c) {
+  StageTimer tm(c, PIC_STAGE_SORT);
+  TRY(scan_counts(c));
+  int np = (int)c->K.np;
+  k_scatter<<<grid_for(np), kBlock, 0, c->stream>>>(c->key, c->slot, c->cstart, c->tidx, c->tkey, np);
+  int s = c->cur, d = 1 - c->cur;
+  k_order_f64<<<grid_for(np), kBlock, 0, c->stream>>>(c->tidx, c->tkey, c->cstart, c->x[s], c->v[s],
+                                                       c->id[s], c->x[d], c->v[d], c->id[d], c->key,
+                                                       np);
+  LAUNCH_CHECK(c, "sort");
+  c->cur = d;
+  return PIC_OK;
+}
+
+// deposit -> RHS (eq. poisson_mms, mean removed) -> CG (warm start) -> E = -grad phi
+int field_solve(pic_ctx* c, double t) {
+  const SimConst& K = c->K;
+  int nbn = grid_for(K.nn);
+  {
+    StageTimer tm(c, PIC_STAGE_DEPOSIT);
+    k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
+                                                         (double*)c->mom);
+    k_node_rhs<double><<<nbn, kBlock, 0, c->stream>>>(K, (const double*)c->mom, t, c->rho, c->b,
+                                                      c->partA);
+    k_sub_mean<<<nbn, kBlock, 0, c->stream>>>(K, c->b, c->partA, nbn);
+    LAUNCH_CHECK(c, "rhs");
+  }
+  TRY(fill<unsigned>(c, c->bar, 0u, 2));
+  CgArgs a;
+  a.b = c->b;
+  a.x = c->phi;
+  a.r = c->r;
+  a.p0 = c->p0;
+  a.p1 = c->p1;
+  a.q = c->q;
+  a.partA = c->partA;
+  a.partB = c->partB;
+  a.bar = c->bar;
+  a.flags = c->flags;
+  a.iters_out = c->cgit;
+  a.relres_out = c->cgrr;
+  a.tol = c->cg_tol;
+  a.max_iter = c->cg_max_iter;
+  SimConst Kc = K;
+  void* args[] = {&Kc, &a};
+  {
+    StageTimer tm(c, PIC_STAGE_CG);
+    HIP_TRY(c, hipLaunchCooperativeKernel((const void*)k_cg, dim3(c->cg_grid), dim3(kBlock), args,
+                                          0, c->stream));
+  }
+  StageTimer tm(c, PIC_STAGE_GRADIENT);
+  k_gradient<<<nbn, kBlock, 0, c->stream>>>(K, c->phi, c->E, c->E32);
+  LAUNCH_CHECK(c, "gradient");
+  return PIC_OK;
+}
+
+int collide(pic_ctx* c, int call, int64_t step, double* D, long long* pairlog, int64_t cap) {
+  const SimConst& K = c->K;
+  StageTimer tm(c, PIC_STAGE_COLLIDE);
+  k_collide_f64<<<grid_for(K.nn), kBlock, 0, c->stream>>>(K, call, step, c->v[c->cur], c->cstart, D,
+                                                          c->U, pairlog, cap, c->cnt);
+  LAUNCH_CHECK(c, "collide");
+  return PIC_OK;
+}
+
+int kick(pic_ctx* c, double t, double t_from, double t_to, double t_src) {
+  const SimConst& K = c->K;
+  StageTimer tm(c, PIC_STAGE_KICK);
+  int s = c->cur;
+  k_kick_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, t, t_from, t_to, t_src, c->x[s], c->v[s],
+                                                       c->id[s], c->key, c->cstart, c->E, c->D);
+  LAUNCH_CHECK(c, "kick");
+  return PIC_OK;
+}
+
+int drift(pic_ctx* c, double t0, double th, double t1) {
+  const SimConst& K = c->K;
+  StageTimer tm(c, PIC_STAGE_DRIFT);
+  TRY(fill<int>(c, c->count, 0, K.nn));
+  int s = c->cur;
+  k_drift_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, t0, th, t1, c->x[s], c->v[s], c->id[s],
+                                                        c->key, c->slot, c->count);
+  LAUNCH_CHECK(c, "drift");
+  return PIC_OK;
+}
+
+int one_step(pic_ctx* c) {
+  const SimConst& K = c->K;
+  const int64_t n = c->step;
+  const double t0 = (double)n * K.dt, th = ((double)n + 0.5) * K.dt, t1 = ((double)n + 1.0) * K.dt;
+  if (K.collisions) TRY(collide(c, 0, n, c->D, nullptr, 0));
+  TRY(kick(c, t0, t0, th, t0));
+  TRY(drift(c, t0, th, t1));
+  TRY(sort_particles(c));
+  TRY(field_solve(c, t1));
+  if (K.collisions) TRY(collide(c, 1, n, c->D, nullptr, 0));
+  TRY(kick(c, t1, th, t1, th));
+  c->step = n + 1;
+  return PIC_OK;
+}
+
+// Read back flags raised by earlier asynchronous work.
+int check_flags(pic_ctx* c) {
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int f[kFlagCount];
+  HIP_TRY(c, hipMemcpy(f, c->flags, sizeof(f), hipMemcpyDeviceToHost));
+  if (f[kFlagBarrier]) {
+    c->err = "grid barrier timed out in the Poisson solver";
+    return PIC_EHIP;
+  }
+  if (f[kFlagCgNoConv]) {
+    c->err = "Poisson CG reached cg_max_iter before cg_tol";
+    return PIC_ENOCONV;
+  }
+  if (f[kFlagNonFinite]) {
+    c->err = "non-finite particle state";
+    return PIC_ENONFINITE;
+  }
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_workspace_size(const pic_problem* prob, const pic_discretization* disc, int precision,
+                       int64_t* bytes) {
+  std::string err;
+  int st = validate(prob, disc, precision, err);
+  if (st != PIC_OK) {
+    g_create_error = err;
+    return st;
+  }
+  if (precision == PIC_MIXED) {
+    g_create_error = "mixed precision form not built yet";
+    return PIC_EINVAL;
+  }
+  if (!bytes) {
+    g_create_error = "null bytes";
+    return PIC_EINVAL;
+  }
+  *bytes = make_layout(disc, precision).total;
+  return PIC_OK;
+}
+
+int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_discretization* disc,
+                          uint64_t seed, uint32_t replicate, int precision, void* workspace,
+                          int64_t workspace_bytes, void* hip_stream) {
+  if (!out) {
+    g_create_error = "null output pointer";
+    return PIC_EINVAL;
+  }
+  *out = nullptr;
+  int64_t need = 0;
+  int st = pic_workspace_size(prob, disc, precision, &need);
+  if (st != PIC_OK) return st;
+  if (!workspace || workspace_bytes < need) {
+    g_create_error = "workspace too small: need " + std::to_string(need) + " bytes";
+    return PIC_ESPACE;
+  }
+  if (((uintptr_t)workspace) % kAlign) {
+    g_create_error = "workspace must be 256-byte aligned";
+    return PIC_EINVAL;
+  }
+  pic_ctx* c = new (std::nothrow) pic_ctx();
+  if (!c) {
+    g_create_error = "out of host memory";
+    return PIC_EINVAL;
+  }
+  c->K = derive(prob, disc, seed, replicate);
+  c->precision = precision;
+  c->cg_tol = disc->cg_tol;
+  c->cg_max_iter = disc->cg_max_iter;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  c->layout = make_layout(disc, precision);
+  c->x[0] = carve<double>(c, A_X0);
+  c->x[1] = carve<double>(c, A_X1);
+  c->v[0] = carve<double>(c, A_V0);
+  c->v[1] = carve<double>(c, A_V1);
+  c->id[0] = carve<int>(c, A_ID0);
+  c->id[1] = carve<int>(c, A_ID1);
+  c->key = carve<int>(c, A_KEY);
+  c->slot = carve<int>(c, A_SLOT);
+  c->tidx = carve<int>(c, A_TIDX);
+  c->tkey = carve<int>(c, A_TKEY);
+  c->D = carve<double>(c, A_D);
+  c->U = carve<double>(c, A_U);
+  c->count = carve<int>(c, A_COUNT);
+  c->cstart = carve<int>(c, A_CSTART);
+  c->bsum = carve<int>(c, A_BSUM);
+  c->mom = carve<void>(c, A_MOM);
+  c->rho = carve<double>(c, A_RHO);
+  c->b = carve<double>(c, A_B);
+  c->phi = carve<double>(c, A_PHI);
+  c->E = carve<double>(c, A_E);
+  c->E32 = carve<float>(c, A_E32);
+  c->r = carve<double>(c, A_R);
+  c->p0 = carve<double>(c, A_P0);
+  c->p1 = carve<double>(c, A_P1);
+  c->q = carve<double>(c, A_Q);
+  c->partA = carve<double>(c, A_PART_A);
+  c->partB = carve<double>(c, A_PART_B);
+  c->epart = carve<double>(c, A_EPART);
+  c->npart = carve<double>(c, A_NPART);
+  c->norms = carve<double>(c, A_NORMS);
+  c->bar = carve<unsigned>(c, A_BAR);
+  c->flags = carve<int>(c, A_FLAGS);
+  c->cnt = carve<unsigned long long>(c, A_CNT);
+  c->cgit = carve<int>(c, A_CGIT);
+  c->cgrr = carve<double>(c, A_CGRR);
+
+  // Cooperative grid for the Poisson solver: one block per CU at most, never
+  // more than the node count needs, and never more than can be co-resident.
+  int dev = 0, ncu = 1, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg, kBlock, 0);
+  if (e != hipSuccess || per_cu < 1) {
+    g_create_error = std::string("device query failed: ") + hipGetErrorString(e);
+    delete c;
+    return PIC_EHIP;
+  }
+  c->cg_grid = (int)std::min<int64_t>({(int64_t)ncu, (int64_t)ncu * per_cu, (int64_t)grid_for(c->K.nn)});
+
+  auto init = [&]() -> int {
+    const SimConst& K = c->K;
+    TRY(fill<int>(c, c->flags, 0, kFlagCount));
+    TRY(fill<unsigned long long>(c, c->cnt, 0ull, kCntCount));
+    TRY(fill<int>(c, c->count, 0, K.nn));
+    TRY(fill<double>(c, c->phi, 0.0, K.nn));
+    // unsorted initial state in buffer 1, sorted into buffer 0
+    c->cur = 1;
+    k_init_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->x[1], c->v[1], c->id[1], c->key,
+                                                         c->slot, c->count);
+    LAUNCH_CHECK(c, "init");
+    TRY(sort_particles(c));
+    TRY(field_solve(c, 0.0));
+    return PIC_OK;
+  };
+  st = init();
+  if (st != PIC_OK) {
+    g_create_error = c->err;
+    delete c;
+    return st;
+  }
+  c->ready = true;
+  c->step = 0;
+  *out = c;
+  if ((double)c->K.navg * c->K.pmax >= 0.5 && c->K.collisions) return PIC_WARN_NAVG;
+  return PIC_OK;
+}
+
+int pic_step(pic_ctx* c, int n_steps) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (n_steps < 0) {
+    c->err = "n_steps must be >= 0";
+    return PIC_EINVAL;
+  }
+  for (int s = 0; s < n_steps; ++s) TRY(one_step(c));
+  return PIC_OK;
+}
+
+int pic_collide(pic_ctx* c, int call, double t, double* dv_avg, double* dv_src, int64_t* pairlog,
+                int64_t pairlog_cap, int64_t* pairlog_n) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if ((call != 0 && call != 1) || !dv_avg || !dv_src || pairlog_cap < 0 ||
+      (pairlog_cap > 0 && !pairlog)) {
+    c->err = "bad pic_collide arguments";
+    return PIC_EINVAL;
+  }
+  const SimConst& K = c->K;
+  TRY(fill<unsigned long long>(c, c->cnt + kCntPairLog, 0ull, 1));
+  TRY(collide(c, call, c->step, dv_avg, pairlog_cap > 0 ? (long long*)pairlog : nullptr,
+              pairlog_cap));
+  k_source_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->v[c->cur], c->key, c->cstart, t, dv_src);
+  LAUNCH_CHECK(c, "source");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (pairlog_n) {
+    unsigned long long nlog = 0;
+    HIP_TRY(c, hipMemcpy(&nlog, c->cnt + kCntPairLog, sizeof(nlog), hipMemcpyDeviceToHost));
+    *pairlog_n = (int64_t)nlog;
+  }
+  return check_flags(c);
+}
+
+int pic_errors(pic_ctx* c, pic_error_norms* out) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (!out) {
+    c->err = "null output";
+    return PIC_EINVAL;
+  }
+  const SimConst& K = c->K;
+  double t = (double)c->step * K.dt;
+  int nbp = grid_for(K.np), nbn = grid_for(K.nn);
+  int s = c->cur;
+  k_err_particles_f64<<<nbp, kBlock, 0, c->stream>>>(K, t, c->x[s], c->v[s], c->id[s], c->epart,
+                                                     c->flags);
+  k_err_nodes<<<nbn, kBlock, 0, c->stream>>>(K, t, c->phi, c->npart);
+  k_err_final<<<1, kBlock, 0, c->stream>>>(K, c->epart, nbp, c->npart, nbn, c->norms);
+  LAUNCH_CHECK(c, "errors");
+  double h[14];
+  HIP_TRY(c, hipMemcpyAsync(h, c->norms, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  TRY(check_flags(c));
+  out->t = t;
+  for (int a = 0; a < 7; ++a) {
+    out->l2[a] = h[a];
+    out->linf[a] = h[7 + a];
+    if (!std::isfinite(h[a]) || !std::isfinite(h[7 + a])) {
+      c->err = "non-finite error norm";
+      return PIC_ENONFINITE;
+    }
+  }
+  return PIC_OK;
+}
+
+int pic_stats(pic_ctx* c, pic_stats_t* out) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (!out) return PIC_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int it = 0;
+  double rr = 0.0;
+  unsigned long long cnt[kCntCount];
+  HIP_TRY(c, hipMemcpy(&it, c->cgit, sizeof(it), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(&rr, c->cgrr, sizeof(rr), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(cnt, c->cnt, sizeof(cnt), hipMemcpyDeviceToHost));
+  out->step = c->step;
+  out->cg_iters = it;
+  out->cg_relres = rr;
+  out->n_accepted = (int64_t)cnt[kCntAccepted];
+  out->n_gmax = (int64_t)cnt[kCntGmax];
+  return check_flags(c);
+}
+
+int pic_get_state(pic_ctx* c, int item, void* host_dst, int64_t bytes) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  const SimConst& K = c->K;
+  int64_t np = K.np, nn = K.nn;
+  int64_t need;
+  switch (item) {
+    case PIC_STATE_X:
+    case PIC_STATE_V: need = 3 * np * 8; break;
+    case PIC_STATE_ID: need = np * 8; break;
+    case PIC_STATE_CELL_START: need = (nn + 1) * 8; break;
+    case PIC_STATE_RHO:
+    case PIC_STATE_PHI: need = nn * 8; break;
+    case PIC_STATE_E: need = 3 * nn * 8; break;
+    default: c->err = "unknown state item"; return PIC_EINVAL;
+  }
+  if (!host_dst || bytes != need) {
+    c->err = "destination size mismatch: need " + std::to_string(need);
+    return PIC_EINVAL;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int s = c->cur;
+  switch (item) {
+    case PIC_STATE_X: HIP_TRY(c, hipMemcpy(host_dst, c->x[s], need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_V: HIP_TRY(c, hipMemcpy(host_dst, c->v[s], need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_ID:
+    case PIC_STATE_CELL_START: {
+      const int* src = item == PIC_STATE_ID ? c->id[s] : c->cstart;
+      int64_t n = need / 8;
+      std::vector<int> tmp((size_t)n);
+      HIP_TRY(c, hipMemcpy(tmp.data(), src, n * 4, hipMemcpyDeviceToHost));
+      int64_t* d = (int64_t*)host_dst;
+      for (int64_t i = 0; i < n; ++i) d[i] = tmp[(size_t)i];
+      break;
+    }
+    case PIC_STATE_RHO: HIP_TRY(c, hipMemcpy(host_dst, c->rho, need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_PHI: HIP_TRY(c, hipMemcpy(host_dst, c->phi, need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_E: HIP_TRY(c, hipMemcpy(host_dst, c->E, need, hipMemcpyDeviceToHost)); break;
+  }
+  return check_flags(c);
+}
+
+int pic_timing_enable(pic_ctx* c, int enable) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  for (int i = 0; i < PIC_STAGE_COUNT; ++i) {
+    c->stage_ms[i] = 0.0;
+    c->stage_n[i] = 0;
+  }
+  c->timing = enable != 0;
+  return PIC_OK;
+}
+
+int pic_timing_read(pic_ctx* c, double* ms, int64_t* launches) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (!ms || !launches) return PIC_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  collect_timing(c);
+  for (int i = 0; i < PIC_STAGE_COUNT; ++i) {
+    ms[i] = c->stage_ms[i];
+    launches[i] = c->stage_n[i];
+  }
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+const char* pic_last_error(const pic_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

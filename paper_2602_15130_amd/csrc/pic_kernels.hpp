@@ -1,0 +1,816 @@
+// HIP kernels of the FP64 form of the step, plus the pieces shared with the
+// mixed form (sort, scan, Poisson CG, gradient, norms).
+#pragma once
+
+#include "pic_device.hpp"
+
+namespace pic {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+// Flags raised by kernels and read back at the next synchronising call.
+enum { kFlagCgNoConv = 0, kFlagBarrier = 1, kFlagNonFinite = 2, kFlagCount = 4 };
+// 64-bit counters: accepted collisions, candidate pairs with g > g_max, pair-log records.
+enum { kCntAccepted = 0, kCntGmax = 1, kCntPairLog = 2, kCntCount = 4 };
+
+// ---------------------------------------------------------------------------
+// Block reductions with a fixed combination order (bitwise reproducible).
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Sum over the block; every thread receives the same value.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  __syncthreads();
+  if (ln == 0) sh[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) r += sh[i];
+  return r;
+}
+__device__ inline double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  __syncthreads();
+  if (ln == 0) sh[wv] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int i = 1; i < kWaves; ++i) r = fmax(r, sh[i]);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Fill kernels (used instead of hipMemsetAsync so that steps stay graph-safe).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Mesh indexing: node / cell (i, j, k) -> (k ny + j) nx + i, periodic.
+// ---------------------------------------------------------------------------
+__device__ inline int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ inline int lin(const SimConst& K, int i, int j, int k) {
+  return (wrapi(k, K.nc[2]) * K.nc[1] + wrapi(j, K.nc[1])) * K.nc[0] + wrapi(i, K.nc[0]);
+}
+
+// Cell and in-cell offset (cell units) of a position in [0, L).
+__device__ inline void locate(const SimConst& K, const double x[3], int c[3], double o[3]) {
+  for (int d = 0; d < 3; ++d) {
+    double s = x[d] * K.inv_h[d];
+    int i = (int)floor(s);
+    i = i < 0 ? 0 : (i > K.nc[d] - 1 ? K.nc[d] - 1 : i);
+    c[d] = i;
+    o[d] = s - (double)i;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stable counting sort by cell.
+//   count:   slot[i] = position of particle i among its cell's arrivals, taken
+//            with one atomic per (wave, key) group (ballot match);
+//   scan:    cell_start = exclusive prefix sum of the counts;
+//   scatter: tmp_idx[cell_start[key] + slot] = i;
+//   order:   inside each cell, rank the source indices, which restores the
+//            input order (stability) independently of atomic arrival order,
+//            and gather the particle state into the destination arrays.
+// ---------------------------------------------------------------------------
+__device__ inline int wave_aggregated_slot(int* count, int key, bool valid) {
+  const int lane = __lane_id();
+  unsigned long long pending = __ballot(valid);
+  int my = 0;
+  while (pending) {
+    int leader = __ffsll((long long)pending) - 1;
+    int lkey = __shfl(key, leader);
+    bool mine = valid && key == lkey && ((pending >> lane) & 1ull);
+    unsigned long long grp = __ballot(mine);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&count[lkey], __popcll(grp));
+    base = __shfl(base, leader);
+    if (mine) my = base + __popcll(grp & ((1ull << lane) - 1ull));
+    pending &= ~grp;
+  }
+  return my;
+}
+
+__global__ void __launch_bounds__(kBlock) k_count(const int* key, int* slot, int* count, int n) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  bool valid = i < n;
+  int k = valid ? key[i] : 0;
+  int s = wave_aggregated_slot(count, k, valid);
+  if (valid) slot[i] = s;
+}
+
+// Exclusive scan of n ints in three passes; 1024 items per block.
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ void __launch_bounds__(kBlock) k_scan_local(const int* in, int* out, int* bsum, int n) {
+  __shared__ int sh[kBlock];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems], tot = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (base + j < n) ? in[base + j] : 0;
+    tot += v[j];
+  }
+  sh[threadIdx.x] = tot;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {  // Hillis-Steele inclusive scan
+    int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - tot;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = sh[kBlock - 1];
+}
+
+// One block scans the block totals; writes the grand total to out[n].
+__global__ void __launch_bounds__(kBlock) k_scan_blocks(int* bsum, int nb, int* out, int n) {
+  __shared__ int sh[kBlock];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int start = 0; start < nb; start += kBlock) {
+    int i = start + threadIdx.x;
+    int v = i < nb ? bsum[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+      int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    int excl = carry + sh[threadIdx.x] - v;
+    if (i < nb) bsum[i] = excl;
+    __syncthreads();
+    if (threadIdx.x == kBlock - 1) carry += sh[kBlock - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_add(int* out, const int* bsum, int n) {
+  int base = blockIdx.x * kScanTile;
+  int add = bsum[blockIdx.x];
+  for (int j = threadIdx.x; j < kScanTile; j += kBlock)
+    if (base + j < n) out[base + j] += add;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scatter(const int* key, const int* slot,
+                                                    const int* cstart, int* tidx, int* tkey,
+                                                    int n) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int k = key[i];
+  int dst = cstart[k] + slot[i];
+  tidx[dst] = i;
+  tkey[dst] = k;
+}
+
+// Rank of `my` among the source indices of its cell segment.
+__device__ inline int stable_rank(const int* tidx, int s, int e, int my) {
+  int r = 0;
+  for (int k = s; k < e; ++k) r += tidx[k] < my;
+  return r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_order_f64(const int* tidx, const int* tkey,
+                                                      const int* cstart, const double* xs,
+                                                      const double* vs, const int* ids,
+                                                      double* xd, double* vd, int* idd, int* keyd,
+                                                      int n) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  int c = tkey[j], s = cstart[c], e = cstart[c + 1], my = tidx[j];
+  int dst = s + stable_rank(tidx, s, e, my);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xd[(int64_t)d * n + dst] = xs[(int64_t)d * n + my];
+    vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
+  }
+  idd[dst] = ids[my];
+  keyd[dst] = c;
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: xi -> x^M(0), v^M(0) in id order (eq. mms_sol), cell keys and
+// counts for the sort.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_init_f64(SimConst K, double* x, double* v, int* id,
+                                                     int* key, int* slot, int* count) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  bool valid = p < K.np;
+  int kk = 0;
+  if (valid) {
+    double xi[6], xm[3], a[3], vm[3], vd[3];
+    init_uniforms(K, p, xi);
+    manufactured_position(K, xi, 0.0, nullptr, xm);
+    velocity_shape(K, xi + 3, a);
+    manufactured_velocity(K, a, 0.0, vm, vd);
+    int c[3];
+    double o[3];
+    locate(K, xm, c, o);
+    kk = lin(K, c[0], c[1], c[2]);
+    for (int d = 0; d < 3; ++d) {
+      x[d * K.np + p] = xm[d];
+      v[d * K.np + p] = vm[d];
+    }
+    id[p] = (int)p;
+    key[p] = kk;
+  }
+  int s = wave_aggregated_slot(count, kk, valid);
+  if (valid) slot[p] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Charge deposition (Sec. 2, cloud in cell), atomic free: each cell sums the
+// eight corner weights of its own particles in cell-sorted order, then each
+// node adds the eight cell moments that touch it in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_deposit_moments_f64(SimConst K, const double* x,
+                                                                const int* cstart, double* mom) {
+  int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= K.nn) return;
+  double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = cstart[c]; j < cstart[c + 1]; ++j) {
+    double xp[3] = {x[j], x[K.np + j], x[2 * K.np + j]};
+    int ci[3];
+    double o[3];
+    locate(K, xp, ci, o);
+    double wx[2] = {1.0 - o[0], o[0]}, wy[2] = {1.0 - o[1], o[1]}, wz[2] = {1.0 - o[2], o[2]};
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) m[cz * 4 + cy * 2 + cx] += wx[cx] * wy[cy] * wz[cz];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) mom[(int64_t)k * K.nn + c] = m[k];
+}
+
+__device__ inline void node_coords(const SimConst& K, int n, int& i, int& j, int& k) {
+  i = n % K.nc[0];
+  j = (n / K.nc[0]) % K.nc[1];
+  k = n / (K.nc[0] * K.nc[1]);
+}
+
+// Node charge and the right-hand side of eq. poisson_mms; block partial sums
+// of b for the mean removal.
+template <class MomT>
+__global__ void __launch_bounds__(kBlock) k_node_rhs(SimConst K, const MomT* mom, double t,
+                                                     double* rho, double* b, double* part) {
+  __shared__ double sh[kWaves];
+  int n = blockIdx.x * kBlock + threadIdx.x;
+  double bv = 0.0;
+  if (n < K.nn) {
+    int i, j, k;
+    node_coords(K, n, i, j, k);
+    double s = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx)
+          s += (double)mom[(int64_t)(cz * 4 + cy * 2 + cx) * K.nn + lin(K, i - cx, j - cy, k - cz)];
+    double r = K.rho_scale * s;
+    rho[n] = r;
+    double xn[3] = {i * K.h[0], j * K.h[1], k * K.h[2]};
+    bv = lap_phiM(K, xn, t);
+    if (K.p2f != 0.0) bv += -(r - K.q * number_density(K, xn, t)) / K.eps0;
+    b[n] = bv;
+  }
+  double tot = block_sum(bv, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sub_mean(SimConst K, double* b, const double* part,
+                                                     int nparts) {
+  __shared__ double sh[kWaves];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) acc += part[i];
+  double mean = block_sum(acc, sh) / (double)K.nn;
+  int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n < K.nn) b[n] -= mean;
+}
+
+// ---------------------------------------------------------------------------
+// Poisson CG: one cooperative persistent kernel.  A = -L_h (periodic 7-point),
+// A phi = -b.  Two grid barriers per iteration: the search direction update
+// p = r + beta p is folded into the next stencil sweep (ping-pong buffers).
+// All dot products are reduced in a fixed order, identically by every block.
+// ---------------------------------------------------------------------------
+struct CgArgs {
+  const double* b;
+  double* x;
+  double* r;
+  double* p0;
+  double* p1;
+  double* q;
+  double* partA;
+  double* partB;
+  unsigned* bar;
+  int* flags;
+  int* iters_out;
+  double* relres_out;
+  double tol;
+  int max_iter;
+};
+
+// Grid barrier with a bounded wait: returns false (and raises kFlagBarrier) if
+// it times out, so every wave always reaches the end of the kernel.
+__device__ inline bool grid_sync(unsigned* bar, int* flags) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    if (prev == gridDim.x - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 23)) {
+          good = 0;
+          atomicOr(&flags[kFlagBarrier], 1);
+          break;
+        }
+      }
+    }
+    __threadfence();
+    if (__hip_atomic_load(&flags[kFlagBarrier], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) good = 0;
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Every block sums the per-block partials in the same fixed order.
+__device__ inline double grid_allreduce(const double* part, double* sh) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) acc += part[i];
+  return block_sum(acc, sh);
+}
+
+// (-L f)(n) for f given by a callable.
+template <class F>
+__device__ inline double neg_lap(const SimConst& K, int i, int j, int k, const F& f) {
+  double c = f(lin(K, i, j, k));
+  double lx = f(lin(K, i + 1, j, k)) - 2.0 * c + f(lin(K, i - 1, j, k));
+  double ly = f(lin(K, i, j + 1, k)) - 2.0 * c + f(lin(K, i, j - 1, k));
+  double lz = f(lin(K, i, j, k + 1)) - 2.0 * c + f(lin(K, i, j, k - 1));
+  return -(lx * K.ih2[0] + ly * K.ih2[1] + lz * K.ih2[2]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
+  __shared__ double sh[kWaves];
+  const int gsize = gridDim.x * kBlock;
+  const int g0 = blockIdx.x * kBlock + threadIdx.x;
+  // r = -b - A x, p = r
+  double s_rr = 0.0, s_bb = 0.0;
+  for (int n = g0; n < K.nn; n += gsize) {
+    int i, j, k;
+    node_coords(K, n, i, j, k);
+    double ax = neg_lap(K, i, j, k, [&](int m) { return a.x[m]; });
+    double rv = -a.b[n] - ax;
+    a.r[n] = rv;
+    a.p0[n] = rv;
+    s_rr += rv * rv;
+    s_bb += a.b[n] * a.b[n];
+  }
+  double t1 = block_sum(s_rr, sh);
+  double t2 = block_sum(s_bb, sh);
+  if (threadIdx.x == 0) {
+    a.partA[blockIdx.x] = t1;
+    a.partB[blockIdx.x] = t2;
+  }
+  if (!grid_sync(a.bar, a.flags)) return;
+  double rr = grid_allreduce(a.partA, sh);
+  double bnorm = sqrt(grid_allreduce(a.partB, sh));
+  if (!grid_sync(a.bar, a.flags)) return;  // partA/partB are reused below
+  int it = 0;
+  int cur = 0;
+  double beta = 0.0;
+  if (bnorm == 0.0) {
+    for (int n = g0; n < K.nn; n += gsize) a.x[n] = 0.0;
+    rr = 0.0;
+  } else {
+    while (true) {
+      if (sqrt(rr) <= a.tol * bnorm) break;
+      if (it >= a.max_iter) {
+        if (g0 == 0) atomicOr(&a.flags[kFlagCgNoConv], 1);
+        break;
+      }
+      const double* pc = cur ? a.p1 : a.p0;
+      double* pn = cur ? a.p0 : a.p1;
+      double s_pq = 0.0;
+      if (it == 0) {
+        for (int n = g0; n < K.nn; n += gsize) {
+          int i, j, k;
+          node_coords(K, n, i, j, k);
+          double qv = neg_lap(K, i, j, k, [&](int m) { return pc[m]; });
+          a.q[n] = qv;
+          s_pq += pc[n] * qv;
+        }
+      } else {
+        for (int n = g0; n < K.nn; n += gsize) {
+          int i, j, k;
+          node_coords(K, n, i, j, k);
+          auto pnew = [&](int m) { return a.r[m] + beta * pc[m]; };
+          double pv = pnew(n);
+          pn[n] = pv;
+          double qv = neg_lap(K, i, j, k, pnew);
+          a.q[n] = qv;
+          s_pq += pv * qv;
+        }
+        cur ^= 1;
+      }
+      const double* p = cur ? a.p1 : a.p0;
+      double tp = block_sum(s_pq, sh);
+      if (threadIdx.x == 0) a.partA[blockIdx.x] = tp;
+      if (!grid_sync(a.bar, a.flags)) return;
+      double alpha = rr / grid_allreduce(a.partA, sh);
+      double s_r = 0.0;
+      for (int n = g0; n < K.nn; n += gsize) {
+        a.x[n] += alpha * p[n];
+        double rv = a.r[n] - alpha * a.q[n];
+        a.r[n] = rv;
+        s_r += rv * rv;
+      }
+      double tr = block_sum(s_r, sh);
+      if (threadIdx.x == 0) a.partB[blockIdx.x] = tr;
+      if (!grid_sync(a.bar, a.flags)) return;
+      double rr_new = grid_allreduce(a.partB, sh);
+      beta = rr_new / rr;
+      rr = rr_new;
+      ++it;
+    }
+  }
+  // zero-mean projection (Sec. 2)
+  double s_x = 0.0;
+  for (int n = g0; n < K.nn; n += gsize) s_x += a.x[n];
+  double tx = block_sum(s_x, sh);
+  if (!grid_sync(a.bar, a.flags)) return;  // everyone is past the last partA read
+  if (threadIdx.x == 0) a.partA[blockIdx.x] = tx;
+  if (!grid_sync(a.bar, a.flags)) return;
+  double mean = grid_allreduce(a.partA, sh) / (double)K.nn;
+  for (int n = g0; n < K.nn; n += gsize) a.x[n] -= mean;
+  if (g0 == 0) {
+    *a.iters_out = it;
+    *a.relres_out = bnorm == 0.0 ? 0.0 : sqrt(rr) / bnorm;
+  }
+}
+
+// E = -grad phi, central differences; optional FP32 copy for the mixed form.
+__global__ void __launch_bounds__(kBlock) k_gradient(SimConst K, const double* phi, double* E,
+                                                     float* E32) {
+  int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= K.nn) return;
+  int i, j, k;
+  node_coords(K, n, i, j, k);
+  double ex = -(phi[lin(K, i + 1, j, k)] - phi[lin(K, i - 1, j, k)]) / (2.0 * K.h[0]);
+  double ey = -(phi[lin(K, i, j + 1, k)] - phi[lin(K, i, j - 1, k)]) / (2.0 * K.h[1]);
+  double ez = -(phi[lin(K, i, j, k + 1)] - phi[lin(K, i, j, k - 1)]) / (2.0 * K.h[2]);
+  E[n] = ex;
+  E[K.nn + n] = ey;
+  E[2 * K.nn + n] = ez;
+  if (E32) {
+    E32[3 * n] = (float)ex;
+    E32[3 * n + 1] = (float)ey;
+    E32[3 * n + 2] = (float)ez;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Collisions, FP64: Algorithm 1 on each cell, N_avg independent outcomes from
+// the same pre-collision velocities, averaged in increasing outcome order
+// (eq. avg_outcome).  One thread per cell; the private velocity copy of an
+// outcome lives in `u` at the cell's own particle slots.
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t redraw_word(const SimConst& K, int cell, int64_t step, int call, int k,
+                                       int64_t m, const U64x4& wb, int r) {
+  if (r < 3) return wb.w[1 + r];
+  int64_t j = (r - 3) / 4;
+  U64x4 b = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagRedraw, (uint64_t)call,
+                         (uint64_t)k, ((uint64_t)m << 16) | (uint64_t)j);
+  return b.w[(r - 3) % 4];
+}
+
+// Candidate partner q != p: Algorithm 1 redraws q while it equals p.
+__device__ inline int pick_partner(const SimConst& K, int cell, int64_t step, int call, int k,
+                                   int64_t m, const U64x4& wa, const U64x4& wb, int p, int n) {
+  int q = index_below(wa.w[1], n);
+  int r = 0;
+  while (q == p) {
+    if (r >= 3 + 4 * 65536) {
+      q = (p + 1) % n;
+      break;
+    }
+    q = index_below(redraw_word(K, cell, step, call, k, m, wb, r), n);
+    ++r;
+  }
+  return q;
+}
+
+__global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, int64_t step,
+                                                        const double* v, const int* cstart,
+                                                        double* D, double* u,
+                                                        long long* pairlog, int64_t cap,
+                                                        unsigned long long* counters) {
+  int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= K.nn) return;
+  const int64_t NP = K.np;
+  int s = cstart[c], n = cstart[c + 1] - s;
+  for (int j = 0; j < n; ++j)
+    for (int d = 0; d < 3; ++d) D[d * NP + s + j] = 0.0;
+  if (n < 2) return;
+  unsigned long long acc = 0, gmx = 0;
+  bool touched = false;
+  for (int k = 0; k < K.navg; ++k) {
+    U64x4 w0 = stream_block(K, (uint64_t)c, (uint64_t)step, kTagColl, (uint64_t)call, (uint64_t)k, 0);
+    int64_t npairs = (int64_t)floor((double)n * (double)(n - 1) * K.pmax / 2.0 + unif(w0.w[0]));
+    if (npairs <= 0) continue;
+    for (int j = 0; j < n; ++j)
+      for (int d = 0; d < 3; ++d) u[d * NP + s + j] = v[d * NP + s + j];
+    for (int64_t m = 0; m < npairs; ++m) {
+      U64x4 wa = stream_block(K, (uint64_t)c, (uint64_t)step, kTagColl, (uint64_t)call,
+                              (uint64_t)k, (uint64_t)(1 + 2 * m));
+      U64x4 wb = stream_block(K, (uint64_t)c, (uint64_t)step, kTagColl, (uint64_t)call,
+                              (uint64_t)k, (uint64_t)(2 + 2 * m));
+      int p = index_below(wa.w[0], n);
+      int q = pick_partner(K, c, step, call, k, m, wa, wb, p, n);
+      double* up[3] = {u + s + p, u + NP + s + p, u + 2 * NP + s + p};
+      double* uq[3] = {u + s + q, u + NP + s + q, u + 2 * NP + s + q};
+      double dx = *up[0] - *uq[0], dy = *up[1] - *uq[1], dz = *up[2] - *uq[2];
+      double g = sqrt(dx * dx + dy * dy + dz * dz);
+      if (g > K.g_max) ++gmx;
+      bool ok = unif(wa.w[2]) < sigma_g(K, g) / K.sgmax;
+      if (ok) {
+        ++acc;
+        double eps = 2.0 * kPi * unif(wa.w[3]);
+        double cchi = 1.0 - 2.0 * unif(wb.w[0]);  // eq. chi_iso
+        double schi = sqrt(fmax(0.0, (1.0 - cchi) * (1.0 + cchi)));
+        double nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
+        for (int d = 0; d < 3; ++d) {
+          double vcm = 0.5 * (*up[d] + *uq[d]);
+          *up[d] = vcm + 0.5 * g * nv[d];
+          *uq[d] = vcm - 0.5 * g * nv[d];
+        }
+      }
+      if (pairlog) {
+        unsigned long long slot = atomicAdd(&counters[kCntPairLog], 1ull);
+        if ((int64_t)slot < cap) {
+          long long* r = pairlog + 7 * slot;
+          r[0] = c; r[1] = call; r[2] = k; r[3] = m; r[4] = p; r[5] = q; r[6] = ok;
+        }
+      }
+    }
+    touched = true;
+    for (int j = 0; j < n; ++j)
+      for (int d = 0; d < 3; ++d) D[d * NP + s + j] += u[d * NP + s + j] - v[d * NP + s + j];
+  }
+  if (touched)
+    for (int j = 0; j < n; ++j)
+      for (int d = 0; d < 3; ++d) D[d * NP + s + j] /= (double)K.navg;
+  if (acc) atomicAdd(&counters[kCntAccepted], acc);
+  if (gmx) atomicAdd(&counters[kCntGmax], gmx);
+}
+
+// <dv^M> per particle (eq. vel_change_3 / vel_change_1c), for the collide API.
+__global__ void __launch_bounds__(kBlock) k_source_f64(SimConst K, const double* v, const int* key,
+                                                       const int* cstart, double t, double* S) {
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= K.np) return;
+  int c = key[i];
+  int n = cstart[c + 1] - cstart[c];
+  double u[3] = {v[i], v[K.np + i], v[2 * K.np + i]}, I[3] = {0, 0, 0};
+  double coef = (K.w * K.dt * (double)(n - 1)) / (2.0 * K.dV);
+  if (n >= 2) source_integral(K, u, t, I);
+  for (int d = 0; d < 3; ++d) S[d * K.np + i] = (n >= 2) ? coef * I[d] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Half kick of eq. velocity_verlet at time t, FP64: CIC gather of E, the
+// manufactured field, the collision terms <dv> - <dv^M> and the manufactured
+// acceleration (or the exact difference in isolation mode).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_kick_f64(SimConst K, double t, double t_from,
+                                                     double t_to, double t_src, const double* x,
+                                                     double* v,
+                                                     const int* id, const int* key,
+                                                     const int* cstart, const double* E,
+                                                     const double* D) {
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= K.np) return;
+  const int64_t NP = K.np;
+  double xp[3] = {x[i], x[NP + i], x[2 * NP + i]};
+  double vp[3] = {v[i], v[NP + i], v[2 * NP + i]};
+  int c[3];
+  double o[3];
+  locate(K, xp, c, o);
+  double ep[3] = {0.0, 0.0, 0.0};
+  double wx[2] = {1.0 - o[0], o[0]}, wy[2] = {1.0 - o[1], o[1]}, wz[2] = {1.0 - o[2], o[2]};
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        int nd = lin(K, c[0] + cx, c[1] + cy, c[2] + cz);
+        double wgt = wx[cx] * wy[cy] * wz[cz];
+        for (int d = 0; d < 3; ++d) ep[d] += wgt * E[(int64_t)d * K.nn + nd];
+      }
+  double em[3];
+  EM(K, xp, t, em);
+  double h[3] = {0.0, 0.0, 0.0};
+  if (K.family == 0) {
+    double xv[3], a[3], va[3], vb[3], da[3], db[3];
+    velocity_uniforms(K, id[i], xv);
+    velocity_shape(K, xv, a);
+    if (K.isolate) {
+      manufactured_velocity(K, a, t_from, va, da);
+      manufactured_velocity(K, a, t_to, vb, db);
+      for (int d = 0; d < 3; ++d) h[d] = vb[d] - va[d];
+    } else {
+      manufactured_velocity(K, a, t, va, da);
+      for (int d = 0; d < 3; ++d) h[d] = 0.5 * K.dt * da[d];
+    }
+  }
+  double coll[3] = {0.0, 0.0, 0.0};
+  if (K.collisions) {
+    int cc = key[i];
+    int n = cstart[cc + 1] - cstart[cc];
+    double I[3] = {0, 0, 0};
+    double coef = (K.w * K.dt * (double)(n - 1)) / (2.0 * K.dV);
+    if (n >= 2) source_integral(K, vp, t_src, I);
+    for (int d = 0; d < 3; ++d) coll[d] = D[d * NP + i] - ((n >= 2) ? coef * I[d] : 0.0);
+  }
+  for (int d = 0; d < 3; ++d) {
+    double acc = K.dt * K.qm * (ep[d] - em[d]);
+    v[d * NP + i] = vp[d] + 0.5 * (acc + coll[d]) + h[d];
+  }
+}
+
+// Drift of eq. velocity_verlet with the manufactured term, periodic wrap, new
+// cell key and its count for the next sort.
+__global__ void __launch_bounds__(kBlock) k_drift_f64(SimConst K, double t0, double th, double t1,
+                                                      double* x, const double* v, const int* id,
+                                                      int* key, int* slot, int* count) {
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  bool valid = i < K.np;
+  int kk = 0;
+  if (valid) {
+    const int64_t NP = K.np;
+    double xp[3] = {x[i], x[NP + i], x[2 * NP + i]};
+    int pid = id[i];
+    double xv[3], a[3], vm[3], vdm[3], h[3] = {0.0, 0.0, 0.0};
+    velocity_uniforms(K, pid, xv);
+    velocity_shape(K, xv, a);
+    manufactured_velocity(K, a, th, vm, vdm);
+    if (K.family == 0) {
+      double xq[3];
+      position_uniforms(K, pid, xq);
+      if (K.isolate) {
+        double xa[3], xb[3];
+        manufactured_position(K, xq, t0, nullptr, xa);
+        manufactured_position(K, xq, t1, nullptr, xb);
+        for (int d = 0; d < 3; ++d) h[d] = xb[d] - xa[d];
+      } else {
+        double xm[3], xd[3];
+        manufactured_position(K, xq, th, nullptr, xm);
+        manufactured_xdot(K, xm, th, xd);
+        for (int d = 0; d < 3; ++d) h[d] = K.dt * xd[d];
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      double xn = xp[d] + K.dt * (v[d * NP + i] - vm[d]) + h[d];
+      if (xn < 0.0) xn += K.L[d];
+      if (xn >= K.L[d]) xn -= K.L[d];
+      xp[d] = xn;
+      x[d * NP + i] = xn;
+    }
+    int c[3];
+    double o[3];
+    locate(K, xp, c, o);
+    kk = lin(K, c[0], c[1], c[2]);
+    key[i] = kk;
+  }
+  int s = wave_aggregated_slot(count, kk, valid);
+  if (valid) slot[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Error norms (Sec. 4.3): per-block partial sums of squares and maxima, then a
+// single block combines them in a fixed order.  part layout: [blk][14].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_err_particles_f64(SimConst K, double t,
+                                                              const double* x, const double* v,
+                                                              const int* id, double* part,
+                                                              int* flags) {
+  __shared__ double sh[kWaves];
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  double e[6] = {0, 0, 0, 0, 0, 0};
+  if (i < K.np) {
+    double xq[3], xv[3], xm[3], a[3], vm[3], vd[3];
+    position_uniforms(K, id[i], xq);
+    velocity_uniforms(K, id[i], xv);
+    double xp[3] = {x[i], x[K.np + i], x[2 * K.np + i]};
+    manufactured_position(K, xq, t, xp, xm);
+    velocity_shape(K, xv, a);
+    manufactured_velocity(K, a, t, vm, vd);
+    for (int d = 0; d < 3; ++d) {
+      double ex = xp[d] - xm[d];
+      if (ex >= 0.5 * K.L[d]) ex -= K.L[d];
+      if (ex < -0.5 * K.L[d]) ex += K.L[d];
+      e[d] = ex;
+      e[3 + d] = v[d * K.np + i] - vm[d];
+    }
+    for (int a2 = 0; a2 < 6; ++a2)
+      if (!isfinite(e[a2])) atomicOr(&flags[kFlagNonFinite], 1);
+  }
+  for (int a2 = 0; a2 < 6; ++a2) {
+    double s2 = block_sum(e[a2] * e[a2], sh);
+    double mx = block_max(fabs(e[a2]), sh);
+    if (threadIdx.x == 0) {
+      part[blockIdx.x * 14 + a2] = s2;
+      part[blockIdx.x * 14 + 7 + a2] = mx;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_err_nodes(SimConst K, double t, const double* phi,
+                                                      double* part) {
+  __shared__ double sh[kWaves];
+  int n = blockIdx.x * kBlock + threadIdx.x;
+  double e = 0.0;
+  if (n < K.nn) {
+    int i, j, k;
+    node_coords(K, n, i, j, k);
+    double xn[3] = {i * K.h[0], j * K.h[1], k * K.h[2]};
+    e = phi[n] - phiM(K, xn, t);
+  }
+  double s2 = block_sum(e * e, sh);
+  double mx = block_max(fabs(e), sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 2] = s2;
+    part[blockIdx.x * 2 + 1] = mx;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_err_final(SimConst K, const double* ppart, int npb,
+                                                      const double* npart, int nnb, double* out) {
+  __shared__ double sh[kWaves];
+  for (int a2 = 0; a2 < 6; ++a2) {
+    double s = 0.0, m = 0.0;
+    for (int b = threadIdx.x; b < npb; b += kBlock) {
+      s += ppart[b * 14 + a2];
+      m = fmax(m, ppart[b * 14 + 7 + a2]);
+    }
+    s = block_sum(s, sh);
+    m = block_max(m, sh);
+    if (threadIdx.x == 0) {
+      out[a2] = sqrt(s / (double)K.np);
+      out[7 + a2] = m;
+    }
+  }
+  double s = 0.0, m = 0.0;
+  for (int b = threadIdx.x; b < nnb; b += kBlock) {
+    s += npart[b * 2];
+    m = fmax(m, npart[b * 2 + 1]);
+  }
+  s = block_sum(s, sh);
+  m = block_max(m, sh);
+  if (threadIdx.x == 0) {
+    out[6] = sqrt(s / (double)K.nn);
+    out[13] = m;
+  }
+}
+
+}  // namespace pic

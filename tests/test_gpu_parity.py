@@ -1,0 +1,249 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer work (cell sort, particle order, cell starts, candidate pairs, accept
+decisions) must match bit for bit.  FP64 floating point must agree to 1e-12
+relative to the natural scale of each quantity (L for positions, the largest
+|v| for velocities, max |phi| for the potential), except where the Poisson CG
+bounds the agreement: two CG runs stopped at relative residual tol differ by at
+most about kappa * tol in phi, kappa = 3 / sin^2(pi / n) for the periodic
+7-point operator, so those cases use tol 1e-13 and state the bound.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2602_15130_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _pic():
+    from paper_2602_15130_amd import pic
+    return pic
+
+
+def _pair(prob, disc, seed=1, rep=0, precision="fp64"):
+    P = _pic()
+    g = P.Sim(prob, disc, seed, rep, precision)
+    o = O.Sim(prob, disc, seed, rep)
+    assert o.init() == 0
+    return P, g, o
+
+
+def _rel(a, b, scale):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) / scale
+
+
+def _kappa(nc):
+    return 3.0 / math.sin(math.pi / max(nc)) ** 2
+
+
+def _compare_state(P, g, o, prob, disc, phi_tol=1e-12, xv_tol=1e-12, tag=""):
+    L = max(prob["L"])
+    np.testing.assert_array_equal(g.get(P.STATE_ID), o.get(o.ID), err_msg=f"particle order {tag}")
+    np.testing.assert_array_equal(g.get(P.STATE_CELL_START), o.get(o.CELL_START),
+                                  err_msg=f"cell starts {tag}")
+    xg, xo = g.get(P.STATE_X), o.get(o.X)
+    vg, vo = g.get(P.STATE_V), o.get(o.V)
+    vs = max(np.abs(vo).max(), prob["vbar"])
+    assert _rel(xg, xo, L) < xv_tol, f"x {tag}: {_rel(xg, xo, L)}"
+    assert _rel(vg, vo, vs) < xv_tol, f"v {tag}: {_rel(vg, vo, vs)}"
+    rg, ro = g.get(P.STATE_RHO), o.get(o.RHO)
+    assert _rel(rg, ro, np.abs(ro).max()) < 1e-12, f"rho {tag}"
+    pg, po = g.get(P.STATE_PHI), o.get(o.PHI)
+    assert _rel(pg, po, np.abs(po).max()) < phi_tol, f"phi {tag}: {_rel(pg, po, np.abs(po).max())}"
+    eg, eo = g.get(P.STATE_E), o.get(o.E)
+    assert _rel(eg, eo, np.abs(eo).max()) < phi_tol * 10, f"E {tag}"
+
+
+def _small(nc, np_, dt, navg, two_way=True, collisions=True, tol=1e-13, **kw):
+    prob = W.cfg_problem(two_way=two_way, collisions=collisions, **kw)
+    disc = W.cfg_disc(nc, np_, dt, 1, navg, cg_tol=tol)
+    return prob, disc
+
+
+# ----------------------------------------------------------------------------- init
+def test_init_parity_cfg0():
+    c = W.get("cfg0")
+    P, g, o = _pair(c["problem"], c["disc"])
+    _compare_state(P, g, o, c["problem"], c["disc"], tag="init")
+    e = g.errors()
+    assert np.all(e["l2"][:6] == 0) and np.all(e["linf"][:6] == 0)
+    eo = o.errors()
+    np.testing.assert_allclose(e["l2"][6], eo["l2"][6], rtol=1e-12)
+
+
+@pytest.mark.parametrize("np_", [1, 2, 255, 257, 5000])
+def test_init_parity_ragged_and_sparse(np_):
+    # ragged particle counts, many empty cells and single-particle cells
+    prob, disc = _small(8, np_, 1e-3, 2)
+    P, g, o = _pair(prob, disc, seed=7)
+    _compare_state(P, g, o, prob, disc, phi_tol=_kappa(disc["nc"]) * 1e-13, tag=f"np={np_}")
+
+
+def test_init_parity_non_cubic_mesh():
+    prob = W.cfg_problem()
+    prob["L"] = (1.0, 0.75, 1.25)
+    disc = {"nc": (5, 7, 9), "np": 3000, "dt": 1e-3, "navg": 3, "cg_tol": 1e-13,
+            "cg_max_iter": 5000, "steps": 1}
+    P, g, o = _pair(prob, disc, seed=3)
+    _compare_state(P, g, o, prob, disc, phi_tol=_kappa(disc["nc"]) * 1e-13, tag="non-cubic")
+
+
+# ----------------------------------------------------------------------------- steps
+def test_steps_parity_cfg0_full_run():
+    """cfg0 (8^3, 16,384 particles, one-way, hard-sphere NTC, N_avg = 4), all 10 steps."""
+    c = W.get("cfg0")
+    P, g, o = _pair(c["problem"], c["disc"])
+    for s in range(c["disc"]["steps"]):
+        g.step(1)
+        assert o.step(1) == 0
+        _compare_state(P, g, o, c["problem"], c["disc"], tag=f"step {s + 1}")
+    sg, eo = g.stats(), o.errors()
+    assert sg["n_accepted"] == o.accepted and sg["n_gmax"] == o.gmax_events
+    e = g.errors()
+    np.testing.assert_allclose(e["l2"], eo["l2"], rtol=1e-9)
+    np.testing.assert_allclose(e["linf"], eo["linf"], rtol=1e-9)
+
+
+def test_steps_parity_two_way_collisional():
+    prob, disc = _small(8, 12000, 2e-3, 6, two_way=True, collisions=True, collisionality=20.0)
+    P, g, o = _pair(prob, disc, seed=11)
+    tol = _kappa(disc["nc"]) * 1e-13
+    for s in range(4):
+        g.step(1)
+        o.step(1)
+        _compare_state(P, g, o, prob, disc, phi_tol=tol, xv_tol=1e-11, tag=f"step {s + 1}")
+    assert g.stats()["n_accepted"] == o.accepted > 0
+
+
+def test_steps_parity_paper_family_collisional():
+    """Sec. 5.2 functions, polynomial cross section, Table 1 level-1 mesh and
+    time step with a reduced particle count."""
+    prob = W.paper_problem(collisions=True)
+    disc = dict(W.paper_level(1, cg_tol=1e-13))
+    disc["np"] = 6000
+    disc["navg"] = 8
+    P, g, o = _pair(prob, disc, seed=2)
+    tol = _kappa(disc["nc"]) * 1e-13
+    for s in range(3):
+        g.step(1)
+        o.step(1)
+        _compare_state(P, g, o, prob, disc, phi_tol=tol, xv_tol=1e-11, tag=f"paper step {s + 1}")
+    eg, eo = g.errors(), o.errors()
+    np.testing.assert_allclose(eg["l2"], eo["l2"], rtol=1e-7)
+
+
+def test_isolation_mode_gpu_matches_manufactured_trajectory():
+    prob = W.paper_problem(collisions=False, field_to_particles=False, particles_to_field=False,
+                           isolate=True)
+    disc = dict(W.paper_level(1, collisions=False))
+    disc["np"] = 3000
+    P = _pic()
+    g = P.Sim(prob, disc, 5, 0)
+    g.step(4)
+    e = g.errors()
+    assert e["linf"][:3].max() < 5e-15 * W.L_PAPER
+    assert e["linf"][3:6].max() < 5e-14 * W.VBAR
+
+
+# ----------------------------------------------------------------------------- collisions
+def _pairs_sorted(arr):
+    a = np.asarray(arr, dtype=np.int64).reshape(-1, 7)
+    order = np.lexsort((a[:, 3], a[:, 2], a[:, 1], a[:, 0]))
+    return a[order]
+
+
+@pytest.mark.parametrize("call", [0, 1])
+def test_collide_parity_and_pair_list(call):
+    prob, disc = _small(8, 16384, 1e-3, 4, collisionality=30.0)
+    P, g, o = _pair(prob, disc, seed=4)
+    cap = 400000
+    dg, sg, pg, ng = g.collide(call, 0.0, pairlog_cap=cap)
+    do, so, po, no, st = o.collide(call, 0.0, log_cap=cap)
+    assert ng == no and ng > 1000
+    np.testing.assert_array_equal(_pairs_sorted(pg), _pairs_sorted(po))
+    scale = np.abs(o.get(o.V)).max()
+    assert _rel(dg, do, scale) < 1e-12
+    assert _rel(sg, so, np.abs(so).max()) < 1e-12
+
+
+def test_collide_momentum_conserved_per_cell():
+    prob, disc = _small(8, 16384, 1e-3, 4, collisionality=30.0)
+    P = _pic()
+    g = P.Sim(prob, disc, 9, 0)
+    dv, _, _, _ = g.collide(0, 0.0)
+    cs = g.get(P.STATE_CELL_START)
+    sums = np.add.reduceat(dv, cs[:-1], axis=1)[:, np.diff(cs) > 0]
+    assert np.abs(sums).max() < 1e-13
+
+
+def test_deterministic_rerun():
+    prob, disc = _small(8, 9000, 2e-3, 4, collisionality=20.0)
+    P = _pic()
+    a = P.Sim(prob, disc, 21, 3)
+    b = P.Sim(prob, disc, 21, 3)
+    a.step(3)
+    b.step(3)
+    for item in (P.STATE_X, P.STATE_V, P.STATE_ID, P.STATE_PHI):
+        np.testing.assert_array_equal(a.get(item), b.get(item))
+
+
+# ----------------------------------------------------------------------------- errors
+def test_error_norms_parity_after_steps():
+    prob, disc = _small(8, 8000, 2e-3, 3, collisionality=10.0)
+    P, g, o = _pair(prob, disc, seed=13)
+    g.step(3)
+    o.step(3)
+    eg, eo = g.errors(), o.errors()
+    np.testing.assert_allclose(eg["l2"], eo["l2"], rtol=1e-9)
+    np.testing.assert_allclose(eg["linf"], eo["linf"], rtol=1e-9)
+
+
+def test_cg_nonconvergence_reported():
+    prob, disc = _small(8, 4000, 1e-3, 1, collisions=False)
+    disc["cg_max_iter"] = 1
+    P = _pic()
+    with pytest.raises(P.PicError) as ei:
+        g = P.Sim(prob, disc, 1, 0)
+        g.stats()
+    assert ei.value.code == P.PIC_ENOCONV
+
+
+# ----------------------------------------------------------------------------- full size
+def test_full_size_cfg2_properties_and_samples():
+    """cfg2 at full size (64^3, 8,388,608 particles, N_avg = 16): properties that
+    hold at any size, and sampled particles/cells against the oracle."""
+    c = W.get("cfg2")
+    prob, disc = c["problem"], c["disc"]
+    P = _pic()
+    g = P.Sim(prob, disc, c["seed"], 0)
+    g.step(1)
+    cs = g.get(P.STATE_CELL_START)
+    ids = g.get(P.STATE_ID)
+    x = g.get(P.STATE_X)
+    v = g.get(P.STATE_V)
+    assert cs[0] == 0 and cs[-1] == disc["np"] and np.all(np.diff(cs) >= 0)
+    assert np.array_equal(np.sort(ids), np.arange(disc["np"]))
+    keys = O.cell_keys(prob, disc, x)
+    assert np.all(np.diff(keys) >= 0)
+    np.testing.assert_array_equal(cs, np.concatenate([[0], np.cumsum(np.bincount(keys, minlength=64**3))]))
+    rho = g.get(P.STATE_RHO)
+    assert rho.sum() * (1 / 64) ** 3 == pytest.approx(prob["q"] * prob["nphys"], rel=1e-12)
+    # sampled cells: the oracle's Algorithm 1 on the same cell velocities
+    dv, src, _, _ = g.collide(0, g.stats()["step"] * disc["dt"])
+    rng = np.random.default_rng(0)
+    for cell in rng.choice(64**3, size=24, replace=False):
+        s, e = cs[cell], cs[cell + 1]
+        do, _, _, _ = O.collide_cell(prob, disc, c["seed"], 0, 1, 0, int(cell), v[:, s:e])
+        assert _rel(dv[:, s:e], do, max(1.0, np.abs(v[:, s:e]).max())) < 1e-12
+    # sampled particles: manufactured velocity from the particle identity
+    for i in rng.choice(disc["np"], size=32, replace=False):
+        xi = O.init_uniforms(c["seed"], 0, int(ids[i]))
+        vm = O.vM(prob, xi[3:], 0.0)
+        # one step moved v by field, collisions and source only: stays near v^M
+        assert np.abs(v[:, i] - vm).max() < 1.0
