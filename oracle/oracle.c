@@ -196,13 +196,21 @@ static double normal_quantile_guess(double p) {
   return (p < 0.5) ? -z : z;
 }
 
+/* Both velocity densities are even, so F^{-1}(xi) = -F^{-1}(1 - xi); the root is
+ * taken on the lower half, where F - xi keeps its relative accuracy (near
+ * F = 1 the residual would lose the digits of the tail).  1 - xi is exact for
+ * the sampled xi. */
 static double paper_a_of_xi(double xi) {
-  double a0 = cbrt(1.5 * sqrt(PI_D) * (xi - 0.5));
-  return solve_cdf(paper_G, NULL, xi, -30.0, 30.0, a0);
+  double pp = (xi < 0.5) ? xi : 1.0 - xi;
+  double a0 = cbrt(1.5 * sqrt(PI_D) * (pp - 0.5));
+  double a = solve_cdf(paper_G, NULL, pp, -30.0, 0.0, a0);
+  return (xi < 0.5) ? a : -a;
 }
 
 static double gauss_z_of_xi(double xi) {
-  return solve_cdf(gauss_Phi, NULL, xi, -40.0, 40.0, normal_quantile_guess(xi));
+  double pp = (xi < 0.5) ? xi : 1.0 - xi;
+  double z = solve_cdf(gauss_Phi, NULL, pp, -40.0, 0.0, normal_quantile_guess(pp));
+  return (xi < 0.5) ? z : -z;
 }
 
 /* Sec. 5.2: vhat_u, vhat_v, vhat_w and their time derivatives. */

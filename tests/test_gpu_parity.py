@@ -247,3 +247,56 @@ def test_full_size_cfg2_properties_and_samples():
         vm = O.vM(prob, xi[3:], 0.0)
         # one step moved v by field, collisions and source only: stays near v^M
         assert np.abs(v[:, i] - vm).max() < 1.0
+
+
+# ----------------------------------------------------------------------------- fused pass
+def _run_path(prob, disc, unfused, steps, seed=5):
+    import os
+    P = _pic()
+    old = os.environ.get("PIC_UNFUSED")
+    os.environ["PIC_UNFUSED"] = "1" if unfused else "0"
+    try:
+        g = P.Sim(prob, disc, seed, 1)
+    finally:
+        if old is None:
+            os.environ.pop("PIC_UNFUSED")
+        else:
+            os.environ["PIC_UNFUSED"] = old
+    for n in steps:
+        g.step(n)
+    return P, g
+
+
+@pytest.mark.parametrize("case", ["cfg0", "dense", "paper"])
+def test_fused_pass_is_bitwise_equal_to_unfused(case):
+    """The fused particle pass (call B, kick 2, call A, kick 1, drift per
+    cell-aligned tile) performs the same operations in the same order as the
+    separate kernels, so the two paths agree bit for bit, including when
+    pic_step is called with different step counts."""
+    if case == "cfg0":
+        c = W.get("cfg0")
+        prob, disc = c["problem"], c["disc"]
+    elif case == "dense":  # most (cell, outcome) lanes have pairs: the event list overflows
+        prob, disc = _small(8, 16384, 2e-3, 128, collisionality=5.0)
+    else:
+        prob = W.paper_problem(collisions=True)
+        disc = dict(W.paper_level(1, cg_tol=1e-13))
+        disc["np"] = 6000
+        disc["navg"] = 8
+    P, a = _run_path(prob, disc, False, [1, 3, 2])
+    _, b = _run_path(prob, disc, True, [1, 3, 2])
+    for item in (P.STATE_X, P.STATE_V, P.STATE_ID, P.STATE_CELL_START, P.STATE_PHI):
+        np.testing.assert_array_equal(a.get(item), b.get(item))
+    assert a.stats()["n_accepted"] == b.stats()["n_accepted"]
+
+
+def test_fused_pass_large_cells_use_global_scratch():
+    """Cells larger than the LDS tile (here ~700 particles per cell) take the
+    global-memory path of the same kernel; parity with the oracle holds."""
+    prob, disc = _small(3, 19000, 1e-3, 3, collisionality=2.0)
+    P, g, o = _pair(prob, disc, seed=8)
+    for s in range(2):
+        g.step(1)
+        o.step(1)
+        _compare_state(P, g, o, prob, disc, phi_tol=_kappa(disc["nc"]) * 1e-13, xv_tol=1e-11,
+                       tag=f"large cells step {s + 1}")

@@ -137,6 +137,13 @@ def test_cfg_inverse_cdfs():
         F, _ = integrate.quad(lambda z: 1 + a * math.sin(2 * math.pi * z), 0.0, x[2],
                               epsabs=1e-15, epsrel=1e-14)
         assert F == pytest.approx(xi[2], abs=2e-15)
+    # tails: the quantile stays accurate near xi = 1 (third-party reference)
+    for q in (1e-6, 1e-10, 2.0**-40):
+        xi_hi = 1.0 - q
+        v = O.vM(CFG, [xi_hi, q, 0.5 + q], 0.0)
+        # 1 - xi_hi is exact in FP64, and is the upper-tail probability of xi_hi
+        assert v[0] == pytest.approx(stats.norm.isf(1.0 - xi_hi), rel=1e-13)
+        assert v[1] == pytest.approx(-stats.norm.isf(q), rel=1e-13)
     # the configuration family is time independent
     xi = [0.3, 0.6, 0.9]
     assert np.all(O.xdotM(CFG, O.xM(CFG, xi, 0), 0.01) == 0)
