@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -12,6 +13,8 @@
 
 #include "../../include/pic.h"
 #include "pic_kernels.hpp"
+#include "pic_particle.hpp"
+#include "pic_mixed.hpp"
 
 using namespace pic;
 
@@ -23,11 +26,11 @@ constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 enum Arr {
-  A_X0, A_X1, A_V0, A_V1, A_ID0, A_ID1,              // FP64 particle state, two buffers
-  A_CELL0, A_CELL1, A_OFF0, A_OFF1, A_VF0, A_VF1,    // mixed particle state, two buffers
-  A_KEY, A_SLOT, A_TIDX, A_TKEY, A_D, A_U,
-  A_COUNT, A_CSTART, A_BSUM, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_R, A_P0, A_P1, A_Q,
-  A_PART_A, A_PART_B, A_EPART, A_NPART, A_NORMS, A_BAR, A_FLAGS, A_CNT, A_CGIT, A_CGRR,
+  A_X0, A_X1, A_V0, A_V1, A_SH0, A_SH1, A_ID0, A_ID1,  // FP64 particle state, two buffers
+  A_OFF0, A_OFF1, A_VF0, A_VF1, A_ASF0, A_ASF1,      // mixed particle state, two buffers
+  A_KEY, A_SLOT, A_TIDX, A_TKEY, A_D, A_U, A_V0G,
+  A_COUNT, A_CSTART, A_BSUM, A_TILE, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_R, A_P0, A_P1, A_Q,
+  A_PART_A, A_PART_B, A_EPART, A_NPART, A_NORMS, A_BAR, A_RESULT, A_FLAGS, A_CNT, A_CGIT, A_CGRR,
   A_NARR
 };
 
@@ -46,17 +49,18 @@ Layout make_layout(const pic_discretization* d, int precision) {
   const int64_t pf = f64 ? np : 0, pm = f64 ? 0 : np;
   Layout L;
   int64_t b[A_NARR] = {};
-  b[A_X0] = b[A_X1] = b[A_V0] = b[A_V1] = 3 * pf * 8;
+  b[A_X0] = b[A_X1] = b[A_V0] = b[A_V1] = b[A_SH0] = b[A_SH1] = 3 * pf * 8;
   b[A_ID0] = b[A_ID1] = np * 4;
-  b[A_CELL0] = b[A_CELL1] = pm * 4;
-  b[A_OFF0] = b[A_OFF1] = b[A_VF0] = b[A_VF1] = 3 * pm * 4;
+  b[A_OFF0] = b[A_OFF1] = b[A_VF0] = b[A_VF1] = b[A_ASF0] = b[A_ASF1] = 3 * pm * 4;
   b[A_KEY] = b[A_SLOT] = b[A_TIDX] = b[A_TKEY] = np * 4;
   b[A_D] = 3 * np * (f64 ? 8 : 4);
-  b[A_U] = 3 * pf * 8;
+  b[A_U] = 3 * np * 8;    // private collision copies; FP64 export of the mixed state
+  b[A_V0G] = 3 * np * 8;
   b[A_COUNT] = nn * 4;
   b[A_CSTART] = (nn + 1) * 4;
   b[A_BSUM] = (nscan + 1) * 4;
-  b[A_MOM] = 8 * nn * (f64 ? 8 : 4);
+  b[A_TILE] = ((np + kTileB - 1) / kTileB + 2) * 4;
+  b[A_MOM] = 64 * nn;  // 8 FP64 cell moments, or 8 FP32 moments + 8 compensations
   b[A_RHO] = b[A_B] = b[A_PHI] = b[A_R] = b[A_P0] = b[A_P1] = b[A_Q] = nn * 8;
   b[A_E] = 3 * nn * 8;
   b[A_E32] = f64 ? 0 : 3 * nn * 4;
@@ -64,7 +68,8 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_EPART] = nblk_p * 14 * 8;
   b[A_NPART] = nblk_n * 2 * 8;
   b[A_NORMS] = 16 * 8;
-  b[A_BAR] = 2 * 4;
+  b[A_BAR] = (int64_t)(4096 + 1) * kFlagStride * 4;  // per-block arrival flags + release word
+  b[A_RESULT] = kMaxRed * 8;
   b[A_FLAGS] = kFlagCount * 4;
   b[A_CNT] = kCntCount * 8;
   b[A_CGIT] = 4;
@@ -205,17 +210,19 @@ struct pic_ctx {
   Layout layout{};
   double* x[2]{};
   double* v[2]{};
+  double* sh[2]{};
   int* id[2]{};
-  int* cell[2]{};
   float* off[2]{};
   float* vf[2]{};
-  int *key{}, *slot{}, *tidx{}, *tkey{}, *count{}, *cstart{}, *bsum{};
-  double *D{}, *U{};
+  float* asf[2]{};
+  int *key{}, *slot{}, *tidx{}, *tkey{}, *count{}, *cstart{}, *bsum{}, *tile_c0{};
+  double *D{}, *U{}, *V0G{};
   float* Df{};
+  bool fused = true;
   void* mom{};
   double *rho{}, *b{}, *phi{}, *E{}, *r{}, *p0{}, *p1{}, *q{}, *partA{}, *partB{};
   float* E32{};
-  double *epart{}, *npart{}, *norms{}, *cgrr{};
+  double *epart{}, *npart{}, *norms{}, *cgrr{}, *result{};
   unsigned* bar{};
   int *flags{}, *cgit{};
   unsigned long long* cnt{};
@@ -332,12 +339,24 @@ int scan_counts(pic_ctx* c) {
 int sort_particles(pic_ctx* c) {
   StageTimer tm(c, PIC_STAGE_SORT);
   TRY(scan_counts(c));
+  {  // cell-aligned tiles of the fused particle pass
+    const int ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
+    TRY(fill<int>(c, c->tile_c0, c->K.nn, ntiles + 1));
+    k_tile_bounds<<<grid_for(c->K.nn), kBlock, 0, c->stream>>>(c->cstart, c->K.nn, c->tile_c0, ntiles);
+    LAUNCH_CHECK(c, "tile bounds");
+  }
   int np = (int)c->K.np;
   k_scatter<<<grid_for(np), kBlock, 0, c->stream>>>(c->key, c->slot, c->cstart, c->tidx, c->tkey, np);
   int s = c->cur, d = 1 - c->cur;
-  k_order_f64<<<grid_for(np), kBlock, 0, c->stream>>>(c->tidx, c->tkey, c->cstart, c->x[s], c->v[s],
-                                                       c->id[s], c->x[d], c->v[d], c->id[d], c->key,
-                                                       np);
+  if (c->precision == PIC_FP64)
+    k_order_f64<<<grid_for(np), kBlock, 0, c->stream>>>(c->tidx, c->tkey, c->cstart, c->x[s], c->v[s],
+                                                         c->sh[s], c->id[s], c->x[d], c->v[d],
+                                                         c->sh[d], c->id[d], c->key, np, c->flags);
+  else
+    k_order_mixed<<<grid_for(np), kBlock, 0, c->stream>>>(c->tidx, c->tkey, c->cstart, c->off[s],
+                                                           c->vf[s], c->asf[s], c->id[s], c->off[d],
+                                                           c->vf[d], c->asf[d], c->id[d], c->key, np,
+                                                           c->flags);
   LAUNCH_CHECK(c, "sort");
   c->cur = d;
   return PIC_OK;
@@ -349,14 +368,22 @@ int field_solve(pic_ctx* c, double t) {
   int nbn = grid_for(K.nn);
   {
     StageTimer tm(c, PIC_STAGE_DEPOSIT);
-    k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
-                                                         (double*)c->mom);
-    k_node_rhs<double><<<nbn, kBlock, 0, c->stream>>>(K, (const double*)c->mom, t, c->rho, c->b,
+    if (c->precision == PIC_FP64) {
+      k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
+                                                           (double*)c->mom);
+      k_node_rhs<double><<<nbn, kBlock, 0, c->stream>>>(K, (const double*)c->mom, t, c->rho, c->b,
+                                                        c->partA);
+    } else {
+      k_deposit_moments_mixed<<<nbn, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
+                                                             (float*)c->mom);
+      k_node_rhs_mixed<<<nbn, kBlock, 0, c->stream>>>(K, (const float*)c->mom, t, c->rho, c->b,
                                                       c->partA);
+    }
     k_sub_mean<<<nbn, kBlock, 0, c->stream>>>(K, c->b, c->partA, nbn);
     LAUNCH_CHECK(c, "rhs");
   }
-  TRY(fill<unsigned>(c, c->bar, 0u, 2));
+  // arrival flags of every block plus the release word, zeroed before each launch
+  TRY(fill<unsigned>(c, c->bar, 0u, (int64_t)(c->cg_grid + 1) * kFlagStride));
   CgArgs a;
   a.b = c->b;
   a.x = c->phi;
@@ -364,9 +391,10 @@ int field_solve(pic_ctx* c, double t) {
   a.p0 = c->p0;
   a.p1 = c->p1;
   a.q = c->q;
-  a.partA = c->partA;
-  a.partB = c->partB;
-  a.bar = c->bar;
+  a.part = c->partA;
+  a.result = c->result;
+  a.arrive = c->bar;
+  a.release = c->bar + (int64_t)c->cg_grid * kFlagStride;
   a.flags = c->flags;
   a.iters_out = c->cgit;
   a.relres_out = c->cgrr;
@@ -389,7 +417,7 @@ int collide(pic_ctx* c, int call, int64_t step, double* D, long long* pairlog, i
   const SimConst& K = c->K;
   StageTimer tm(c, PIC_STAGE_COLLIDE);
   k_collide_f64<<<grid_for(K.nn), kBlock, 0, c->stream>>>(K, call, step, c->v[c->cur], c->cstart, D,
-                                                          c->U, pairlog, cap, c->cnt);
+                                                          c->U, pairlog, cap, c->cnt, c->flags);
   LAUNCH_CHECK(c, "collide");
   return PIC_OK;
 }
@@ -399,7 +427,8 @@ int kick(pic_ctx* c, double t, double t_from, double t_to, double t_src) {
   StageTimer tm(c, PIC_STAGE_KICK);
   int s = c->cur;
   k_kick_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, t, t_from, t_to, t_src, c->x[s], c->v[s],
-                                                       c->id[s], c->key, c->cstart, c->E, c->D);
+                                                       c->sh[s], c->id[s], c->key, c->cstart, c->E,
+                                                       c->D);
   LAUNCH_CHECK(c, "kick");
   return PIC_OK;
 }
@@ -409,9 +438,109 @@ int drift(pic_ctx* c, double t0, double th, double t1) {
   StageTimer tm(c, PIC_STAGE_DRIFT);
   TRY(fill<int>(c, c->count, 0, K.nn));
   int s = c->cur;
-  k_drift_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, t0, th, t1, c->x[s], c->v[s], c->id[s],
-                                                        c->key, c->slot, c->count);
+  k_drift_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, t0, th, t1, c->x[s], c->v[s], c->sh[s],
+                                                        c->id[s], c->key, c->slot, c->count,
+                                                        c->flags);
   LAUNCH_CHECK(c, "drift");
+  return PIC_OK;
+}
+
+PartArgs part_args(pic_ctx* c) {
+  PartArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int s = c->cur;
+  a.x = c->x[s];
+  a.v = c->v[s];
+  a.ash = c->sh[s];
+  a.id = c->id[s];
+  a.key = c->key;
+  a.slot = c->slot;
+  a.count = c->count;
+  a.cstart = c->cstart;
+  a.tile_c0 = c->tile_c0;
+  a.E = c->E;
+  a.gv0 = c->V0G;
+  a.gu = c->U;
+  a.gD = c->D;
+  a.counters = c->cnt;
+  a.flags = c->flags;
+  a.callB = 1;
+  a.callA = 0;
+  return a;
+}
+
+MixConst mix_const(const SimConst& K, double tA, double tB) {
+  MixConst M;
+  M.dt = (float)K.dt;
+  M.dtqm = (float)(K.dt * K.qm);
+  for (int d = 0; d < 3; ++d) {
+    M.inv_h[d] = (float)K.inv_h[d];
+    M.inv_n[d] = (float)(1.0 / K.nc[d]);
+    double kd = 2.0 * kPi / K.L[d];
+    M.emA[d] = (float)(K.phibar * std::exp(tA / (2.0 * K.T)) * kd);
+    M.emB[d] = (float)(K.phibar * std::exp(tB / (2.0 * K.T)) * kd);
+  }
+  M.vbar = (float)K.vbar;
+  M.src_w = (float)(K.w * K.dt / (2.0 * K.dV));
+  M.sigma_ref = (float)K.sigma_ref;
+  return M;
+}
+
+// Fused pass specialised on (manufactured family, cross-section model).
+int launch_particles(pic_ctx* c, const PartArgs& a) {
+  const SimConst& K = c->K;
+  const int tiles = (int)((K.np + kTileB - 1) / kTileB);
+  const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
+  if (c->precision == PIC_MIXED) {
+    const double tA = (double)a.na * K.dt, tB = ((double)a.nb + 1.0) * K.dt;
+    MixConst M = mix_const(K, tA, tB);
+    const int s = c->cur;
+    if (sig == kSigHS)
+      k_particles_mixed<kSigHS><<<tiles, kBlock, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+    else if (sig == kSigMaxwell)
+      k_particles_mixed<kSigMaxwell><<<tiles, kBlock, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+    else
+      k_particles_mixed<kSigPoly><<<tiles, kBlock, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+    LAUNCH_CHECK(c, "particles (mixed)");
+    return PIC_OK;
+  }
+  if (K.family == 1) {
+    if (sig == kSigHS) k_particles_f64<1, kSigHS><<<tiles, kBlock, 0, c->stream>>>(K, a);
+    else if (sig == kSigMaxwell) k_particles_f64<1, kSigMaxwell><<<tiles, kBlock, 0, c->stream>>>(K, a);
+    else k_particles_f64<1, kSigPoly><<<tiles, kBlock, 0, c->stream>>>(K, a);
+  } else {
+    if (sig == kSigMaxwell) k_particles_f64<0, kSigMaxwell><<<tiles, kBlock, 0, c->stream>>>(K, a);
+    else k_particles_f64<0, kSigPoly><<<tiles, kBlock, 0, c->stream>>>(K, a);
+  }
+  LAUNCH_CHECK(c, "particles");
+  return PIC_OK;
+}
+
+int particle_pass(pic_ctx* c, int mode, int64_t nb, int64_t na) {
+  const SimConst& K = c->K;
+  StageTimer tm(c, PIC_STAGE_PARTICLE);
+  if (mode & kDoA) TRY(fill<int>(c, c->count, 0, K.nn));
+  PartArgs a = part_args(c);
+  a.mode = mode;
+  a.nb = nb;
+  a.na = na;
+  TRY(launch_particles(c, a));
+  return PIC_OK;
+}
+
+// n_steps of eq. velocity_verlet with the fused particle pass: the pass after
+// each field solve finishes step s (call B, kick 2) and starts step s + 1
+// (call A, kick 1, drift).
+int fused_steps(pic_ctx* c, int n_steps) {
+  for (int i = 0; i < n_steps; ++i) {
+    const int64_t s = c->step;
+    if (i == 0) TRY(particle_pass(c, kDoA, 0, s));
+    TRY(sort_particles(c));
+    TRY(field_solve(c, ((double)s + 1.0) * c->K.dt));
+    if (i == n_steps - 1) TRY(particle_pass(c, kDoB, s, 0));
+    else TRY(particle_pass(c, kDoB | kDoA, s, s + 1));
+    c->step = s + 1;
+  }
   return PIC_OK;
 }
 
@@ -443,6 +572,10 @@ int check_flags(pic_ctx* c) {
     c->err = "Poisson CG reached cg_max_iter before cg_tol";
     return PIC_ENOCONV;
   }
+  if (f[kFlagCapacity]) {
+    c->err = "degenerate state: a cell exceeded the stable-sort or pair-count bound";
+    return PIC_ENONFINITE;
+  }
   if (f[kFlagNonFinite]) {
     c->err = "non-finite particle state";
     return PIC_ENONFINITE;
@@ -461,10 +594,6 @@ int pic_workspace_size(const pic_problem* prob, const pic_discretization* disc, 
   if (st != PIC_OK) {
     g_create_error = err;
     return st;
-  }
-  if (precision == PIC_MIXED) {
-    g_create_error = "mixed precision form not built yet";
-    return PIC_EINVAL;
   }
   if (!bytes) {
     g_create_error = "null bytes";
@@ -500,6 +629,10 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   }
   c->K = derive(prob, disc, seed, replicate);
   c->precision = precision;
+  {
+    const char* e = std::getenv("PIC_UNFUSED");
+    c->fused = !(e && e[0] == '1') || precision == PIC_MIXED;
+  }
   c->cg_tol = disc->cg_tol;
   c->cg_max_iter = disc->cg_max_iter;
   c->stream = (hipStream_t)hip_stream;
@@ -509,6 +642,14 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   c->x[1] = carve<double>(c, A_X1);
   c->v[0] = carve<double>(c, A_V0);
   c->v[1] = carve<double>(c, A_V1);
+  c->sh[0] = carve<double>(c, A_SH0);
+  c->sh[1] = carve<double>(c, A_SH1);
+  c->off[0] = carve<float>(c, A_OFF0);
+  c->off[1] = carve<float>(c, A_OFF1);
+  c->vf[0] = carve<float>(c, A_VF0);
+  c->vf[1] = carve<float>(c, A_VF1);
+  c->asf[0] = carve<float>(c, A_ASF0);
+  c->asf[1] = carve<float>(c, A_ASF1);
   c->id[0] = carve<int>(c, A_ID0);
   c->id[1] = carve<int>(c, A_ID1);
   c->key = carve<int>(c, A_KEY);
@@ -517,9 +658,11 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   c->tkey = carve<int>(c, A_TKEY);
   c->D = carve<double>(c, A_D);
   c->U = carve<double>(c, A_U);
+  c->V0G = carve<double>(c, A_V0G);
   c->count = carve<int>(c, A_COUNT);
   c->cstart = carve<int>(c, A_CSTART);
   c->bsum = carve<int>(c, A_BSUM);
+  c->tile_c0 = carve<int>(c, A_TILE);
   c->mom = carve<void>(c, A_MOM);
   c->rho = carve<double>(c, A_RHO);
   c->b = carve<double>(c, A_B);
@@ -536,6 +679,7 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   c->npart = carve<double>(c, A_NPART);
   c->norms = carve<double>(c, A_NORMS);
   c->bar = carve<unsigned>(c, A_BAR);
+  c->result = carve<double>(c, A_RESULT);
   c->flags = carve<int>(c, A_FLAGS);
   c->cnt = carve<unsigned long long>(c, A_CNT);
   c->cgit = carve<int>(c, A_CGIT);
@@ -562,8 +706,12 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     TRY(fill<double>(c, c->phi, 0.0, K.nn));
     // unsorted initial state in buffer 1, sorted into buffer 0
     c->cur = 1;
-    k_init_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->x[1], c->v[1], c->id[1], c->key,
-                                                         c->slot, c->count);
+    if (c->precision == PIC_FP64)
+      k_init_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->x[1], c->v[1], c->sh[1], c->id[1],
+                                                           c->key, c->slot, c->count);
+    else
+      k_init_mixed<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->off[1], c->vf[1], c->asf[1],
+                                                             c->id[1], c->key, c->slot, c->count);
     LAUNCH_CHECK(c, "init");
     TRY(sort_particles(c));
     TRY(field_solve(c, 0.0));
@@ -588,6 +736,7 @@ int pic_step(pic_ctx* c, int n_steps) {
     c->err = "n_steps must be >= 0";
     return PIC_EINVAL;
   }
+  if (c->fused) return fused_steps(c, n_steps);
   for (int s = 0; s < n_steps; ++s) TRY(one_step(c));
   return PIC_OK;
 }
@@ -602,10 +751,24 @@ int pic_collide(pic_ctx* c, int call, double t, double* dv_avg, double* dv_src, 
   }
   const SimConst& K = c->K;
   TRY(fill<unsigned long long>(c, c->cnt + kCntPairLog, 0ull, 1));
-  TRY(collide(c, call, c->step, dv_avg, pairlog_cap > 0 ? (long long*)pairlog : nullptr,
-              pairlog_cap));
-  k_source_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->v[c->cur], c->key, c->cstart, t, dv_src);
-  LAUNCH_CHECK(c, "source");
+  if (c->fused) {
+    PartArgs a = part_args(c);
+    a.mode = kCollideOnly;
+    a.na = c->step;
+    a.callA = call;
+    a.tB = t;
+    a.Dout = dv_avg;
+    a.Sout = dv_src;
+    a.pairlog = pairlog_cap > 0 ? (long long*)pairlog : nullptr;
+    a.cap = pairlog_cap;
+    TRY(launch_particles(c, a));
+  } else {
+    TRY(collide(c, call, c->step, dv_avg, pairlog_cap > 0 ? (long long*)pairlog : nullptr,
+                pairlog_cap));
+    k_source_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->v[c->cur], c->key, c->cstart, t,
+                                                          dv_src);
+    LAUNCH_CHECK(c, "source");
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (pairlog_n) {
     unsigned long long nlog = 0;
@@ -625,8 +788,12 @@ int pic_errors(pic_ctx* c, pic_error_norms* out) {
   double t = (double)c->step * K.dt;
   int nbp = grid_for(K.np), nbn = grid_for(K.nn);
   int s = c->cur;
-  k_err_particles_f64<<<nbp, kBlock, 0, c->stream>>>(K, t, c->x[s], c->v[s], c->id[s], c->epart,
-                                                     c->flags);
+  if (c->precision == PIC_FP64)
+    k_err_particles_f64<<<nbp, kBlock, 0, c->stream>>>(K, t, c->x[s], c->v[s], c->id[s], c->epart,
+                                                       c->flags);
+  else
+    k_err_particles_mixed<<<nbp, kBlock, 0, c->stream>>>(K, t, c->key, c->off[s], c->vf[s], c->id[s],
+                                                         c->epart, c->flags);
   k_err_nodes<<<nbn, kBlock, 0, c->stream>>>(K, t, c->phi, c->npart);
   k_err_final<<<1, kBlock, 0, c->stream>>>(K, c->epart, nbp, c->npart, nbn, c->norms);
   LAUNCH_CHECK(c, "errors");
@@ -684,6 +851,15 @@ int pic_get_state(pic_ctx* c, int item, void* host_dst, int64_t bytes) {
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int s = c->cur;
+  if (c->precision == PIC_MIXED && (item == PIC_STATE_X || item == PIC_STATE_V)) {
+    k_export_mixed<<<grid_for(np), kBlock, 0, c->stream>>>(K, c->key, c->off[s], c->vf[s],
+                                                           item == PIC_STATE_X ? c->U : nullptr,
+                                                           item == PIC_STATE_V ? c->U : nullptr);
+    LAUNCH_CHECK(c, "export");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(host_dst, c->U, need, hipMemcpyDeviceToHost));
+    return check_flags(c);
+  }
   switch (item) {
     case PIC_STATE_X: HIP_TRY(c, hipMemcpy(host_dst, c->x[s], need, hipMemcpyDeviceToHost)); break;
     case PIC_STATE_V: HIP_TRY(c, hipMemcpy(host_dst, c->v[s], need, hipMemcpyDeviceToHost)); break;

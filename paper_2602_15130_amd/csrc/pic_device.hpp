@@ -203,20 +203,34 @@ __device__ inline void vhat_of_t(const SimConst& K, double t, double vh[3], doub
   vd[2] = 0.2 * (1.5 * kPi / K.T) * cospi(1.5 * u) * K.vbar;
 }
 
-// Standard normal quantile: erfcinv estimate refined by one Newton step on erfc.
+// Standard normal quantile.  The root is taken on the lower tail, Phi(-z) =
+// min(xi, 1 - xi) (1 - xi is exact for xi >= 1/2), which keeps the residual
+// well conditioned in both tails; starting guess Abramowitz & Stegun 26.2.23
+// (|error| < 4.5e-4), then Newton steps on 0.5 erfc(-y / sqrt 2) in FP64.
 __device__ inline double normal_quantile(double xi) {
-  double z = -1.4142135623730951 * erfcinv(2.0 * xi);
-  NormalCdf F;
-  double dens;
-  double r = F(z, dens) - xi;
-  if (dens > 0.0) z -= r / dens;
-  return z;
+  const double pp = xi < 0.5 ? xi : 1.0 - xi;
+  const double t = sqrt(-2.0 * log(pp));
+  double y = -(t - (2.515517 + t * (0.802853 + t * 0.010328)) /
+                       (1.0 + t * (1.432788 + t * (0.189269 + t * 0.001308))));
+#pragma unroll 1
+  for (int it = 0; it < 4; ++it) {
+    double f = 0.5 * erfc(-0.7071067811865476 * y) - pp;
+    double dens = 0.3989422804014327 * exp(-0.5 * y * y);
+    double dy = f / dens;
+    y -= dy;
+    if (fabs(dy) <= 1e-16 * fabs(y)) break;
+  }
+  return xi < 0.5 ? y : -y;
 }
 
-// Paper family: a = G^{-1}(xi), time independent (v^M = vhat(t) a).
-__device__ inline double paper_a(double xi) {
-  double a0 = cbrt(2.6586807763582730 * (xi - 0.5));  // 1.5 sqrt(pi)
-  return invert_cdf(PaperGCdf{}, xi, -30.0, 30.0, a0);
+// Paper family: a = G^{-1}(xi), time independent (v^M = vhat(t) a).  The
+// density of eq. fv is even, so G^{-1}(xi) = -G^{-1}(1 - xi): solve on the
+// lower half.
+__device__ __noinline__ double paper_a(double xi) {
+  const double pp = xi < 0.5 ? xi : 1.0 - xi;
+  double a0 = cbrt(2.6586807763582730 * (pp - 0.5));  // 1.5 sqrt(pi)
+  double a = invert_cdf(PaperGCdf{}, pp, -30.0, 0.0, a0);
+  return xi < 0.5 ? a : -a;
 }
 
 // Velocity shape factor per component: v^M(t) = vhat(t) * shape.
@@ -234,16 +248,8 @@ __device__ inline void manufactured_velocity(const SimConst& K, const double a[3
   }
 }
 
-// eq. mms_sol for the positions; `guess` speeds up the paper-family roots.
-__device__ inline void manufactured_position(const SimConst& K, const double xp[3], double t,
+__device__ __noinline__ void paper_position(const SimConst& K, const double xp[3], double t,
                                              const double* guess, double x[3]) {
-  if (K.family == 1) {
-    x[0] = K.L[0] * xp[0];
-    x[1] = K.L[1] * xp[1];
-    CfgZCdf F{K.L[2], K.rho_amp * sinpi(2.0 * x[0] / K.L[0]) * sinpi(2.0 * x[1] / K.L[1])};
-    x[2] = invert_cdf(F, xp[2], 0.0, K.L[2], K.L[2] * xp[2]);
-    return;
-  }
   double e = exp(t / K.T);
   for (int d = 0; d < 3; ++d) {
     PaperPosCdf F{d, K.L[d], e};
@@ -251,8 +257,22 @@ __device__ inline void manufactured_position(const SimConst& K, const double xp[
   }
 }
 
+__device__ __noinline__ void cfg_position(const SimConst& K, const double xp[3], double x[3]) {
+  x[0] = K.L[0] * xp[0];
+  x[1] = K.L[1] * xp[1];
+  CfgZCdf F{K.L[2], K.rho_amp * sinpi(2.0 * x[0] / K.L[0]) * sinpi(2.0 * x[1] / K.L[1])};
+  x[2] = invert_cdf(F, xp[2], 0.0, K.L[2], K.L[2] * xp[2]);
+}
+
+// eq. mms_sol for the positions; `guess` speeds up the paper-family roots.
+__device__ inline void manufactured_position(const SimConst& K, const double xp[3], double t,
+                                             const double* guess, double x[3]) {
+  if (K.family == 1) cfg_position(K, xp, x);
+  else paper_position(K, xp, t, guess, x);
+}
+
 // xdot^M = -(dF/dt)/f at x^M (Sec. 3.2).
-__device__ inline void manufactured_xdot(const SimConst& K, const double xm[3], double t,
+__device__ __noinline__ void manufactured_xdot(const SimConst& K, const double xm[3], double t,
                                          double xd[3]) {
   if (K.family == 1) {
     xd[0] = xd[1] = xd[2] = 0.0;
@@ -315,6 +335,19 @@ __device__ inline void EM(const SimConst& K, const double x[3], double t, double
   E[2] = -a * (2.0 * kPi / K.L[2]) * s[0] * s[1] * c[2];
 }
 
+// Cross-section models known at compile time in the fused kernels.
+enum { kSigHS = 0, kSigMaxwell = 1, kSigPoly = 2 };
+
+template <int SIG>
+__device__ inline double sigma_g_t(const SimConst& K, double g) {
+  if (SIG == kSigHS) return K.sg_coef * g;          // omega = 1/2: sigma constant
+  if (SIG == kSigMaxwell) return K.sg_coef;         // omega = 1: sigma g constant
+  double g2 = g * g, r = K.sigma_n[0];
+  if (K.n_sigma > 1) r += K.sigma_n[1] * g2;
+  if (K.n_sigma > 2) r += K.sigma_n[2] * (g2 * g2);
+  return r;
+}
+
 // sigma(g) g.
 __device__ inline double sigma_g(const SimConst& K, double g) {
   if (K.sigma_model == 1) return K.sg_coef * pow(g, K.sg_pow);
@@ -349,6 +382,11 @@ __device__ inline double hs_kernel(double l) {
   return ((l2 * l2 + 2.0 * l2 - 1.0) * erf(0.7071067811865476 * l) + 2.0 * l * (l2 + 1.0) * phin) / l2;
 }
 
+__device__ inline void poly_source_inl(const SimConst& K, const double u[3], double t,
+                                       double out[3]);
+__device__ __noinline__ void poly_source(const SimConst& K, const double u[3], double t,
+                                         double out[3]);
+
 // eq. vel_change_1c integral (no prefactor) at particle velocity u and time t.
 __device__ inline void source_integral(const SimConst& K, const double u[3], double t,
                                        double out[3]) {
@@ -368,6 +406,12 @@ __device__ inline void source_integral(const SimConst& K, const double u[3], dou
     for (int i = 0; i < 3; ++i) out[i] = -K.sigma_ref * s * s * kk * u[i] / sp;
     return;
   }
+  poly_source(K, u, t, out);
+}
+
+// Polynomial cross section (eq. sigma_ms): sum_n sigma_n f_n (eq. vel_change_3).
+__device__ inline void poly_source_inl(const SimConst& K, const double u[3], double t,
+                                       double out[3]) {
   double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   double f[3][3];
   if (K.family == 0) {
@@ -405,4 +449,32 @@ __device__ inline void source_integral(const SimConst& K, const double u[3], dou
   }
 }
 
+}  // namespace pic
+
+namespace pic {
+__device__ __noinline__ void poly_source(const SimConst& K, const double u[3], double t,
+                                         double out[3]) {
+  poly_source_inl(K, u, t, out);
+}
+
+// Source integral with the cross-section model fixed at compile time.
+template <int SIG>
+__device__ inline void source_integral_t(const SimConst& K, const double u[3], double t,
+                                         double out[3]) {
+  if (SIG == kSigMaxwell) {
+    double c = K.sigma_ref * K.g_ref;
+    for (int i = 0; i < 3; ++i) out[i] = -c * u[i];
+  } else if (SIG == kSigHS) {
+    double sp = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (sp == 0.0) {
+      out[0] = out[1] = out[2] = 0.0;
+      return;
+    }
+    double s = K.vbar;
+    double kk = hs_kernel(sp / s);
+    for (int i = 0; i < 3; ++i) out[i] = -K.sigma_ref * s * s * kk * u[i] / sp;
+  } else {
+    poly_source_inl(K, u, t, out);
+  }
+}
 }  // namespace pic

@@ -10,7 +10,12 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 
 // Flags raised by kernels and read back at the next synchronising call.
-enum { kFlagCgNoConv = 0, kFlagBarrier = 1, kFlagNonFinite = 2, kFlagCount = 4 };
+enum { kFlagCgNoConv = 0, kFlagBarrier = 1, kFlagNonFinite = 2, kFlagCapacity = 3, kFlagCount = 4 };
+// Work bounds that keep every kernel finite on degenerate input (a run-away
+// state collapsing into one cell): candidate pairs per outcome, and the cell
+// size for the in-cell stable rank.  Exceeding them raises kFlagCapacity.
+constexpr int64_t kMaxPairsPerOutcome = int64_t(1) << 22;
+constexpr int kMaxStableCell = 1 << 16;
 // 64-bit counters: accepted collisions, candidate pairs with g > g_max, pair-log records.
 enum { kCntAccepted = 0, kCntGmax = 1, kCntPairLog = 2, kCntCount = 4 };
 
@@ -199,19 +204,33 @@ __device__ inline int stable_rank(const int* tidx, int s, int e, int my) {
   return r;
 }
 
+// Destination of scatter slot j: its stable rank inside its cell, or (for a
+// cell beyond kMaxStableCell, flagged as a capacity error) the slot itself.
+__device__ inline int order_dst(const int* tidx, const int* tkey, const int* cstart, int j,
+                                int* flags) {
+  int c = tkey[j], s = cstart[c], e = cstart[c + 1];
+  if (e - s > kMaxStableCell) {
+    atomicOr(&flags[kFlagCapacity], 1);
+    return j;
+  }
+  return s + stable_rank(tidx, s, e, tidx[j]);
+}
+
 __global__ void __launch_bounds__(kBlock) k_order_f64(const int* tidx, const int* tkey,
                                                       const int* cstart, const double* xs,
-                                                      const double* vs, const int* ids,
-                                                      double* xd, double* vd, int* idd, int* keyd,
-                                                      int n) {
+                                                      const double* vs, const double* as,
+                                                      const int* ids, double* xd, double* vd,
+                                                      double* ad, int* idd, int* keyd, int n,
+                                                      int* flags) {
   int j = blockIdx.x * kBlock + threadIdx.x;
   if (j >= n) return;
-  int c = tkey[j], s = cstart[c], e = cstart[c + 1], my = tidx[j];
-  int dst = s + stable_rank(tidx, s, e, my);
+  int c = tkey[j], my = tidx[j];
+  int dst = order_dst(tidx, tkey, cstart, j, flags);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     xd[(int64_t)d * n + dst] = xs[(int64_t)d * n + my];
     vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
+    ad[(int64_t)d * n + dst] = as[(int64_t)d * n + my];
   }
   idd[dst] = ids[my];
   keyd[dst] = c;
@@ -221,8 +240,8 @@ __global__ void __launch_bounds__(kBlock) k_order_f64(const int* tidx, const int
 // Initial state: xi -> x^M(0), v^M(0) in id order (eq. mms_sol), cell keys and
 // counts for the sort.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_init_f64(SimConst K, double* x, double* v, int* id,
-                                                     int* key, int* slot, int* count) {
+__global__ void __launch_bounds__(kBlock) k_init_f64(SimConst K, double* x, double* v, double* ash,
+                                                     int* id, int* key, int* slot, int* count) {
   int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   bool valid = p < K.np;
   int kk = 0;
@@ -239,6 +258,7 @@ __global__ void __launch_bounds__(kBlock) k_init_f64(SimConst K, double* x, doub
     for (int d = 0; d < 3; ++d) {
       x[d * K.np + p] = xm[d];
       v[d * K.np + p] = vm[d];
+      ash[d * K.np + p] = a[d];  // time-independent velocity shape, v^M = vhat(t) a
     }
     id[p] = (int)p;
     key[p] = kk;
@@ -322,10 +342,18 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(SimConst K, double* b, cons
 
 // ---------------------------------------------------------------------------
 // Poisson CG: one cooperative persistent kernel.  A = -L_h (periodic 7-point),
-// A phi = -b.  Two grid barriers per iteration: the search direction update
-// p = r + beta p is folded into the next stencil sweep (ping-pong buffers).
-// All dot products are reduced in a fixed order, identically by every block.
+// A phi = -b.  The search direction update p = r + beta p is folded into the
+// next stencil sweep (ping-pong buffers), so an iteration has two grid-wide
+// reductions.  Each reduction is also the grid barrier: every block publishes
+// its partial sums and then a flag (one release store); block 0 waits for all
+// flags, sums the partials in block order and publishes the result and a
+// release word; every block waits on that word.  Waits poll with relaxed
+// loads and take one acquire fence at the end; they are bounded and raise
+// kFlagBarrier on timeout so every wave always leaves the kernel.
 // ---------------------------------------------------------------------------
+constexpr int kFlagStride = 32;  // 128 bytes between per-block flags
+constexpr int kMaxRed = 3;       // values per reduction
+
 struct CgArgs {
   const double* b;
   double* x;
@@ -333,9 +361,10 @@ struct CgArgs {
   double* p0;
   double* p1;
   double* q;
-  double* partA;
-  double* partB;
-  unsigned* bar;
+  double* part;       // [grid][kMaxRed]
+  double* result;     // [kMaxRed]
+  unsigned* arrive;   // [grid * kFlagStride], zero before launch
+  unsigned* release;  // [1], zero before launch
   int* flags;
   int* iters_out;
   double* relres_out;
@@ -343,43 +372,59 @@ struct CgArgs {
   int max_iter;
 };
 
-// Grid barrier with a bounded wait: returns false (and raises kFlagBarrier) if
-// it times out, so every wave always reaches the end of the kernel.
-__device__ inline bool grid_sync(unsigned* bar, int* flags) {
-  __shared__ int ok;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    int good = 1;
-    if (prev == gridDim.x - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1u << 23)) {
-          good = 0;
-          atomicOr(&flags[kFlagBarrier], 1);
-          break;
-        }
-      }
+__device__ inline bool spin_until(const unsigned* addr, unsigned want, int* flags) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > (1u << 24)) {
+      atomicOr(&flags[kFlagBarrier], 1);
+      return false;
     }
-    __threadfence();
-    if (__hip_atomic_load(&flags[kFlagBarrier], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) good = 0;
-    ok = good;
+    if ((spins & 1023u) == 0 &&
+        __hip_atomic_load(&flags[kFlagBarrier], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return false;
   }
-  __syncthreads();
-  return ok != 0;
+  return true;
 }
 
-// Every block sums the per-block partials in the same fixed order.
-__device__ inline double grid_allreduce(const double* part, double* sh) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock) acc += part[i];
-  return block_sum(acc, sh);
+// Grid-wide sum of nv block values; every thread of every block gets the same
+// nv results.  `gen` increases by one per call within a launch.
+__device__ inline bool grid_sum(const CgArgs& a, double* vals, int nv, unsigned gen, double* sh) {
+  __shared__ int ok;
+  __shared__ double res[kMaxRed];
+  double tot[kMaxRed];
+  for (int i = 0; i < nv; ++i) tot[i] = block_sum(vals[i], sh);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < nv; ++i) a.part[blockIdx.x * kMaxRed + i] = tot[i];
+    __hip_atomic_store(&a.arrive[blockIdx.x * kFlagStride], gen, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    ok = 1;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    int good = 1;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+      if (!spin_until(&a.arrive[b * kFlagStride], gen, a.flags)) good = 0;
+    if (!good) ok = 0;
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int i = 0; i < nv; ++i) {
+      double acc = 0.0;
+      for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) acc += a.part[b * kMaxRed + i];
+      double s = block_sum(acc, sh);
+      if (threadIdx.x == 0) a.result[i] = s;
+    }
+    if (threadIdx.x == 0)
+      __hip_atomic_store(a.release, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x == 0) {
+    if (!spin_until(a.release, gen, a.flags)) ok = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int i = 0; i < nv; ++i) res[i] = a.result[i];
+  }
+  __syncthreads();
+  for (int i = 0; i < nv; ++i) vals[i] = res[i];
+  return ok != 0;
 }
 
 // (-L f)(n) for f given by a callable.
@@ -396,8 +441,9 @@ __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
   __shared__ double sh[kWaves];
   const int gsize = gridDim.x * kBlock;
   const int g0 = blockIdx.x * kBlock + threadIdx.x;
+  unsigned gen = 0;
   // r = -b - A x, p = r
-  double s_rr = 0.0, s_bb = 0.0;
+  double v2[kMaxRed] = {0.0, 0.0, 0.0};
   for (int n = g0; n < K.nn; n += gsize) {
     int i, j, k;
     node_coords(K, n, i, j, k);
@@ -405,19 +451,12 @@ __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
     double rv = -a.b[n] - ax;
     a.r[n] = rv;
     a.p0[n] = rv;
-    s_rr += rv * rv;
-    s_bb += a.b[n] * a.b[n];
+    v2[0] += rv * rv;
+    v2[1] += a.b[n] * a.b[n];
   }
-  double t1 = block_sum(s_rr, sh);
-  double t2 = block_sum(s_bb, sh);
-  if (threadIdx.x == 0) {
-    a.partA[blockIdx.x] = t1;
-    a.partB[blockIdx.x] = t2;
-  }
-  if (!grid_sync(a.bar, a.flags)) return;
-  double rr = grid_allreduce(a.partA, sh);
-  double bnorm = sqrt(grid_allreduce(a.partB, sh));
-  if (!grid_sync(a.bar, a.flags)) return;  // partA/partB are reused below
+  if (!grid_sum(a, v2, 2, ++gen, sh)) return;
+  double rr = v2[0];
+  double bnorm = sqrt(v2[1]);
   int it = 0;
   int cur = 0;
   double beta = 0.0;
@@ -433,14 +472,14 @@ __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
       }
       const double* pc = cur ? a.p1 : a.p0;
       double* pn = cur ? a.p0 : a.p1;
-      double s_pq = 0.0;
+      double s_pq[kMaxRed] = {0.0, 0.0, 0.0};
       if (it == 0) {
         for (int n = g0; n < K.nn; n += gsize) {
           int i, j, k;
           node_coords(K, n, i, j, k);
           double qv = neg_lap(K, i, j, k, [&](int m) { return pc[m]; });
           a.q[n] = qv;
-          s_pq += pc[n] * qv;
+          s_pq[0] += pc[n] * qv;
         }
       } else {
         for (int n = g0; n < K.nn; n += gsize) {
@@ -451,39 +490,31 @@ __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
           pn[n] = pv;
           double qv = neg_lap(K, i, j, k, pnew);
           a.q[n] = qv;
-          s_pq += pv * qv;
+          s_pq[0] += pv * qv;
         }
         cur ^= 1;
       }
       const double* p = cur ? a.p1 : a.p0;
-      double tp = block_sum(s_pq, sh);
-      if (threadIdx.x == 0) a.partA[blockIdx.x] = tp;
-      if (!grid_sync(a.bar, a.flags)) return;
-      double alpha = rr / grid_allreduce(a.partA, sh);
-      double s_r = 0.0;
+      if (!grid_sum(a, s_pq, 1, ++gen, sh)) return;
+      double alpha = rr / s_pq[0];
+      double s_r[kMaxRed] = {0.0, 0.0, 0.0};
       for (int n = g0; n < K.nn; n += gsize) {
         a.x[n] += alpha * p[n];
         double rv = a.r[n] - alpha * a.q[n];
         a.r[n] = rv;
-        s_r += rv * rv;
+        s_r[0] += rv * rv;
       }
-      double tr = block_sum(s_r, sh);
-      if (threadIdx.x == 0) a.partB[blockIdx.x] = tr;
-      if (!grid_sync(a.bar, a.flags)) return;
-      double rr_new = grid_allreduce(a.partB, sh);
-      beta = rr_new / rr;
-      rr = rr_new;
+      if (!grid_sum(a, s_r, 1, ++gen, sh)) return;
+      beta = s_r[0] / rr;
+      rr = s_r[0];
       ++it;
     }
   }
   // zero-mean projection (Sec. 2)
-  double s_x = 0.0;
-  for (int n = g0; n < K.nn; n += gsize) s_x += a.x[n];
-  double tx = block_sum(s_x, sh);
-  if (!grid_sync(a.bar, a.flags)) return;  // everyone is past the last partA read
-  if (threadIdx.x == 0) a.partA[blockIdx.x] = tx;
-  if (!grid_sync(a.bar, a.flags)) return;
-  double mean = grid_allreduce(a.partA, sh) / (double)K.nn;
+  double s_x[kMaxRed] = {0.0, 0.0, 0.0};
+  for (int n = g0; n < K.nn; n += gsize) s_x[0] += a.x[n];
+  if (!grid_sum(a, s_x, 1, ++gen, sh)) return;
+  double mean = s_x[0] / (double)K.nn;
   for (int n = g0; n < K.nn; n += gsize) a.x[n] -= mean;
   if (g0 == 0) {
     *a.iters_out = it;
@@ -546,7 +577,7 @@ __global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, in
                                                         const double* v, const int* cstart,
                                                         double* D, double* u,
                                                         long long* pairlog, int64_t cap,
-                                                        unsigned long long* counters) {
+                                                        unsigned long long* counters, int* flags) {
   int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= K.nn) return;
   const int64_t NP = K.np;
@@ -558,7 +589,12 @@ __global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, in
   bool touched = false;
   for (int k = 0; k < K.navg; ++k) {
     U64x4 w0 = stream_block(K, (uint64_t)c, (uint64_t)step, kTagColl, (uint64_t)call, (uint64_t)k, 0);
-    int64_t npairs = (int64_t)floor((double)n * (double)(n - 1) * K.pmax / 2.0 + unif(w0.w[0]));
+    double xpairs = (double)n * (double)(n - 1) * K.pmax / 2.0 + unif(w0.w[0]);
+    if (!(xpairs < (double)kMaxPairsPerOutcome)) {
+      atomicOr(&flags[kFlagCapacity], 1);
+      continue;
+    }
+    int64_t npairs = (int64_t)floor(xpairs);
     if (npairs <= 0) continue;
     for (int j = 0; j < n; ++j)
       for (int d = 0; d < 3; ++d) u[d * NP + s + j] = v[d * NP + s + j];
@@ -626,7 +662,7 @@ __global__ void __launch_bounds__(kBlock) k_source_f64(SimConst K, const double*
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_kick_f64(SimConst K, double t, double t_from,
                                                      double t_to, double t_src, const double* x,
-                                                     double* v,
+                                                     double* v, const double* ash,
                                                      const int* id, const int* key,
                                                      const int* cstart, const double* E,
                                                      const double* D) {
@@ -651,9 +687,7 @@ __global__ void __launch_bounds__(kBlock) k_kick_f64(SimConst K, double t, doubl
   EM(K, xp, t, em);
   double h[3] = {0.0, 0.0, 0.0};
   if (K.family == 0) {
-    double xv[3], a[3], va[3], vb[3], da[3], db[3];
-    velocity_uniforms(K, id[i], xv);
-    velocity_shape(K, xv, a);
+    double a[3] = {ash[i], ash[NP + i], ash[2 * NP + i]}, va[3], vb[3], da[3], db[3];
     if (K.isolate) {
       manufactured_velocity(K, a, t_from, va, da);
       manufactured_velocity(K, a, t_to, vb, db);
@@ -681,8 +715,9 @@ __global__ void __launch_bounds__(kBlock) k_kick_f64(SimConst K, double t, doubl
 // Drift of eq. velocity_verlet with the manufactured term, periodic wrap, new
 // cell key and its count for the next sort.
 __global__ void __launch_bounds__(kBlock) k_drift_f64(SimConst K, double t0, double th, double t1,
-                                                      double* x, const double* v, const int* id,
-                                                      int* key, int* slot, int* count) {
+                                                      double* x, const double* v,
+                                                      const double* ash, const int* id, int* key,
+                                                      int* slot, int* count, int* flags) {
   int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   bool valid = i < K.np;
   int kk = 0;
@@ -690,9 +725,7 @@ __global__ void __launch_bounds__(kBlock) k_drift_f64(SimConst K, double t0, dou
     const int64_t NP = K.np;
     double xp[3] = {x[i], x[NP + i], x[2 * NP + i]};
     int pid = id[i];
-    double xv[3], a[3], vm[3], vdm[3], h[3] = {0.0, 0.0, 0.0};
-    velocity_uniforms(K, pid, xv);
-    velocity_shape(K, xv, a);
+    double a[3] = {ash[i], ash[NP + i], ash[2 * NP + i]}, vm[3], vdm[3], h[3] = {0.0, 0.0, 0.0};
     manufactured_velocity(K, a, th, vm, vdm);
     if (K.family == 0) {
       double xq[3];
@@ -713,6 +746,11 @@ __global__ void __launch_bounds__(kBlock) k_drift_f64(SimConst K, double t0, dou
       double xn = xp[d] + K.dt * (v[d * NP + i] - vm[d]) + h[d];
       if (xn < 0.0) xn += K.L[d];
       if (xn >= K.L[d]) xn -= K.L[d];
+      if (!(xn >= 0.0 && xn < K.L[d])) {  // non-finite or more than a box length
+        atomicOr(&flags[kFlagNonFinite], 1);
+        xn = isfinite(xn) ? xn - floor(xn / K.L[d]) * K.L[d] : 0.0;
+        if (!(xn >= 0.0 && xn < K.L[d])) xn = 0.0;
+      }
       xp[d] = xn;
       x[d * NP + i] = xn;
     }

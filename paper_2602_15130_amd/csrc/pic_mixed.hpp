@@ -1,0 +1,414 @@
+// Mixed-precision form of the step (configuration family): particle positions
+// as a cell index plus an FP32 offset in cell units, FP32 velocities, FP32
+// gather / kick / drift / collisions, per-cell FP32 deposition sums with
+// Neumaier compensation.  The inverse-CDF roots, N_pairs, the Poisson CG and
+// the error norms stay FP64.
+#pragma once
+
+#include "pic_particle.hpp"
+
+namespace pic {
+
+constexpr float kOneBelow = 0x1.fffffep-1f;  // largest float below 1
+
+// Per-launch FP32 constants of the mixed pass.
+struct MixConst {
+  float dt, dtqm;          // dt and dt q/m
+  float inv_h[3];          // 1 / h per dimension (offsets are in cell units)
+  float inv_n[3];          // 1 / ncell per dimension
+  float emA[3], emB[3];    // phibar e^{t/(2T)} 2 pi / L_d at the kick times of calls A and B
+  float vbar;
+  float src_w;             // w dt / (2 dV): source prefactor per (N - 1)
+  float sigma_ref;
+};
+
+// Initial state (eq. mms_sol): FP64 roots, then cell + FP32 offset.  An offset
+// that would round up to 1 is kept just below it, so the cell is the one the
+// FP64 position falls in.
+__global__ void __launch_bounds__(kBlock) k_init_mixed(SimConst K, float* off, float* vf, float* ash,
+                                                       int* id, int* key, int* slot, int* count) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  bool valid = p < K.np;
+  int kk = 0;
+  if (valid) {
+    double xi[6], xm[3], a[3];
+    init_uniforms(K, p, xi);
+    manufactured_position(K, xi, 0.0, nullptr, xm);
+    velocity_shape(K, xi + 3, a);
+    int c[3];
+    double o[3];
+    locate(K, xm, c, o);
+    kk = lin(K, c[0], c[1], c[2]);
+    for (int d = 0; d < 3; ++d) {
+      off[d * K.np + p] = fminf((float)o[d], kOneBelow);
+      vf[d * K.np + p] = (float)(K.vbar * a[d]);
+      ash[d * K.np + p] = (float)a[d];
+    }
+    id[p] = (int)p;
+    key[p] = kk;
+  }
+  int s = wave_aggregated_slot(count, kk, valid);
+  if (valid) slot[p] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_order_mixed(const int* tidx, const int* tkey,
+                                                        const int* cstart, const float* os,
+                                                        const float* vs, const float* as,
+                                                        const int* ids, float* od, float* vd,
+                                                        float* ad, int* idd, int* keyd, int n,
+                                                        int* flags) {
+  int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  int c = tkey[j], my = tidx[j];
+  int dst = order_dst(tidx, tkey, cstart, j, flags);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    od[(int64_t)d * n + dst] = os[(int64_t)d * n + my];
+    vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
+    ad[(int64_t)d * n + dst] = as[(int64_t)d * n + my];
+  }
+  idd[dst] = ids[my];
+  keyd[dst] = c;
+}
+
+// Neumaier-compensated accumulation: s + c carries the sum to about FP64 accuracy.
+__device__ inline void neumaier_add(float& s, float& c, float x) {
+  float t = s + x;
+  if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+// Cloud-in-cell cell moments with FP32 weights (the offsets are the weights),
+// summed in cell-sorted order with compensation; hi and lo parts stored.
+__global__ void __launch_bounds__(kBlock) k_deposit_moments_mixed(SimConst K, const float* off,
+                                                                  const int* cstart, float* mom) {
+  int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= K.nn) return;
+  float s[8], e[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s[k] = e[k] = 0.0f;
+  for (int j = cstart[c]; j < cstart[c + 1]; ++j) {
+    float ox = off[j], oy = off[K.np + j], oz = off[2 * K.np + j];
+    float wx[2] = {1.0f - ox, ox}, wy[2] = {1.0f - oy, oy}, wz[2] = {1.0f - oz, oz};
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx)
+          neumaier_add(s[cz * 4 + cy * 2 + cx], e[cz * 4 + cy * 2 + cx], wx[cx] * wy[cy] * wz[cz]);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    mom[(int64_t)k * K.nn + c] = s[k];
+    mom[(int64_t)(8 + k) * K.nn + c] = e[k];
+  }
+}
+
+// Node charge from the compensated FP32 cell moments (summed in FP64) and the
+// right-hand side of eq. poisson_mms; block partial sums of b.
+__global__ void __launch_bounds__(kBlock) k_node_rhs_mixed(SimConst K, const float* mom, double t,
+                                                           double* rho, double* b, double* part) {
+  __shared__ double sh[kWaves];
+  int n = blockIdx.x * kBlock + threadIdx.x;
+  double bv = 0.0;
+  if (n < K.nn) {
+    int i, j, k;
+    node_coords(K, n, i, j, k);
+    double s = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          int kk = cz * 4 + cy * 2 + cx;
+          int cell = lin(K, i - cx, j - cy, k - cz);
+          s += (double)mom[(int64_t)kk * K.nn + cell] + (double)mom[(int64_t)(8 + kk) * K.nn + cell];
+        }
+    double r = K.rho_scale * s;
+    rho[n] = r;
+    double xn[3] = {i * K.h[0], j * K.h[1], k * K.h[2]};
+    bv = lap_phiM(K, xn, t);
+    if (K.p2f != 0.0) bv += -(r - K.q * number_density(K, xn, t)) / K.eps0;
+    b[n] = bv;
+  }
+  double tot = block_sum(bv, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Hard-sphere kernel K(l) in FP32 (series below 0.5, closed form above).
+__device__ inline float hs_kernel_f(float l) {
+  if (l < 0.5f) {
+    float bm2 = 0.0f, am2 = 0.0f, bm1 = 1.0f, am1 = 1.0f, sum = 0.0f, l2 = l * l, lp = l;
+    for (int j = 1; j < 10; ++j) {
+      float bj = bm1 * (-0.5f) / (float)j, aj = bj / (2.0f * j + 1.0f);
+      sum += (am2 + 2.0f * am1 - aj + bm1 + bj) * lp;
+      am2 = am1; bm2 = bm1; am1 = aj; bm1 = bj;
+      lp *= l2;
+    }
+    (void)bm2;
+    return 0.7978845608f * sum;
+  }
+  float l2 = l * l;
+  float phin = 0.3989422804f * expf(-0.5f * l2);
+  return ((l2 * l2 + 2.0f * l2 - 1.0f) * erff(0.7071067812f * l) + 2.0f * l * (l2 + 1.0f) * phin) / l2;
+}
+
+// eq. vel_change_1c integral in FP32 for the configuration family.
+template <int SIG>
+__device__ inline void source_integral_f(const SimConst& K, const MixConst& M, const float u[3],
+                                         float out[3]) {
+  if (SIG == kSigMaxwell) {
+    float c = (float)(K.sigma_ref * K.g_ref);
+    for (int i = 0; i < 3; ++i) out[i] = -c * u[i];
+  } else if (SIG == kSigHS) {
+    float sp = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (sp == 0.0f) {
+      out[0] = out[1] = out[2] = 0.0f;
+      return;
+    }
+    float s = M.vbar;
+    float kk = hs_kernel_f(sp / s);
+    for (int i = 0; i < 3; ++i) out[i] = -M.sigma_ref * s * s * kk * u[i] / sp;
+  } else {
+    // polynomial cross section with Gaussian moments m2 = s^2, m4 = 3 s^4
+    float m2 = M.vbar * M.vbar, m4 = 3.0f * m2 * m2;
+    float f[3][3];
+    for (int i = 0; i < 3; ++i) {
+      int j = (i + 1) % 3, k = (i + 2) % 3;
+      float ui2 = u[i] * u[i], uj2 = u[j] * u[j], uk2 = u[k] * u[k];
+      float qj = m2 + uj2, qk = m2 + uk2, s1 = qj + qk;
+      float s2 = (m4 + 6.0f * uj2 * m2 + uj2 * uj2) + (m4 + 6.0f * uk2 * m2 + uk2 * uk2);
+      f[0][i] = -u[i];
+      f[1][i] = -u[i] * (3.0f * m2 + ui2 + s1);
+      f[2][i] = -u[i] * (5.0f * m4 + 10.0f * ui2 * m2 + ui2 * ui2 + s2 + 2.0f * qj * qk +
+                         2.0f * (3.0f * m2 + ui2) * s1);
+    }
+    for (int i = 0; i < 3; ++i) {
+      float r = 0.0f;
+      for (int n = 0; n < K.n_sigma; ++n) r += (float)K.sigma_n[n] * f[n][i];
+      out[i] = r;
+    }
+  }
+}
+
+// CIC gather of the FP32 nodal field (AoS, 3 floats per node); the offsets are
+// the interpolation weights.
+__device__ inline void gather_mixed(const SimConst& K, const float* E32, int ci, int cj, int ck,
+                                    const float o[3], float ep[3]) {
+  ep[0] = ep[1] = ep[2] = 0.0f;
+  float wx[2] = {1.0f - o[0], o[0]}, wy[2] = {1.0f - o[1], o[1]}, wz[2] = {1.0f - o[2], o[2]};
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        const float* e = E32 + 3 * (int64_t)lin(K, ci + cx, cj + cy, ck + cz);
+        float wgt = wx[cx] * wy[cy] * wz[cz];
+        ep[0] += wgt * e[0];
+        ep[1] += wgt * e[1];
+        ep[2] += wgt * e[2];
+      }
+}
+
+// E^M at the particle in FP32: position fraction (i + o) / n of the box.
+__device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const float o[3],
+                                const float amp[3], float em[3]) {
+  const float shift[3] = {1.0f / 7.0f, 1.0f / 5.0f, 1.0f / 3.0f};
+  const int cc[3] = {ci, cj, ck};
+  float s[3], c[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    float arg = 2.0f * (((float)cc[d] + o[d]) * M.inv_n[d] - shift[d]);
+    s[d] = sinpif(arg);
+    c[d] = cospif(arg);
+  }
+  em[0] = -amp[0] * c[0] * s[1] * s[2];
+  em[1] = -amp[1] * s[0] * c[1] * s[2];
+  em[2] = -amp[2] * s[0] * s[1] * c[2];
+}
+
+// The mixed-form fused pass (configuration family), same phases as the FP64 one.
+template <int SIG>
+__global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
+                                                            float* off, float* vf, const float* ash,
+                                                            const float* E32) {
+  __shared__ float lv0[3 * kLdsSlots], lu[3 * kLdsSlots], lD[3 * kLdsSlots];
+  __shared__ int evt[kMaxEvents];
+  __shared__ int sh_i[6];
+  const int tid = threadIdx.x;
+  const int NP = (int)K.np;
+  if (tid == 0) {
+    int c0 = min(a.tile_c0[blockIdx.x], K.nn);
+    int c1 = min(max(a.tile_c0[blockIdx.x + 1], c0), K.nn);
+    sh_i[0] = c0;
+    sh_i[1] = c1;
+    sh_i[2] = a.cstart[c0];
+    sh_i[3] = a.cstart[c1];
+  }
+  __syncthreads();
+  const int c0 = sh_i[0], ncells = sh_i[1] - sh_i[0], s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
+  if (ns <= 0) return;
+  const bool lds = ns <= kLdsSlots;
+  const int st = lds ? kLdsSlots : NP;
+  float* v0 = lds ? lv0 : (float*)a.gv0 + s0;
+  float* u = lds ? lu : (float*)a.gu + s0;
+  float* D = lds ? lD : (float*)a.gD + s0;
+
+  for (int j = tid; j < ns; j += kBlock)
+    for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + s0 + j];
+  __syncthreads();
+
+  auto kick = [&](int j, const float amp[3], bool coll_on) {
+    int p = s0 + j;
+    int c = a.key[p];
+    int ci = c % K.nc[0], cj = (c / K.nc[0]) % K.nc[1], ck = c / (K.nc[0] * K.nc[1]);
+    float o[3] = {off[p], off[NP + p], off[2 * NP + p]};
+    float ep[3], em[3];
+    gather_mixed(K, E32, ci, cj, ck, o, ep);
+    EM_mixed(M, ci, cj, ck, o, amp, em);
+    float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
+    float coll[3] = {0.0f, 0.0f, 0.0f};
+    if (coll_on) {
+      int n = a.cstart[c + 1] - a.cstart[c];
+      float I[3] = {0.0f, 0.0f, 0.0f};
+      float coef = M.src_w * (float)(n - 1);
+      if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
+      for (int d = 0; d < 3; ++d) coll[d] = D[d * st + j] - ((n >= 2) ? coef * I[d] : 0.0f);
+    }
+    for (int d = 0; d < 3; ++d) {
+      float acc = M.dtqm * (ep[d] - em[d]);
+      vp[d] = vp[d] + 0.5f * (acc + coll[d]);
+      v0[d * st + j] = vp[d];
+    }
+  };
+
+  if (a.mode & kCollideOnly) {
+    tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4],
+                             &sh_i[5]);
+    for (int j = tid; j < ns; j += kBlock) {
+      int c = a.key[s0 + j];
+      int n = a.cstart[c + 1] - a.cstart[c];
+      float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
+      float coef = M.src_w * (float)(n - 1);
+      if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
+      for (int d = 0; d < 3; ++d) {
+        a.Dout[(int64_t)d * NP + s0 + j] = (double)D[d * st + j];
+        a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? (double)(coef * I[d]) : 0.0;
+      }
+    }
+    return;
+  }
+
+  if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
+    if (K.collisions)
+      tile_collide<SIG, float>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, st, evt,
+                               &sh_i[4], &sh_i[5]);
+    for (int j = tid; j < ns; j += kBlock) kick(j, M.emB, K.collisions != 0);
+    __syncthreads();
+    if (!(a.mode & kDoA)) {
+      for (int j = tid; j < ns; j += kBlock)
+        for (int d = 0; d < 3; ++d) vf[(int64_t)d * NP + s0 + j] = v0[d * st + j];
+      return;
+    }
+  }
+
+  // call A at t^{na}, first half kick, drift to t^{na+1}
+  if (K.collisions)
+    tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4],
+                             &sh_i[5]);
+  for (int base = 0; base < ns; base += kBlock) {
+    int j = base + tid;
+    bool valid = j < ns;
+    int kk = 0;
+    if (valid) {
+      int p = s0 + j;
+      kick(j, M.emA, K.collisions != 0);
+      int c = a.key[p];
+      int cc[3] = {c % K.nc[0], (c / K.nc[0]) % K.nc[1], c / (K.nc[0] * K.nc[1])};
+      for (int d = 0; d < 3; ++d) {
+        // x += dt (v - v^M) in cell units; v^M = vbar a (time independent)
+        float vm = M.vbar * ash[(int64_t)d * NP + p];
+        float o = off[(int64_t)d * NP + p] + M.dt * (v0[d * st + j] - vm) * M.inv_h[d];
+        float fl = floorf(o);
+        o -= fl;
+        int shift = (int)fl;
+        if (o >= 1.0f) {  // a tiny negative offset rounds up to 1 after adding 1
+          o -= 1.0f;
+          shift += 1;
+        }
+        if (!(o >= 0.0f && o < 1.0f)) {  // non-finite
+          atomicOr(&a.flags[kFlagNonFinite], 1);
+          o = 0.0f;
+          shift = 0;
+        }
+        int nd = K.nc[d];
+        int ni = cc[d] + (shift % nd);
+        ni = ni < 0 ? ni + nd : (ni >= nd ? ni - nd : ni);
+        cc[d] = ni;
+        off[(int64_t)d * NP + p] = o;
+        vf[(int64_t)d * NP + p] = v0[d * st + j];
+      }
+      kk = (cc[2] * K.nc[1] + cc[1]) * K.nc[0] + cc[0];
+      a.key[p] = kk;
+    }
+    int sl = wave_aggregated_slot(a.count, kk, valid);
+    if (valid) a.slot[s0 + j] = sl;
+  }
+}
+
+// Positions and velocities exported as FP64 (component-major).
+__global__ void __launch_bounds__(kBlock) k_export_mixed(SimConst K, const int* key, const float* off,
+                                                         const float* vf, double* x, double* v) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (p >= K.np) return;
+  int c = key[p];
+  int cc[3] = {c % K.nc[0], (c / K.nc[0]) % K.nc[1], c / (K.nc[0] * K.nc[1])};
+  for (int d = 0; d < 3; ++d) {
+    if (x) x[d * K.np + p] = ((double)cc[d] + (double)off[d * K.np + p]) * K.h[d];
+    if (v) v[d * K.np + p] = (double)vf[d * K.np + p];
+  }
+}
+
+// Error norms of the mixed state: positions rebuilt in FP64, manufactured
+// values from FP64 roots, FP64 reductions.
+__global__ void __launch_bounds__(kBlock) k_err_particles_mixed(SimConst K, double t, const int* key,
+                                                                const float* off, const float* vf,
+                                                                const int* id, double* part,
+                                                                int* flags) {
+  __shared__ double sh[kWaves];
+  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  double e[6] = {0, 0, 0, 0, 0, 0};
+  if (i < K.np) {
+    double xi[6], xm[3], a[3];
+    init_uniforms(K, id[i], xi);
+    int c = key[i];
+    int cc[3] = {c % K.nc[0], (c / K.nc[0]) % K.nc[1], c / (K.nc[0] * K.nc[1])};
+    double xp[3];
+    for (int d = 0; d < 3; ++d) xp[d] = ((double)cc[d] + (double)off[d * K.np + i]) * K.h[d];
+    manufactured_position(K, xi, t, xp, xm);
+    velocity_shape(K, xi + 3, a);
+    for (int d = 0; d < 3; ++d) {
+      double ex = xp[d] - xm[d];
+      if (ex >= 0.5 * K.L[d]) ex -= K.L[d];
+      if (ex < -0.5 * K.L[d]) ex += K.L[d];
+      e[d] = ex;
+      e[3 + d] = (double)vf[d * K.np + i] - K.vbar * a[d];
+    }
+    for (int a2 = 0; a2 < 6; ++a2)
+      if (!isfinite(e[a2])) atomicOr(&flags[kFlagNonFinite], 1);
+  }
+  for (int a2 = 0; a2 < 6; ++a2) {
+    double s2 = block_sum(e[a2] * e[a2], sh);
+    double mx = block_max(fabs(e[a2]), sh);
+    if (threadIdx.x == 0) {
+      part[blockIdx.x * 14 + a2] = s2;
+      part[blockIdx.x * 14 + 7 + a2] = mx;
+    }
+  }
+}
+
+}  // namespace pic

@@ -1,0 +1,430 @@
+// Fused particle pass: for a cell-aligned tile of sorted particles, in one
+// kernel, the collision call B of step nb and the second half kick, then the
+// collision call A of step na, the first half kick and the drift of step na
+// (eq. velocity_verlet with eq. avg_outcome and the manufactured sources).
+// Either half can be switched off, and a collide-only mode writes <dv> and
+// <dv^M> without touching the state.
+//
+// Tiles: tile t holds the cells whose first particle lies in [t B, (t+1) B)
+// of the sorted order, i.e. cells [lower_bound(cstart, tB), lower_bound(cstart,
+// (t+1)B)), so every cell is processed whole by one workgroup.  A tile holds
+// fewer than B + (largest cell) particles; per-particle working arrays live in
+// LDS when they fit and in global scratch otherwise.
+//
+// Collisions in a tile: (1) one lane per (cell, outcome) draws N_pairs
+// (Algorithm 1) and records the few lanes that have candidate pairs; (2) one
+// thread per cell runs those outcomes in increasing outcome order on a private
+// copy of its cell's velocities and accumulates <dv> in that order, exactly as
+// eq. avg_outcome sums them.  If the event list of a tile overflows, step (2)
+// redraws N_pairs for every outcome itself.
+#pragma once
+
+#include "pic_kernels.hpp"
+
+namespace pic {
+
+constexpr int kTileB = 256;       // particle slots that start cells in one tile
+constexpr int kLdsSlots = 384;    // LDS-resident slots per tile
+constexpr int kMaxEvents = 512;   // (cell, outcome) lanes with pairs per tile
+
+enum { kDoB = 1, kDoA = 2, kCollideOnly = 4 };
+
+struct PartArgs {
+  double* x;            // [3][np] positions, updated by the drift
+  double* v;            // [3][np] velocities
+  const double* ash;    // [3][np] velocity shape: v^M(t) = vhat(t) a (time independent)
+  const int* id;
+  int* key;             // cell of each particle (in), new cell after the drift (out)
+  int* slot;            // arrival slot for the next sort
+  int* count;           // per-cell counts for the next sort (zeroed by the caller)
+  const int* cstart;
+  const int* tile_c0;   // first cell of each tile, [ntiles + 1]
+  const double* E;      // nodal field [3][nn]
+  double* gv0;          // global fallback scratch [3][np]
+  double* gu;           // global fallback scratch [3][np]
+  double* gD;           // global fallback scratch [3][np]
+  double* Dout;         // collide-only outputs [3][np]
+  double* Sout;
+  long long* pairlog;
+  int64_t cap;
+  unsigned long long* counters;
+  int* flags;
+  int mode;
+  int64_t nb, na;       // step index of call B (second half) and of call A (first half)
+  int callB, callA;     // random-stream call tags (collide-only mode uses callA)
+  double tB;            // collide-only: time of the source
+};
+
+// First cell of every tile: tile_c0[t] = min{c : cstart[c] >= t B}.  For c >= 1
+// that is c exactly when cstart[c-1] < t B <= cstart[c], so each cell marks the
+// tiles whose boundary falls in its range; tile_c0 is filled with ncells first
+// and tile 0 starts at cell 0.
+__global__ void __launch_bounds__(kBlock) k_tile_bounds(const int* cstart, int nn, int* tile_c0,
+                                                        int ntiles) {
+  int c = blockIdx.x * kBlock + threadIdx.x + 1;
+  if (c > nn) return;
+  int lo = cstart[c - 1], hi = cstart[c];
+  for (int t = lo / kTileB + 1; t * kTileB <= hi && t <= ntiles; ++t) tile_c0[t] = c;
+  if (c == 1) tile_c0[0] = 0;
+}
+
+__device__ inline int lower_bound_i(const int* a, int n, int key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Arithmetic of the collision step in the working precision R: FP64 in the
+// FP64 form, FP32 in the mixed form (uniforms from the top 24 bits of the same
+// words, so both forms draw from one stream).
+template <class R> __device__ inline R unif_r(uint64_t w);
+template <> __device__ inline double unif_r<double>(uint64_t w) { return unif(w); }
+template <> __device__ inline float unif_r<float>(uint64_t w) { return unif32(w); }
+
+template <int SIG, class R>
+__device__ inline R sigma_g_r(const SimConst& K, R g) {
+  if (SIG == kSigHS) return (R)K.sg_coef * g;
+  if (SIG == kSigMaxwell) return (R)K.sg_coef;
+  R g2 = g * g, r = (R)K.sigma_n[0];
+  if (K.n_sigma > 1) r += (R)K.sigma_n[1] * g2;
+  if (K.n_sigma > 2) r += (R)K.sigma_n[2] * (g2 * g2);
+  return r;
+}
+
+// One outcome of Algorithm 1 on the private copy u (cell-local SoA with stride
+// `st`) of one cell with n particles.
+template <int SIG, class R>
+__device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, int call, int k,
+                                   int64_t npairs, int n, R* u, int st, long long* pairlog,
+                                   int64_t cap, unsigned long long* counters,
+                                   unsigned long long& acc, unsigned long long& gmx) {
+  const R sgmax = (R)K.sgmax, gmax = (R)K.g_max;
+  for (int64_t m = 0; m < npairs; ++m) {
+    U64x4 wa = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call,
+                            (uint64_t)k, (uint64_t)(1 + 2 * m));
+    U64x4 wb = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call,
+                            (uint64_t)k, (uint64_t)(2 + 2 * m));
+    int p = index_below(wa.w[0], n);
+    int q = pick_partner(K, cell, step, call, k, m, wa, wb, p, n);
+    R* up[3] = {u + p, u + st + p, u + 2 * st + p};
+    R* uq[3] = {u + q, u + st + q, u + 2 * st + q};
+    R dx = *up[0] - *uq[0], dy = *up[1] - *uq[1], dz = *up[2] - *uq[2];
+    R g = sqrt(dx * dx + dy * dy + dz * dz);
+    if (g > gmax) ++gmx;
+    bool ok = unif_r<R>(wa.w[2]) < sigma_g_r<SIG, R>(K, g) / sgmax;
+    if (ok) {
+      ++acc;
+      R eps = (R)2.0 * (R)kPi * unif_r<R>(wa.w[3]);
+      R cchi = (R)1.0 - (R)2.0 * unif_r<R>(wb.w[0]);  // eq. chi_iso
+      R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
+      R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
+      for (int d = 0; d < 3; ++d) {
+        R vcm = (R)0.5 * (*up[d] + *uq[d]);
+        *up[d] = vcm + (R)0.5 * g * nv[d];
+        *uq[d] = vcm - (R)0.5 * g * nv[d];
+      }
+    }
+    if (pairlog) {
+      unsigned long long s = atomicAdd(&counters[kCntPairLog], 1ull);
+      if ((int64_t)s < cap) {
+        long long* r = pairlog + 7 * s;
+        r[0] = cell; r[1] = call; r[2] = k; r[3] = m; r[4] = p; r[5] = q; r[6] = ok;
+      }
+    }
+  }
+}
+
+// Algorithm 1: N_pairs = floor(N (N - 1) P_max / 2 + U), in FP64 in both forms.
+// Beyond kMaxPairsPerOutcome (a degenerate state) it raises kFlagCapacity.
+__device__ inline int64_t npairs_of(const SimConst& K, int cell, int64_t step, int call, int k,
+                                    int n, int* flags) {
+  U64x4 w0 = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call, (uint64_t)k, 0);
+  double x = (double)n * (double)(n - 1) * K.pmax / 2.0 + unif(w0.w[0]);
+  if (!(x < (double)kMaxPairsPerOutcome)) {
+    atomicOr(&flags[kFlagCapacity], 1);
+    return 0;
+  }
+  return (int64_t)floor(x);
+}
+
+
+
+// The outcomes of one cell that have candidate pairs, in increasing outcome
+// order, accumulated into D (eq. avg_outcome).
+template <int SIG, class R>
+__device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call,
+                                               int64_t step, int c, int ci, int cs, int n,
+                                               const R* v0, R* u, R* D, int st,
+                                               const int* evt, int ne, bool all,
+                                               unsigned long long& acc,
+                                               unsigned long long& gmx) {
+    const int navg = K.navg;
+    bool touched = false;
+    int last = -1;
+    for (int it = 0; it < navg; ++it) {
+      int k;
+      if (all) {
+        k = it;
+      } else {  // next event of this cell in increasing outcome order
+        k = navg;
+        for (int e = 0; e < ne; ++e) {
+          int l = evt[e];
+          int eci = l / navg, ek = l - eci * navg;
+          if (eci == ci && ek > last && ek < k) k = ek;
+        }
+        if (k == navg) break;
+      }
+      last = k;
+      int64_t np_ = npairs_of(K, c, step, call, k, n, a.flags);
+      if (np_ <= 0) continue;
+      for (int j = 0; j < n; ++j)
+        for (int d = 0; d < 3; ++d) u[d * st + cs + j] = v0[d * st + cs + j];
+      ntc_outcome<SIG, R>(K, c, step, call, k, np_, n, u + cs, st, a.pairlog, a.cap, a.counters, acc,
+                      gmx);
+      for (int j = 0; j < n; ++j)
+        for (int d = 0; d < 3; ++d) D[d * st + cs + j] += u[d * st + cs + j] - v0[d * st + cs + j];
+      touched = true;
+    }
+    if (touched)
+      for (int j = 0; j < n; ++j)
+        for (int d = 0; d < 3; ++d) D[d * st + cs + j] /= (R)navg;
+}
+
+// Collision call over the tile: v0 (pre-collision velocities, tile slots,
+// stride st) -> D = <dv> per slot.  u is scratch of the same shape.
+template <int SIG, class R>
+__device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
+                                    int64_t step, int c0, int ncells, int s0, int ns,
+                                    const R* v0, R* u, R* D, int st,
+                                    int* evt, int* evt_n, int* overflow) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    *evt_n = 0;
+    *overflow = 0;
+  }
+  for (int j = tid; j < ns; j += kBlock) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
+  __syncthreads();
+  const int navg = K.navg;
+  const int64_t lanes = (int64_t)ncells * navg;
+  for (int64_t l = tid; l < lanes; l += kBlock) {
+    int ci = (int)(l / navg), k = (int)(l - (int64_t)ci * navg);
+    int c = c0 + ci;
+    int n = a.cstart[c + 1] - a.cstart[c];
+    if (n < 2) continue;
+    if (npairs_of(K, c, step, call, k, n, a.flags) > 0) {
+      int e = atomicAdd(evt_n, 1);
+      if (e < kMaxEvents) evt[e] = (int)l; else *overflow = 1;
+    }
+  }
+  __syncthreads();
+  const int ne = min(*evt_n, kMaxEvents);
+  const bool all = *overflow != 0;
+  unsigned long long acc = 0, gmx = 0;
+  for (int ci = tid; ci < ncells; ci += kBlock) {
+    int c = c0 + ci;
+    int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
+    if (n < 2) continue;
+    if (!all) {  // skip cells without events quickly
+      bool any = false;
+      for (int e = 0; e < ne; ++e) any |= (evt[e] / navg) == ci;
+      if (!any) continue;
+    }
+    cell_outcomes<SIG, R>(K, a, call, step, c, ci, cs, n, v0, u, D, st, evt, ne, all, acc, gmx);
+  }
+  if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
+  if (gmx) atomicAdd(&a.counters[kCntGmax], gmx);
+  __syncthreads();
+}
+
+__device__ inline void gather_f64(const SimConst& K, const double* E, const double xp[3], double ep[3],
+                                  int c[3]) {
+  double o[3];
+  locate(K, xp, c, o);
+  ep[0] = ep[1] = ep[2] = 0.0;
+  double wx[2] = {1.0 - o[0], o[0]}, wy[2] = {1.0 - o[1], o[1]}, wz[2] = {1.0 - o[2], o[2]};
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        int nd = lin(K, c[0] + cx, c[1] + cy, c[2] + cz);
+        double wgt = wx[cx] * wy[cy] * wz[cz];
+        for (int d = 0; d < 3; ++d) ep[d] += wgt * E[(int64_t)d * K.nn + nd];
+      }
+}
+
+// Half kick of one particle (eq. velocity_verlet): v += (acc + D - S)/2 + h.
+// FAM: 0 paper family (time-dependent velocity shape), 1 configuration family.
+template <int FAM, int SIG>
+__device__ inline void half_kick_f64(const SimConst& K, const double xp[3], const double ep[3],
+                                     double t, double t_from, double t_to, double t_src,
+                                     const double aa[3], int n, const double D[3], double v[3]) {
+  double em[3];
+  EM(K, xp, t, em);
+  double h[3] = {0.0, 0.0, 0.0};
+  if (FAM == 0) {
+    double va[3], vb[3], da[3], db[3];
+    if (K.isolate) {
+      manufactured_velocity(K, aa, t_from, va, da);
+      manufactured_velocity(K, aa, t_to, vb, db);
+      for (int d = 0; d < 3; ++d) h[d] = vb[d] - va[d];
+    } else {
+      manufactured_velocity(K, aa, t, va, da);
+      for (int d = 0; d < 3; ++d) h[d] = 0.5 * K.dt * da[d];
+    }
+  }
+  double coll[3] = {0.0, 0.0, 0.0};
+  if (K.collisions) {
+    double I[3] = {0.0, 0.0, 0.0};
+    double coef = (K.w * K.dt * (double)(n - 1)) / (2.0 * K.dV);
+    if (n >= 2) source_integral_t<SIG>(K, v, t_src, I);
+    for (int d = 0; d < 3; ++d) coll[d] = D[d] - ((n >= 2) ? coef * I[d] : 0.0);
+  }
+  for (int d = 0; d < 3; ++d) {
+    double acc = K.dt * K.qm * (ep[d] - em[d]);
+    v[d] = v[d] + 0.5 * (acc + coll[d]) + h[d];
+  }
+}
+
+// LDS (three tile arrays) allows four workgroups per CU; ask for registers to match.
+template <int FAM, int SIG>
+__global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a) {
+  __shared__ double lv0[3 * kLdsSlots], lu[3 * kLdsSlots], lD[3 * kLdsSlots];
+  __shared__ int evt[kMaxEvents];
+  __shared__ int sh_i[6];
+  const int tid = threadIdx.x;
+  const int NP = (int)K.np;
+  if (tid == 0) {
+    int c0 = min(a.tile_c0[blockIdx.x], K.nn);
+    int c1 = min(max(a.tile_c0[blockIdx.x + 1], c0), K.nn);
+    sh_i[0] = c0;
+    sh_i[1] = c1;
+    sh_i[2] = a.cstart[c0];
+    sh_i[3] = a.cstart[c1];
+  }
+  __syncthreads();
+  const int c0 = sh_i[0], ncells = sh_i[1] - sh_i[0], s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
+  if (ns <= 0) return;
+  const bool lds = ns <= kLdsSlots;
+  const int st = lds ? kLdsSlots : NP;
+  double* v0 = lds ? lv0 : a.gv0 + s0;
+  double* u = lds ? lu : a.gu + s0;
+  double* D = lds ? lD : a.gD + s0;
+  const double dt = K.dt;
+
+  for (int j = tid; j < ns; j += kBlock)
+    for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
+  __syncthreads();
+
+  if (a.mode & kCollideOnly) {
+    tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4], &sh_i[5]);
+    for (int j = tid; j < ns; j += kBlock) {
+      int c = a.key[s0 + j];
+      int n = a.cstart[c + 1] - a.cstart[c];
+      double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
+      double coef = (K.w * K.dt * (double)(n - 1)) / (2.0 * K.dV);
+      if (n >= 2) source_integral_t<SIG>(K, vp, a.tB, I);
+      for (int d = 0; d < 3; ++d) {
+        a.Dout[(int64_t)d * NP + s0 + j] = D[d * st + j];
+        a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? coef * I[d] : 0.0;
+      }
+    }
+    return;
+  }
+
+  if (a.mode & kDoB) {
+    // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
+    const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
+    if (K.collisions)
+      tile_collide<SIG, double>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4], &sh_i[5]);
+    for (int j = tid; j < ns; j += kBlock) {
+      int p = s0 + j;
+      double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
+      int cc[3];
+      gather_f64(K, a.E, xp, ep, cc);
+      int c = a.key[p];
+      int n = a.cstart[c + 1] - a.cstart[c];
+      double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
+      double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
+      double Dj[3] = {0.0, 0.0, 0.0};
+      if (K.collisions) Dj[0] = D[j], Dj[1] = D[st + j], Dj[2] = D[2 * st + j];
+      half_kick_f64<FAM, SIG>(K, xp, ep, t1, th, t1, th, aa, n, Dj, vp);
+      for (int d = 0; d < 3; ++d) v0[d * st + j] = vp[d];
+    }
+    __syncthreads();
+    if (!(a.mode & kDoA)) {
+      for (int j = tid; j < ns; j += kBlock)
+        for (int d = 0; d < 3; ++d) a.v[(int64_t)d * NP + s0 + j] = v0[d * st + j];
+      return;
+    }
+  }
+
+  // collision call A at t^{na} on v^{na}, first half kick, drift to t^{na+1}
+  const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
+  if (K.collisions)
+    tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4], &sh_i[5]);
+  for (int base = 0; base < ns; base += kBlock) {
+    int j = base + tid;
+    bool valid = j < ns;
+    int kk = 0;
+    if (valid) {
+      int p = s0 + j;
+      double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
+      int cc[3];
+      gather_f64(K, a.E, xp, ep, cc);
+      int c = a.key[p];
+      int n = a.cstart[c + 1] - a.cstart[c];
+      double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
+      double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
+      double Dj[3] = {0.0, 0.0, 0.0};
+      if (K.collisions) Dj[0] = D[j], Dj[1] = D[st + j], Dj[2] = D[2 * st + j];
+      half_kick_f64<FAM, SIG>(K, xp, ep, t0, t0, th, t0, aa, n, Dj, vp);
+      // drift (eq. velocity_verlet) with the manufactured term
+      double vm[3], vdm[3], h[3] = {0.0, 0.0, 0.0};
+      if (FAM == 1) {
+        for (int d = 0; d < 3; ++d) vm[d] = K.vbar * aa[d];
+      } else {
+        manufactured_velocity(K, aa, th, vm, vdm);
+      }
+      if (FAM == 0) {
+        int pid = a.id[p];
+        double xq[3];
+        position_uniforms(K, pid, xq);
+        if (K.isolate) {
+          double xa[3], xb[3];
+          manufactured_position(K, xq, t0, nullptr, xa);
+          manufactured_position(K, xq, t1, nullptr, xb);
+          for (int d = 0; d < 3; ++d) h[d] = xb[d] - xa[d];
+        } else {
+          double xm[3], xd[3];
+          manufactured_position(K, xq, th, nullptr, xm);
+          manufactured_xdot(K, xm, th, xd);
+          for (int d = 0; d < 3; ++d) h[d] = dt * xd[d];
+        }
+      }
+      for (int d = 0; d < 3; ++d) {
+        double xn = xp[d] + dt * (vp[d] - vm[d]) + h[d];
+        if (xn < 0.0) xn += K.L[d];
+        if (xn >= K.L[d]) xn -= K.L[d];
+        if (!(xn >= 0.0 && xn < K.L[d])) {  // non-finite or more than a box length
+          atomicOr(&a.flags[kFlagNonFinite], 1);
+          xn = isfinite(xn) ? xn - floor(xn / K.L[d]) * K.L[d] : 0.0;
+          if (!(xn >= 0.0 && xn < K.L[d])) xn = 0.0;
+        }
+        xp[d] = xn;
+        a.x[(int64_t)d * NP + p] = xn;
+        a.v[(int64_t)d * NP + p] = vp[d];
+      }
+      int ci[3];
+      double o[3];
+      locate(K, xp, ci, o);
+      kk = lin(K, ci[0], ci[1], ci[2]);
+      a.key[p] = kk;
+    }
+    int sl = wave_aggregated_slot(a.count, kk, valid);
+    if (valid) a.slot[s0 + j] = sl;
+  }
+}
+
+}  // namespace pic
