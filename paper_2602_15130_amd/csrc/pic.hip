@@ -462,6 +462,8 @@ PartArgs part_args(pic_ctx* c) {
   a.gv0 = c->V0G;
   a.gu = c->U;
   a.gD = c->D;
+  a.gmark = c->tidx;  // the sort's index arrays are idle during the particle pass
+  a.gtl = c->tkey;
   a.counters = c->cnt;
   a.flags = c->flags;
   a.callB = 1;

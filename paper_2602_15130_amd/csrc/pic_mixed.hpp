@@ -237,6 +237,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
   __shared__ float lv0[3 * kLdsSlots], lu[3 * kLdsSlots], lD[3 * kLdsSlots];
+  __shared__ int lmark[kLdsSlots], ltl[kLdsSlots];
   __shared__ int evt[kMaxEvents];
   __shared__ int sh_i[6];
   const int tid = threadIdx.x;
@@ -257,9 +258,14 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
   float* v0 = lds ? lv0 : (float*)a.gv0 + s0;
   float* u = lds ? lu : (float*)a.gu + s0;
   float* D = lds ? lD : (float*)a.gD + s0;
+  int* mark = lds ? lmark : a.gmark + s0;
+  int* tl = lds ? ltl : a.gtl + s0;
+  const float navg_f = (float)K.navg;
 
-  for (int j = tid; j < ns; j += kBlock)
+  for (int j = tid; j < ns; j += kBlock) {
     for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + s0 + j];
+    mark[j] = 0;
+  }
   __syncthreads();
 
   auto kick = [&](int j, const float amp[3], bool coll_on) {
@@ -277,7 +283,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
       float I[3] = {0.0f, 0.0f, 0.0f};
       float coef = M.src_w * (float)(n - 1);
       if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
-      for (int d = 0; d < 3; ++d) coll[d] = D[d * st + j] - ((n >= 2) ? coef * I[d] : 0.0f);
+      for (int d = 0; d < 3; ++d) coll[d] = D[d * st + j] / navg_f - ((n >= 2) ? coef * I[d] : 0.0f);
     }
     for (int d = 0; d < 3; ++d) {
       float acc = M.dtqm * (ep[d] - em[d]);
@@ -287,8 +293,8 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
   };
 
   if (a.mode & kCollideOnly) {
-    tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4],
-                             &sh_i[5]);
+    tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+                             evt, &sh_i[4], &sh_i[5]);
     for (int j = tid; j < ns; j += kBlock) {
       int c = a.key[s0 + j];
       int n = a.cstart[c + 1] - a.cstart[c];
@@ -296,7 +302,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
       float coef = M.src_w * (float)(n - 1);
       if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
       for (int d = 0; d < 3; ++d) {
-        a.Dout[(int64_t)d * NP + s0 + j] = (double)D[d * st + j];
+        a.Dout[(int64_t)d * NP + s0 + j] = (double)(D[d * st + j] / navg_f);
         a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? (double)(coef * I[d]) : 0.0;
       }
     }
@@ -305,8 +311,8 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
 
   if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
     if (K.collisions)
-      tile_collide<SIG, float>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, st, evt,
-                               &sh_i[4], &sh_i[5]);
+      tile_collide<SIG, float>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+                               evt, &sh_i[4], &sh_i[5]);
     for (int j = tid; j < ns; j += kBlock) kick(j, M.emB, K.collisions != 0);
     __syncthreads();
     if (!(a.mode & kDoA)) {
@@ -318,8 +324,8 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
 
   // call A at t^{na}, first half kick, drift to t^{na+1}
   if (K.collisions)
-    tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4],
-                             &sh_i[5]);
+    tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+                             st, evt, &sh_i[4], &sh_i[5]);
   for (int base = 0; base < ns; base += kBlock) {
     int j = base + tid;
     bool valid = j < ns;

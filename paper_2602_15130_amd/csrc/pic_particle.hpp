@@ -43,6 +43,8 @@ struct PartArgs {
   double* gv0;          // global fallback scratch [3][np]
   double* gu;           // global fallback scratch [3][np]
   double* gD;           // global fallback scratch [3][np]
+  int* gmark;           // global fallback scratch [np]
+  int* gtl;             // global fallback scratch [np]
   double* Dout;         // collide-only outputs [3][np]
   double* Sout;
   long long* pairlog;
@@ -94,13 +96,16 @@ __device__ inline R sigma_g_r(const SimConst& K, R g) {
   return r;
 }
 
-// One outcome of Algorithm 1 on the private copy u (cell-local SoA with stride
-// `st`) of one cell with n particles.
+// One outcome of Algorithm 1 on one cell of n particles (cell-local SoA arrays
+// with stride st).  The outcome's private velocities are copy-on-write: slot j
+// holds a private value in u when mark[j] == tag, else its value is v0[j]; the
+// slots written are appended to the touched list tl.
 template <int SIG, class R>
 __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, int call, int k,
-                                   int64_t npairs, int n, R* u, int st, long long* pairlog,
-                                   int64_t cap, unsigned long long* counters,
-                                   unsigned long long& acc, unsigned long long& gmx) {
+                                   int64_t npairs, int n, const R* v0, R* u, int* mark, int tag,
+                                   int* tl, int& ntl, int st, long long* pairlog, int64_t cap,
+                                   unsigned long long* counters, unsigned long long& acc,
+                                   unsigned long long& gmx) {
   const R sgmax = (R)K.sgmax, gmax = (R)K.g_max;
   for (int64_t m = 0; m < npairs; ++m) {
     U64x4 wa = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call,
@@ -109,9 +114,11 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
                             (uint64_t)k, (uint64_t)(2 + 2 * m));
     int p = index_below(wa.w[0], n);
     int q = pick_partner(K, cell, step, call, k, m, wa, wb, p, n);
-    R* up[3] = {u + p, u + st + p, u + 2 * st + p};
-    R* uq[3] = {u + q, u + st + q, u + 2 * st + q};
-    R dx = *up[0] - *uq[0], dy = *up[1] - *uq[1], dz = *up[2] - *uq[2];
+    const R* sp = mark[p] == tag ? u : v0;
+    const R* sq = mark[q] == tag ? u : v0;
+    R up[3] = {sp[p], sp[st + p], sp[2 * st + p]};
+    R uq[3] = {sq[q], sq[st + q], sq[2 * st + q]};
+    R dx = up[0] - uq[0], dy = up[1] - uq[1], dz = up[2] - uq[2];
     R g = sqrt(dx * dx + dy * dy + dz * dz);
     if (g > gmax) ++gmx;
     bool ok = unif_r<R>(wa.w[2]) < sigma_g_r<SIG, R>(K, g) / sgmax;
@@ -122,9 +129,17 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
       R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
       R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
       for (int d = 0; d < 3; ++d) {
-        R vcm = (R)0.5 * (*up[d] + *uq[d]);
-        *up[d] = vcm + (R)0.5 * g * nv[d];
-        *uq[d] = vcm - (R)0.5 * g * nv[d];
+        R vcm = (R)0.5 * (up[d] + uq[d]);
+        u[d * st + p] = vcm + (R)0.5 * g * nv[d];
+        u[d * st + q] = vcm - (R)0.5 * g * nv[d];
+      }
+      if (mark[p] != tag) {
+        mark[p] = tag;
+        tl[ntl++] = p;
+      }
+      if (mark[q] != tag) {
+        mark[q] = tag;
+        tl[ntl++] = q;
       }
     }
     if (pairlog) {
@@ -153,53 +168,51 @@ __device__ inline int64_t npairs_of(const SimConst& K, int cell, int64_t step, i
 
 
 // The outcomes of one cell that have candidate pairs, in increasing outcome
-// order, accumulated into D (eq. avg_outcome).
+// order, summed into D (eq. avg_outcome; the division by N_avg is done where D
+// is read).  Only the particles an outcome changed contribute to the sum; the
+// others would add exact zeros.
 template <int SIG, class R>
-__device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call,
-                                               int64_t step, int c, int ci, int cs, int n,
-                                               const R* v0, R* u, R* D, int st,
-                                               const int* evt, int ne, bool all,
-                                               unsigned long long& acc,
-                                               unsigned long long& gmx) {
-    const int navg = K.navg;
-    bool touched = false;
-    int last = -1;
-    for (int it = 0; it < navg; ++it) {
-      int k;
-      if (all) {
-        k = it;
-      } else {  // next event of this cell in increasing outcome order
-        k = navg;
-        for (int e = 0; e < ne; ++e) {
-          int l = evt[e];
-          int eci = l / navg, ek = l - eci * navg;
-          if (eci == ci && ek > last && ek < k) k = ek;
-        }
-        if (k == navg) break;
+__device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
+                                     int c, int ci, int cs, int n, const R* v0, R* u, R* D,
+                                     int* mark, int* tl, int tagbase, int st, const int* evt,
+                                     int ne, bool all, unsigned long long& acc,
+                                     unsigned long long& gmx) {
+  const int navg = K.navg;
+  int last = -1;
+  for (int it = 0; it < navg; ++it) {
+    int k;
+    if (all) {
+      k = it;
+    } else {  // next event of this cell in increasing outcome order
+      k = navg;
+      for (int e = 0; e < ne; ++e) {
+        int l = evt[e];
+        int eci = l / navg, ek = l - eci * navg;
+        if (eci == ci && ek > last && ek < k) k = ek;
       }
-      last = k;
-      int64_t np_ = npairs_of(K, c, step, call, k, n, a.flags);
-      if (np_ <= 0) continue;
-      for (int j = 0; j < n; ++j)
-        for (int d = 0; d < 3; ++d) u[d * st + cs + j] = v0[d * st + cs + j];
-      ntc_outcome<SIG, R>(K, c, step, call, k, np_, n, u + cs, st, a.pairlog, a.cap, a.counters, acc,
-                      gmx);
-      for (int j = 0; j < n; ++j)
-        for (int d = 0; d < 3; ++d) D[d * st + cs + j] += u[d * st + cs + j] - v0[d * st + cs + j];
-      touched = true;
+      if (k == navg) break;
     }
-    if (touched)
-      for (int j = 0; j < n; ++j)
-        for (int d = 0; d < 3; ++d) D[d * st + cs + j] /= (R)navg;
+    last = k;
+    int64_t np_ = npairs_of(K, c, step, call, k, n, a.flags);
+    if (np_ <= 0) continue;
+    int ntl = 0;
+    ntc_outcome<SIG, R>(K, c, step, call, k, np_, n, v0 + cs, u + cs, mark + cs, tagbase + k + 1,
+                        tl + cs, ntl, st, a.pairlog, a.cap, a.counters, acc, gmx);
+    for (int t = 0; t < ntl; ++t) {
+      int j = cs + tl[cs + t];
+      for (int d = 0; d < 3; ++d) D[d * st + j] += u[d * st + j] - v0[d * st + j];
+    }
+  }
 }
 
 // Collision call over the tile: v0 (pre-collision velocities, tile slots,
-// stride st) -> D = <dv> per slot.  u is scratch of the same shape.
+// stride st) -> D = N_avg <dv> per slot.  u, mark and tl are scratch of the
+// tile's slots; mark must hold values below tagbase + 1 on entry.
 template <int SIG, class R>
 __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
                                     int64_t step, int c0, int ncells, int s0, int ns,
-                                    const R* v0, R* u, R* D, int st,
-                                    int* evt, int* evt_n, int* overflow) {
+                                    const R* v0, R* u, R* D, int* mark, int* tl, int tagbase,
+                                    int st, int* evt, int* evt_n, int* overflow) {
   const int tid = threadIdx.x;
   if (tid == 0) {
     *evt_n = 0;
@@ -232,7 +245,8 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
       for (int e = 0; e < ne; ++e) any |= (evt[e] / navg) == ci;
       if (!any) continue;
     }
-    cell_outcomes<SIG, R>(K, a, call, step, c, ci, cs, n, v0, u, D, st, evt, ne, all, acc, gmx);
+    cell_outcomes<SIG, R>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, evt, ne,
+                          all, acc, gmx);
   }
   if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
   if (gmx) atomicAdd(&a.counters[kCntGmax], gmx);
@@ -291,6 +305,7 @@ __device__ inline void half_kick_f64(const SimConst& K, const double xp[3], cons
 template <int FAM, int SIG>
 __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a) {
   __shared__ double lv0[3 * kLdsSlots], lu[3 * kLdsSlots], lD[3 * kLdsSlots];
+  __shared__ int lmark[kLdsSlots], ltl[kLdsSlots];
   __shared__ int evt[kMaxEvents];
   __shared__ int sh_i[6];
   const int tid = threadIdx.x;
@@ -311,14 +326,20 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
   double* v0 = lds ? lv0 : a.gv0 + s0;
   double* u = lds ? lu : a.gu + s0;
   double* D = lds ? lD : a.gD + s0;
+  int* mark = lds ? lmark : a.gmark + s0;
+  int* tl = lds ? ltl : a.gtl + s0;
   const double dt = K.dt;
+  const double inv_navg_den = (double)K.navg;
 
-  for (int j = tid; j < ns; j += kBlock)
+  for (int j = tid; j < ns; j += kBlock) {
     for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
+    mark[j] = 0;
+  }
   __syncthreads();
 
   if (a.mode & kCollideOnly) {
-    tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4], &sh_i[5]);
+    tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+                              evt, &sh_i[4], &sh_i[5]);
     for (int j = tid; j < ns; j += kBlock) {
       int c = a.key[s0 + j];
       int n = a.cstart[c + 1] - a.cstart[c];
@@ -326,7 +347,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
       double coef = (K.w * K.dt * (double)(n - 1)) / (2.0 * K.dV);
       if (n >= 2) source_integral_t<SIG>(K, vp, a.tB, I);
       for (int d = 0; d < 3; ++d) {
-        a.Dout[(int64_t)d * NP + s0 + j] = D[d * st + j];
+        a.Dout[(int64_t)d * NP + s0 + j] = D[d * st + j] / inv_navg_den;
         a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? coef * I[d] : 0.0;
       }
     }
@@ -337,7 +358,8 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
     // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
     const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
     if (K.collisions)
-      tile_collide<SIG, double>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4], &sh_i[5]);
+      tile_collide<SIG, double>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+                                evt, &sh_i[4], &sh_i[5]);
     for (int j = tid; j < ns; j += kBlock) {
       int p = s0 + j;
       double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
@@ -348,7 +370,8 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
       double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
       double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
       double Dj[3] = {0.0, 0.0, 0.0};
-      if (K.collisions) Dj[0] = D[j], Dj[1] = D[st + j], Dj[2] = D[2 * st + j];
+      if (K.collisions)
+        for (int d = 0; d < 3; ++d) Dj[d] = D[d * st + j] / inv_navg_den;
       half_kick_f64<FAM, SIG>(K, xp, ep, t1, th, t1, th, aa, n, Dj, vp);
       for (int d = 0; d < 3; ++d) v0[d * st + j] = vp[d];
     }
@@ -363,7 +386,8 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
   // collision call A at t^{na} on v^{na}, first half kick, drift to t^{na+1}
   const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
   if (K.collisions)
-    tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, st, evt, &sh_i[4], &sh_i[5]);
+    tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+                              st, evt, &sh_i[4], &sh_i[5]);
   for (int base = 0; base < ns; base += kBlock) {
     int j = base + tid;
     bool valid = j < ns;
@@ -378,7 +402,8 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
       double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
       double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
       double Dj[3] = {0.0, 0.0, 0.0};
-      if (K.collisions) Dj[0] = D[j], Dj[1] = D[st + j], Dj[2] = D[2 * st + j];
+      if (K.collisions)
+        for (int d = 0; d < 3; ++d) Dj[d] = D[d * st + j] / inv_navg_den;
       half_kick_f64<FAM, SIG>(K, xp, ep, t0, t0, th, t0, aa, n, Dj, vp);
       // drift (eq. velocity_verlet) with the manufactured term
       double vm[3], vdm[3], h[3] = {0.0, 0.0, 0.0};
