@@ -1,6 +1,6 @@
 """Throughput of the manufactured-solution PIC/DSMC time step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|...]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3|cfg2|...]
 
 A step is one pass of the whole path: collision call A, half kick, drift, cell
 sort, deposit, Poisson CG, gradient, collision call B, half kick.  Inputs are
@@ -70,7 +70,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--beside", default="cfg2",
+                    help="second workload timed beside the first (the FP64 form); 'none' to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -81,25 +83,37 @@ def main():
     import torch
     from paper_2602_15130_amd import pic, workloads as W
 
-    c = W.get(args.workload)
+    out = run_workload(pic, W, torch, args.workload, args.steps, args.warmup)
+    if args.beside and args.beside != "none":
+        b = run_workload(pic, W, torch, args.beside, args.steps, args.warmup)
+        out["beside"] = {k: b[k] for k in ("value", "ms_per_step", "dtype", "config", "roofline",
+                                           "roofline_particle_path", "stages")}
+    if not args.no_cpu_baseline:
+        c = W.get(args.workload)
+        out["cpu_baseline"] = cpu_baseline(c["problem"], c["disc"], c["seed"])
+    print(json.dumps(out), flush=True)
+
+
+def run_workload(pic, W, torch, workload, steps, warmup):
+    c = W.get(workload)
     prob, disc, precision, seed = c["problem"], c["disc"], c["precision"], c["seed"]
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     sim = pic.Sim(prob, disc, seed, 0, precision, "cuda:0", stream)
-    if args.warmup:
-        sim.step(args.warmup)
+    if warmup:
+        sim.step(warmup)
     torch.cuda.synchronize()
     sim.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    sim.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages = sim.timing_read()
     sim.timing(False)
     st = sim.stats()
     elapsed = t1 - t0
-    value = disc["np"] * args.steps / elapsed
+    value = disc["np"] * steps / elapsed
 
     per_stage = {}
     for name, (ms, n) in stages.items():
@@ -115,23 +129,34 @@ def main():
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
             "algorithmic_bytes_per_launch": dom_bytes}
+    # the particle path (push, deposit, collide: the fused pass, sort and deposit)
+    part_names = [k for k in ("particle", "collide", "kick", "drift", "sort", "deposit") if k in per_stage]
+    pb = sum(stage_bytes(k, prob, disc, precision, st["cg_iters"]) * per_stage[k]["launches"]
+             for k in part_names)
+    pms = sum(per_stage[k]["ms_total"] for k in part_names)
+    pach = pb / (pms * 1e-3) / 1e9
+    roof_part = {"bound": "hbm", "kernels": part_names, "achieved": round(pach, 1),
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
+                 "ms_per_step": round(pms / steps, 3),
+                 "algorithmic_bytes_per_particle_step": round(pb / steps / disc["np"], 1)}
     out = {
         "metric": "particle-steps/s", "value": value, "unit": "particle-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * elapsed / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic (manufactured solution, Philox seed %d)" % seed,
-        "config": {"workload": args.workload, "mesh": list(disc["nc"]), "particles": disc["np"],
+        "config": {"workload": workload, "mesh": list(disc["nc"]), "particles": disc["np"],
                    "n_avg": disc["navg"], "dt": disc["dt"], "precision": precision,
                    "collisions": bool(prob["collisions"]), "two_way": bool(prob["particles_to_field"])},
         "roofline": roof,
+        "roofline_particle_path": roof_part,
         "stages": per_stage,
         "cg_iters_last": st["cg_iters"],
         "accepted_collisions": st["n_accepted"],
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, disc, seed)
-    print(json.dumps(out), flush=True)
+    del sim
+    torch.cuda.synchronize()
+    return out
 
 
 if __name__ == "__main__":
