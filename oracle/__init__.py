@@ -74,6 +74,7 @@ def lib():
         L.orc_deposit.argtypes = [P(OrcProblem), P(OrcDisc), i64, P(d), P(d)]
         L.orc_rhs.argtypes = [P(OrcProblem), P(OrcDisc), P(d), d, P(d)]
         L.orc_cg.argtypes = [P(OrcDisc), P(OrcProblem), P(d), P(d), d, C.c_int, P(C.c_int), P(d)]
+        L.orc_cg_textbook.argtypes = L.orc_cg.argtypes
         L.orc_laplacian.argtypes = [P(OrcDisc), P(OrcProblem), P(d), P(d)]
         L.orc_gradient.argtypes = [P(OrcProblem), P(OrcDisc), P(d), P(d)]
         L.orc_gather.argtypes = [P(OrcProblem), P(OrcDisc), P(d), i64, P(d), P(d)]
@@ -231,13 +232,14 @@ def rhs(prob, disc, rho, t):
     return b
 
 
-def cg(prob, disc, b, phi0=None, tol=None, max_iter=None):
+def cg(prob, disc, b, phi0=None, tol=None, max_iter=None, textbook=False):
     P, D = make_problem(prob), make_disc(disc)
     b = np.ascontiguousarray(b, dtype=np.float64)
     phi = np.zeros_like(b) if phi0 is None else np.array(phi0, dtype=np.float64)
     it = C.c_int()
     rr = C.c_double()
-    st = lib().orc_cg(C.byref(D), C.byref(P), _dp(b), _dp(phi),
+    fn = lib().orc_cg_textbook if textbook else lib().orc_cg
+    st = fn(C.byref(D), C.byref(P), _dp(b), _dp(phi),
                       float(disc["cg_tol"] if tol is None else tol),
                       int(disc["cg_max_iter"] if max_iter is None else max_iter),
                       C.byref(it), C.byref(rr))

@@ -586,10 +586,78 @@ static double dot(int64_t n, const double* a, const double* b) {
   return s;
 }
 
-/* Plain conjugate gradients on A = -L_h (SPD on zero-mean fields), A phi = -b.
- * phi holds the initial guess on entry; the result is projected to zero mean. */
+/* Conjugate gradients on A = -L_h (SPD on zero-mean fields), A phi = -b, in
+ * the single-reduction recurrence of Chronopoulos and Gear (1989): the
+ * operator is applied to the residual, s = A p is carried by its own
+ * recurrence, and the two inner products of an iteration are formed together:
+ *   r_0 = -b - A x_0, w_0 = A r_0, gamma_0 = r_0.r_0, alpha_0 = gamma_0 / (w_0.r_0);
+ *   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}   (beta_0 = 0)
+ *   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i,  w_{i+1} = A r_{i+1}
+ *   gamma_{i+1} = r_{i+1}.r_{i+1},  delta_{i+1} = w_{i+1}.r_{i+1}
+ *   beta_{i+1} = gamma_{i+1} / gamma_i
+ *   alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i).
+ * In exact arithmetic its iterates are those of textbook CG (orc_cg_textbook).
+ * Stops when ||r||_2 <= tol ||b||_2.  phi holds the initial guess on entry;
+ * the result is projected to zero mean (Sec. 2). */
 int orc_cg(const orc_disc* D, const orc_problem* P, const double* b, double* phi, double tol,
            int max_iter, int* iters, double* relres) {
+  int64_t n = nnodes(D);
+  double* r = (double*)malloc(sizeof(double) * n);
+  double* w = (double*)malloc(sizeof(double) * n);
+  double* p = (double*)malloc(sizeof(double) * n);
+  double* s = (double*)malloc(sizeof(double) * n);
+  double* rhs = (double*)malloc(sizeof(double) * n);
+  for (int64_t i = 0; i < n; ++i) rhs[i] = -b[i];
+  orc_laplacian(D, P, phi, w); /* w = L phi, so A phi = -w */
+  for (int64_t i = 0; i < n; ++i) r[i] = rhs[i] + w[i];
+  double bnorm = sqrt(dot(n, rhs, rhs));
+  double gamma = dot(n, r, r);
+  int it = 0, status = 0;
+  if (bnorm == 0.0) {
+    for (int64_t i = 0; i < n; ++i) phi[i] = 0.0;
+    gamma = 0.0;
+  } else if (sqrt(gamma) > tol * bnorm) {
+    orc_laplacian(D, P, r, w);
+    for (int64_t i = 0; i < n; ++i) w[i] = -w[i];
+    double delta = dot(n, w, r);
+    double alpha = gamma / delta, beta = 0.0;
+    while (1) {
+      if (it >= max_iter) {
+        status = -3;
+        break;
+      }
+      for (int64_t i = 0; i < n; ++i) {
+        p[i] = (it == 0) ? r[i] : r[i] + beta * p[i];
+        s[i] = (it == 0) ? w[i] : w[i] + beta * s[i];
+      }
+      for (int64_t i = 0; i < n; ++i) phi[i] += alpha * p[i];
+      for (int64_t i = 0; i < n; ++i) r[i] -= alpha * s[i];
+      orc_laplacian(D, P, r, w);
+      for (int64_t i = 0; i < n; ++i) w[i] = -w[i];
+      double gamma_new = dot(n, r, r);
+      delta = dot(n, w, r);
+      ++it;
+      beta = gamma_new / gamma;
+      alpha = gamma_new / (delta - beta * gamma_new / alpha);
+      gamma = gamma_new;
+      if (sqrt(gamma) <= tol * bnorm) break;
+    }
+  }
+  double mean = 0.0;
+  for (int64_t i = 0; i < n; ++i) mean += phi[i];
+  mean /= (double)n;
+  for (int64_t i = 0; i < n; ++i) phi[i] -= mean;
+  *iters = it;
+  *relres = (bnorm == 0.0) ? 0.0 : sqrt(gamma) / bnorm;
+  free(r); free(w); free(p); free(s); free(rhs);
+  return status;
+}
+
+/* Textbook conjugate gradients (Hestenes and Stiefel) on the same system, with
+ * the same stopping rule and projection; kept as an independent check of the
+ * recurrence above. */
+int orc_cg_textbook(const orc_disc* D, const orc_problem* P, const double* b, double* phi,
+                    double tol, int max_iter, int* iters, double* relres) {
   int64_t n = nnodes(D);
   double* r = (double*)malloc(sizeof(double) * n);
   double* p = (double*)malloc(sizeof(double) * n);

@@ -104,6 +104,8 @@ void orc_deposit(const orc_problem* P, const orc_disc* D, int64_t np, const doub
 void orc_rhs(const orc_problem* P, const orc_disc* D, const double* rho, double t, double* b);
 int orc_cg(const orc_disc* D, const orc_problem* P, const double* b, double* phi,
            double tol, int max_iter, int* iters, double* relres);
+int orc_cg_textbook(const orc_disc* D, const orc_problem* P, const double* b, double* phi,
+                    double tol, int max_iter, int* iters, double* relres);
 void orc_laplacian(const orc_disc* D, const orc_problem* P, const double* phi, double* out);
 void orc_gradient(const orc_problem* P, const orc_disc* D, const double* phi, double* E);
 void orc_gather(const orc_problem* P, const orc_disc* D, const double* E, int64_t np,

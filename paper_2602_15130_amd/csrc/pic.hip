@@ -29,7 +29,7 @@ enum Arr {
   A_X0, A_X1, A_V0, A_V1, A_SH0, A_SH1, A_ID0, A_ID1,  // FP64 particle state, two buffers
   A_OFF0, A_OFF1, A_VF0, A_VF1, A_ASF0, A_ASF1,      // mixed particle state, two buffers
   A_KEY, A_SLOT, A_TIDX, A_TKEY, A_D, A_U, A_V0G,
-  A_COUNT, A_CSTART, A_BSUM, A_TILE, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_R, A_P0, A_P1, A_Q,
+  A_COUNT, A_CSTART, A_BSUM, A_TILE, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_CGV,
   A_PART_A, A_PART_B, A_EPART, A_NPART, A_NORMS, A_BAR, A_RESULT, A_FLAGS, A_CNT, A_CGIT, A_CGRR,
   A_NARR
 };
@@ -61,7 +61,8 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_BSUM] = (nscan + 1) * 4;
   b[A_TILE] = ((np + kTileB - 1) / kTileB + 2) * 4;
   b[A_MOM] = 64 * nn;  // 8 FP64 cell moments, or 8 FP32 moments + 8 compensations
-  b[A_RHO] = b[A_B] = b[A_PHI] = b[A_R] = b[A_P0] = b[A_P1] = b[A_Q] = nn * 8;
+  b[A_RHO] = b[A_B] = b[A_PHI] = nn * 8;
+  b[A_CGV] = 7 * nn * 8;  // CG vectors r, w, s (two each) and p
   b[A_E] = 3 * nn * 8;
   b[A_E32] = f64 ? 0 : 3 * nn * 4;
   b[A_PART_A] = b[A_PART_B] = std::max<int64_t>(nblk_n, 4096) * 8;
@@ -220,7 +221,7 @@ struct pic_ctx {
   float* Df{};
   bool fused = true;
   void* mom{};
-  double *rho{}, *b{}, *phi{}, *E{}, *r{}, *p0{}, *p1{}, *q{}, *partA{}, *partB{};
+  double *rho{}, *b{}, *phi{}, *E{}, *cgv{}, *partA{}, *partB{};
   float* E32{};
   double *epart{}, *npart{}, *norms{}, *cgrr{}, *result{};
   unsigned* bar{};
@@ -387,10 +388,12 @@ int field_solve(pic_ctx* c, double t) {
   CgArgs a;
   a.b = c->b;
   a.x = c->phi;
-  a.r = c->r;
-  a.p0 = c->p0;
-  a.p1 = c->p1;
-  a.q = c->q;
+  for (int k = 0; k < 2; ++k) {
+    a.r[k] = c->cgv + (int64_t)k * K.nn;
+    a.w[k] = c->cgv + (int64_t)(2 + k) * K.nn;
+    a.s[k] = c->cgv + (int64_t)(4 + k) * K.nn;
+  }
+  a.p = c->cgv + 6 * (int64_t)K.nn;
   a.part = c->partA;
   a.result = c->result;
   a.arrive = c->bar;
@@ -671,10 +674,7 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   c->phi = carve<double>(c, A_PHI);
   c->E = carve<double>(c, A_E);
   c->E32 = carve<float>(c, A_E32);
-  c->r = carve<double>(c, A_R);
-  c->p0 = carve<double>(c, A_P0);
-  c->p1 = carve<double>(c, A_P1);
-  c->q = carve<double>(c, A_Q);
+  c->cgv = carve<double>(c, A_CGV);
   c->partA = carve<double>(c, A_PART_A);
   c->partB = carve<double>(c, A_PART_B);
   c->epart = carve<double>(c, A_EPART);
@@ -699,6 +699,12 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     return PIC_EHIP;
   }
   c->cg_grid = (int)std::min<int64_t>({(int64_t)ncu, (int64_t)ncu * per_cu, (int64_t)grid_for(c->K.nn)});
+  // PIC_CG_BLOCKS narrows the solver grid (fewer blocks make each grid-wide
+  // reduction cheaper and each sweep longer); it never exceeds the co-resident bound.
+  if (const char* ev = std::getenv("PIC_CG_BLOCKS")) {
+    int want = std::atoi(ev);
+    if (want >= 1) c->cg_grid = std::min(c->cg_grid, want);
+  }
 
   auto init = [&]() -> int {
     const SimConst& K = c->K;

@@ -342,14 +342,20 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(SimConst K, double* b, cons
 
 // ---------------------------------------------------------------------------
 // Poisson CG: one cooperative persistent kernel.  A = -L_h (periodic 7-point),
-// A phi = -b.  The search direction update p = r + beta p is folded into the
-// next stencil sweep (ping-pong buffers), so an iteration has two grid-wide
-// reductions.  Each reduction is also the grid barrier: every block publishes
-// its partial sums and then a flag (one release store); block 0 waits for all
-// flags, sums the partials in block order and publishes the result and a
-// release word; every block waits on that word.  Waits poll with relaxed
-// loads and take one acquire fence at the end; they are bounded and raise
-// kFlagBarrier on timeout so every wave always leaves the kernel.
+// A phi = -b, in the single-reduction recurrence of Chronopoulos and Gear:
+// the operator acts on the residual (w = A r), s = A p follows its own
+// recurrence, and gamma = r.r and delta = w.r are reduced together, so an
+// iteration has ONE grid-wide reduction.  The pointwise updates of iteration i
+// (p, s, x, r) and the stencil w_{i+1} = A r_{i+1} share one sweep: the
+// stencil rebuilds r_{i+1} at the six neighbours from r_i, w_i and s_{i-1},
+// which were all published before the reduction, with the same expression the
+// neighbour's owner evaluates (ping-pong buffers for r, w and s).  The
+// reduction is also the grid barrier: every block publishes its partial sums
+// and then a flag (one release store); block 0 waits for all flags, sums the
+// partials in block order and publishes the result and a release word; every
+// block waits on that word.  Waits poll with relaxed loads and take one
+// acquire fence at the end; they are bounded and raise kFlagBarrier on
+// timeout so every wave always leaves the kernel.
 // ---------------------------------------------------------------------------
 constexpr int kFlagStride = 32;  // 128 bytes between per-block flags
 constexpr int kMaxRed = 3;       // values per reduction
@@ -357,10 +363,10 @@ constexpr int kMaxRed = 3;       // values per reduction
 struct CgArgs {
   const double* b;
   double* x;
-  double* r;
-  double* p0;
-  double* p1;
-  double* q;
+  double* r[2];       // residual, ping-pong
+  double* w[2];       // A r, ping-pong
+  double* s[2];       // A p, ping-pong
+  double* p;          // search direction
   double* part;       // [grid][kMaxRed]
   double* result;     // [kMaxRed]
   unsigned* arrive;   // [grid * kFlagStride], zero before launch
@@ -442,72 +448,77 @@ __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
   const int gsize = gridDim.x * kBlock;
   const int g0 = blockIdx.x * kBlock + threadIdx.x;
   unsigned gen = 0;
-  // r = -b - A x, p = r
+  // r_0 = -b - A x_0; gamma_0 = r_0.r_0 and ||b||^2
   double v2[kMaxRed] = {0.0, 0.0, 0.0};
   for (int n = g0; n < K.nn; n += gsize) {
     int i, j, k;
     node_coords(K, n, i, j, k);
     double ax = neg_lap(K, i, j, k, [&](int m) { return a.x[m]; });
     double rv = -a.b[n] - ax;
-    a.r[n] = rv;
-    a.p0[n] = rv;
+    a.r[0][n] = rv;
     v2[0] += rv * rv;
     v2[1] += a.b[n] * a.b[n];
   }
   if (!grid_sum(a, v2, 2, ++gen, sh)) return;
-  double rr = v2[0];
-  double bnorm = sqrt(v2[1]);
+  double gamma = v2[0];
+  const double bnorm = sqrt(v2[1]);
   int it = 0;
-  int cur = 0;
-  double beta = 0.0;
   if (bnorm == 0.0) {
     for (int n = g0; n < K.nn; n += gsize) a.x[n] = 0.0;
-    rr = 0.0;
-  } else {
+    gamma = 0.0;
+  } else if (sqrt(gamma) > a.tol * bnorm) {
+    // w_0 = A r_0, delta_0 = w_0.r_0
+    double v1[kMaxRed] = {0.0, 0.0, 0.0};
+    for (int n = g0; n < K.nn; n += gsize) {
+      int i, j, k;
+      node_coords(K, n, i, j, k);
+      double wv = neg_lap(K, i, j, k, [&](int m) { return a.r[0][m]; });
+      a.w[0][n] = wv;
+      v1[0] += wv * a.r[0][n];
+    }
+    if (!grid_sum(a, v1, 1, ++gen, sh)) return;
+    double alpha = gamma / v1[0], beta = 0.0;
+    int cur = 0;
     while (true) {
-      if (sqrt(rr) <= a.tol * bnorm) break;
       if (it >= a.max_iter) {
         if (g0 == 0) atomicOr(&a.flags[kFlagCgNoConv], 1);
         break;
       }
-      const double* pc = cur ? a.p1 : a.p0;
-      double* pn = cur ? a.p0 : a.p1;
-      double s_pq[kMaxRed] = {0.0, 0.0, 0.0};
-      if (it == 0) {
-        for (int n = g0; n < K.nn; n += gsize) {
-          int i, j, k;
-          node_coords(K, n, i, j, k);
-          double qv = neg_lap(K, i, j, k, [&](int m) { return pc[m]; });
-          a.q[n] = qv;
-          s_pq[0] += pc[n] * qv;
-        }
-      } else {
-        for (int n = g0; n < K.nn; n += gsize) {
-          int i, j, k;
-          node_coords(K, n, i, j, k);
-          auto pnew = [&](int m) { return a.r[m] + beta * pc[m]; };
-          double pv = pnew(n);
-          pn[n] = pv;
-          double qv = neg_lap(K, i, j, k, pnew);
-          a.q[n] = qv;
-          s_pq[0] += pv * qv;
-        }
-        cur ^= 1;
-      }
-      const double* p = cur ? a.p1 : a.p0;
-      if (!grid_sum(a, s_pq, 1, ++gen, sh)) return;
-      double alpha = rr / s_pq[0];
-      double s_r[kMaxRed] = {0.0, 0.0, 0.0};
+      const double* rc = a.r[cur];
+      const double* wc = a.w[cur];
+      const double* sc = a.s[cur];
+      double* rn = a.r[cur ^ 1];
+      double* wn = a.w[cur ^ 1];
+      double* sn = a.s[cur ^ 1];
+      const bool first = it == 0;  // p_{-1} = s_{-1} = 0: never read
+      // r_{i+1} at any node, exactly as its owner computes it below
+      auto rnext = [&](int m) {
+        double sv = first ? wc[m] : wc[m] + beta * sc[m];
+        return rc[m] - alpha * sv;
+      };
+      double gd[kMaxRed] = {0.0, 0.0, 0.0};
       for (int n = g0; n < K.nn; n += gsize) {
-        a.x[n] += alpha * p[n];
-        double rv = a.r[n] - alpha * a.q[n];
-        a.r[n] = rv;
-        s_r[0] += rv * rv;
+        int i, j, k;
+        node_coords(K, n, i, j, k);
+        double pv = first ? rc[n] : rc[n] + beta * a.p[n];
+        double sv = first ? wc[n] : wc[n] + beta * sc[n];
+        a.p[n] = pv;
+        sn[n] = sv;
+        a.x[n] += alpha * pv;
+        double rv = rc[n] - alpha * sv;
+        rn[n] = rv;
+        double wv = neg_lap(K, i, j, k, rnext);
+        wn[n] = wv;
+        gd[0] += rv * rv;
+        gd[1] += wv * rv;
       }
-      if (!grid_sum(a, s_r, 1, ++gen, sh)) return;
-      beta = s_r[0] / rr;
-      rr = s_r[0];
+      if (!grid_sum(a, gd, 2, ++gen, sh)) return;
+      cur ^= 1;
       ++it;
+      beta = gd[0] / gamma;
+      alpha = gd[0] / (gd[1] - beta * gd[0] / alpha);
+      gamma = gd[0];
+      if (sqrt(gamma) <= a.tol * bnorm) break;
     }
   }
   // zero-mean projection (Sec. 2)
@@ -518,7 +529,7 @@ __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
   for (int n = g0; n < K.nn; n += gsize) a.x[n] -= mean;
   if (g0 == 0) {
     *a.iters_out = it;
-    *a.relres_out = bnorm == 0.0 ? 0.0 : sqrt(rr) / bnorm;
+    *a.relres_out = bnorm == 0.0 ? 0.0 : sqrt(gamma) / bnorm;
   }
 }
 

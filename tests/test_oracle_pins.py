@@ -400,6 +400,37 @@ def test_cg_matches_fft_solution():
     assert abs(phi.mean()) < 1e-15 * np.abs(phi).max()
 
 
+@pytest.mark.parametrize("textbook", [False, True])
+def test_cg_recurrences_fft_exact_and_agree(textbook):
+    """Both CG recurrences reach the DFT-exact discrete solution within the
+    kappa * tol bound; the single-reduction form takes the textbook form's
+    iteration count (same iterates in exact arithmetic) and its first iterates
+    agree to rounding."""
+    n = 16
+    prob, disc = CFG, _disc(n, tol=1e-13)
+    rng = np.random.default_rng(21)
+    b = rng.normal(size=n**3)
+    b -= b.mean()
+    phi0 = rng.normal(size=n**3)
+    phi, it, rr, st = O.cg(prob, disc, b, phi0=phi0, textbook=textbook)
+    assert st == 0 and rr <= 1e-13
+    k = 2 * np.pi * np.fft.fftfreq(n)
+    h = 1 / n
+    lam = sum(np.meshgrid(*(-(4 / h**2) * np.sin(k / 2) ** 2,) * 3, indexing="ij"))
+    lam[0, 0, 0] = 1.0
+    ph = np.fft.fftn(b.reshape(n, n, n)) / lam
+    ph[0, 0, 0] = 0.0
+    ref = np.real(np.fft.ifftn(ph)).ravel()
+    kappa = 3 / math.sin(math.pi / n) ** 2
+    np.testing.assert_allclose(phi, ref, rtol=0, atol=kappa * 1e-13 * np.abs(ref).max())
+    other, it2, _, _ = O.cg(prob, disc, b, phi0=phi0, textbook=not textbook)
+    assert abs(it - it2) <= 1
+    for m in (1, 2, 5):
+        a, _, _, _ = O.cg(prob, disc, b, phi0=phi0, max_iter=m, textbook=textbook)
+        c, _, _, _ = O.cg(prob, disc, b, phi0=phi0, max_iter=m, textbook=not textbook)
+        assert np.abs(a - c).max() < 1e-10 * np.abs(c).max()
+
+
 def test_cg_reports_nonconvergence():
     n = 8
     prob, disc = CFG, _disc(n, tol=1e-14)
