@@ -152,6 +152,7 @@ def run_workload(pic, W, torch, workload, steps, warmup):
         "roofline_particle_path": roof_part,
         "stages": per_stage,
         "cg_iters_last": st["cg_iters"],
+        "cg_solver": {"blocks": st["cg_blocks"], "brick": st["cg_brick"]},
         "accepted_collisions": st["n_accepted"],
     }
     del sim

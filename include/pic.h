@@ -174,6 +174,8 @@ typedef struct {
   double cg_relres;         /* its final relative residual */
   int64_t n_accepted;       /* accepted collisions since initialisation */
   int64_t n_gmax;           /* candidate pairs with g > g_max */
+  int cg_blocks;            /* workgroups of the Poisson solver */
+  int cg_brick[3];          /* nodes per brick of the on-chip solver; 0 0 0 = global-memory solver */
 } pic_stats_t;
 int pic_stats(pic_ctx* ctx, pic_stats_t* out);
 

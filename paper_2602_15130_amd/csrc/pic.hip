@@ -15,6 +15,7 @@
 #include "pic_kernels.hpp"
 #include "pic_particle.hpp"
 #include "pic_mixed.hpp"
+#include "pic_cg_brick.hpp"
 
 using namespace pic;
 
@@ -194,6 +195,58 @@ SimConst derive(const pic_problem* p, const pic_discretization* d, uint64_t seed
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
 
+// The Poisson solver kernel for q nodes per thread (0: the global-memory one).
+const void* cg_kernel(int q) {
+  switch (q) {
+    case 1: return (const void*)k_cg_brick<1>;
+    case 2: return (const void*)k_cg_brick<2>;
+    case 4: return (const void*)k_cg_brick<4>;
+    case 8: return (const void*)k_cg_brick<8>;
+    case 16: return (const void*)k_cg_brick<16>;
+    default: return (const void*)k_cg;
+  }
+}
+
+// Brick decomposition for the on-chip solver: bricks of kBlock * q nodes
+// (q in 1..16) that tile the mesh exactly, whose padded copy fits 64 KB of LDS,
+// and whose count fits the co-resident grid and the reduction scratch.  Among
+// those, the count closest to `target` (ties: smallest face area, then the
+// longest x extent for coalesced rows) wins.  Returns false when none exists.
+struct BrickChoice {
+  int q, bd[3], nbr[3];
+};
+bool choose_bricks(const int nc[3], int max_blocks, int target, BrickChoice& out) {
+  bool found = false;
+  long best_cost = 0;
+  for (int q = 1; q <= 16; q *= 2) {
+    const int m = kBlock * q;
+    for (int bx = 1; bx <= nc[0]; ++bx) {
+      if (nc[0] % bx || m % bx) continue;
+      for (int by = 1; by <= nc[1]; ++by) {
+        if (nc[1] % by || (m / bx) % by) continue;
+        int bz = m / (bx * by);
+        if (bz < 1 || bz > nc[2] || nc[2] % bz) continue;
+        const int bdv[3] = {bx, by, bz};
+        if (brick_lds_bytes(bdv) > 65536) continue;
+        // published faces (6 per node of surface) must fit the 6 nn doubles they reuse
+        if (2L * (bx * by + by * bz + bx * bz) > m) continue;
+        int64_t nb = (int64_t)(nc[0] / bx) * (nc[1] / by) * (nc[2] / bz);
+        if (nb > max_blocks || nb > 1024) continue;
+        long area = 2L * (bx * by + by * bz + bx * bz);
+        long cost = std::labs((long)nb - target) * 1000000L + area * 100L + (100 - std::min(bx, 99));
+        if (!found || cost < best_cost) {
+          found = true;
+          best_cost = cost;
+          out.q = q;
+          out.bd[0] = bx; out.bd[1] = by; out.bd[2] = bz;
+          out.nbr[0] = nc[0] / bx; out.nbr[1] = nc[1] / by; out.nbr[2] = nc[2] / bz;
+        }
+      }
+    }
+  }
+  return found;
+}
+
 }  // namespace
 
 struct pic_ctx {
@@ -203,6 +256,10 @@ struct pic_ctx {
   int cg_max_iter = 1000;
   hipStream_t stream = nullptr;
   int cg_grid = 1;
+  int cg_q = 0;                 // nodes per thread of the brick solver; 0 = global solver
+  int cg_bd[3] = {0, 0, 0};     // brick dimensions
+  int cg_nbr[3] = {0, 0, 0};    // bricks per axis
+  size_t cg_lds = 0;            // padded brick, bytes of LDS
   bool ready = false;
   int64_t step = 0;
   int cur = 0;
@@ -369,14 +426,23 @@ int field_solve(pic_ctx* c, double t) {
   int nbn = grid_for(K.nn);
   {
     StageTimer tm(c, PIC_STAGE_DEPOSIT);
+    const int ntiles = (int)((K.np + kTileB - 1) / kTileB);
     if (c->precision == PIC_FP64) {
-      k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
-                                                           (double*)c->mom);
+      if (c->fused)
+        k_deposit_tiles_f64<<<ntiles, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
+                                                              c->tile_c0, (double*)c->mom);
+      else
+        k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
+                                                             (double*)c->mom);
       k_node_rhs<double><<<nbn, kBlock, 0, c->stream>>>(K, (const double*)c->mom, t, c->rho, c->b,
                                                         c->partA);
     } else {
-      k_deposit_moments_mixed<<<nbn, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
-                                                             (float*)c->mom);
+      if (c->fused)
+        k_deposit_tiles_mixed<<<ntiles, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
+                                                                c->tile_c0, (float*)c->mom);
+      else
+        k_deposit_moments_mixed<<<nbn, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
+                                                               (float*)c->mom);
       k_node_rhs_mixed<<<nbn, kBlock, 0, c->stream>>>(K, (const float*)c->mom, t, c->rho, c->b,
                                                       c->partA);
     }
@@ -394,6 +460,7 @@ int field_solve(pic_ctx* c, double t) {
     a.s[k] = c->cgv + (int64_t)(4 + k) * K.nn;
   }
   a.p = c->cgv + 6 * (int64_t)K.nn;
+  a.pub = c->cgv;  // the brick solver's face buffers reuse the global solver's vectors
   a.part = c->partA;
   a.result = c->result;
   a.arrive = c->bar;
@@ -403,12 +470,16 @@ int field_solve(pic_ctx* c, double t) {
   a.relres_out = c->cgrr;
   a.tol = c->cg_tol;
   a.max_iter = c->cg_max_iter;
+  for (int d = 0; d < 3; ++d) {
+    a.bdim[d] = c->cg_bd[d];
+    a.nbr[d] = c->cg_nbr[d];
+  }
   SimConst Kc = K;
   void* args[] = {&Kc, &a};
   {
     StageTimer tm(c, PIC_STAGE_CG);
-    HIP_TRY(c, hipLaunchCooperativeKernel((const void*)k_cg, dim3(c->cg_grid), dim3(kBlock), args,
-                                          0, c->stream));
+    HIP_TRY(c, hipLaunchCooperativeKernel(cg_kernel(c->cg_q), dim3(c->cg_grid), dim3(kBlock), args,
+                                          c->cg_lds, c->stream));
   }
   StageTimer tm(c, PIC_STAGE_GRADIENT);
   k_gradient<<<nbn, kBlock, 0, c->stream>>>(K, c->phi, c->E, c->E32);
@@ -699,11 +770,45 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     return PIC_EHIP;
   }
   c->cg_grid = (int)std::min<int64_t>({(int64_t)ncu, (int64_t)ncu * per_cu, (int64_t)grid_for(c->K.nn)});
-  // PIC_CG_BLOCKS narrows the solver grid (fewer blocks make each grid-wide
-  // reduction cheaper and each sweep longer); it never exceeds the co-resident bound.
+  // PIC_CG_BLOCKS sets the solver grid wanted (fewer blocks make each grid-wide
+  // reduction cheaper and each sweep longer); it never exceeds the co-resident
+  // bound.  The brick solver is used when the mesh splits into bricks that
+  // fit; PIC_CG_GLOBAL=1 keeps the global-memory solver.
+  int target = c->cg_grid;
   if (const char* ev = std::getenv("PIC_CG_BLOCKS")) {
     int want = std::atoi(ev);
-    if (want >= 1) c->cg_grid = std::min(c->cg_grid, want);
+    if (want >= 1) {
+      target = want;
+      c->cg_grid = std::min(c->cg_grid, want);
+    }
+  }
+  const char* force_global = std::getenv("PIC_CG_GLOBAL");
+  if (!(force_global && std::atoi(force_global) == 1)) {
+    BrickChoice bc{};
+    // co-resident bound for the largest padded brick (64 KB of LDS)
+    int per_cu_b = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_cg_brick<16>, kBlock, 65536);
+    if (e == hipSuccess && per_cu_b >= 1 &&
+        choose_bricks(c->K.nc, ncu * per_cu_b, std::min(target, ncu), bc)) {
+      c->cg_q = bc.q;
+      for (int d = 0; d < 3; ++d) {
+        c->cg_bd[d] = bc.bd[d];
+        c->cg_nbr[d] = bc.nbr[d];
+      }
+      c->cg_grid = bc.nbr[0] * bc.nbr[1] * bc.nbr[2];
+      c->cg_lds = brick_lds_bytes(bc.bd);
+      // the chosen instance must be co-resident at this grid, else keep the global solver
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cg_kernel(c->cg_q), kBlock,
+                                                       c->cg_lds) != hipSuccess ||
+          (int64_t)per * ncu < c->cg_grid) {
+        c->cg_q = 0;
+        c->cg_lds = 0;
+        c->cg_grid = (int)std::min<int64_t>({(int64_t)ncu, (int64_t)ncu * per_cu,
+                                             (int64_t)grid_for(c->K.nn), (int64_t)target});
+      }
+    }
+    (void)hipGetLastError();
   }
 
   auto init = [&]() -> int {
@@ -835,6 +940,8 @@ int pic_stats(pic_ctx* c, pic_stats_t* out) {
   out->cg_relres = rr;
   out->n_accepted = (int64_t)cnt[kCntAccepted];
   out->n_gmax = (int64_t)cnt[kCntGmax];
+  out->cg_blocks = c->cg_grid;
+  for (int d = 0; d < 3; ++d) out->cg_brick[d] = c->cg_q ? c->cg_bd[d] : 0;
   return check_flags(c);
 }
 

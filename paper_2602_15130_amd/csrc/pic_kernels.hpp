@@ -376,6 +376,9 @@ struct CgArgs {
   double* relres_out;
   double tol;
   int max_iter;
+  double* pub;        // brick solver: published faces, [bricks][2][3][nh]
+  int bdim[3];        // brick solver: nodes per brick along each axis
+  int nbr[3];         // brick solver: bricks along each axis
 };
 
 __device__ inline bool spin_until(const unsigned* addr, unsigned want, int* flags) {
@@ -399,6 +402,11 @@ __device__ inline bool grid_sum(const CgArgs& a, double* vals, int nv, unsigned 
   __shared__ int ok;
   __shared__ double res[kMaxRed];
   double tot[kMaxRed];
+  // Every wave waits until its own global stores have reached L2 before the
+  // block barrier; thread 0's agent-scope release below then writes back L2
+  // and so publishes the whole block's stores with its flag.  (A workgroup
+  // barrier alone does not wait for outstanding vector-memory stores.)
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   for (int i = 0; i < nv; ++i) tot[i] = block_sum(vals[i], sh);
   if (threadIdx.x == 0) {
     for (int i = 0; i < nv; ++i) a.part[blockIdx.x * kMaxRed + i] = tot[i];

@@ -106,6 +106,58 @@ __global__ void __launch_bounds__(kBlock) k_deposit_moments_mixed(SimConst K, co
   }
 }
 
+// The compensated cell moments by cell-aligned tiles (see k_deposit_tiles_f64):
+// FP32 corner weights in parallel into LDS, then one lane per (cell, corner)
+// accumulates them in sorted order with the same Neumaier steps as
+// k_deposit_moments_mixed, so the two agree bit for bit.
+__device__ inline void cic_weights_mixed(const float o[3], float w[8]) {
+  float wx[2] = {1.0f - o[0], o[0]}, wy[2] = {1.0f - o[1], o[1]}, wz[2] = {1.0f - o[2], o[2]};
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) w[cz * 4 + cy * 2 + cx] = wx[cx] * wy[cy] * wz[cz];
+}
+
+__global__ void __launch_bounds__(kBlock) k_deposit_tiles_mixed(SimConst K, const float* off,
+                                                                const int* cstart,
+                                                                const int* tile_c0, float* mom) {
+  __shared__ float W[8 * kLdsSlots];
+  __shared__ int sh_i[4];
+  tile_range(K, tile_c0, cstart, blockIdx.x, sh_i);
+  const int c0 = sh_i[0], ncells = sh_i[1] - sh_i[0], s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
+  const bool lds = ns <= kLdsSlots;
+  const int NP = (int)K.np;
+  if (lds) {
+    for (int j = threadIdx.x; j < ns; j += kBlock) {
+      const int p = s0 + j;
+      float o[3] = {off[p], off[NP + p], off[2 * NP + p]}, w[8];
+      cic_weights_mixed(o, w);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) W[k * kLdsSlots + j] = w[k];
+    }
+    __syncthreads();
+  }
+  for (int l = threadIdx.x; l < 8 * ncells; l += kBlock) {
+    const int k = l & 7, c = c0 + (l >> 3);
+    const int a = cstart[c] - s0, e = cstart[c + 1] - s0;
+    float sum = 0.0f, comp = 0.0f;
+    if (lds) {
+      for (int j = a; j < e; ++j) neumaier_add(sum, comp, W[k * kLdsSlots + j]);
+    } else {
+      for (int j = a; j < e; ++j) {
+        const int p = s0 + j;
+        float o[3] = {off[p], off[NP + p], off[2 * NP + p]}, w[8];
+        cic_weights_mixed(o, w);
+        neumaier_add(sum, comp, w[k]);
+      }
+    }
+    mom[(int64_t)k * K.nn + c] = sum;
+    mom[(int64_t)(8 + k) * K.nn + c] = comp;
+  }
+}
+
 // Node charge from the compensated FP32 cell moments (summed in FP64) and the
 // right-hand side of eq. poisson_mms; block partial sums of b.
 __global__ void __launch_bounds__(kBlock) k_node_rhs_mixed(SimConst K, const float* mom, double t,

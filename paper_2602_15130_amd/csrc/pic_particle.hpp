@@ -253,6 +253,76 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
   __syncthreads();
 }
 
+// Tile bounds of block b: first cell, cell count, first particle, particle count.
+__device__ inline void tile_range(const SimConst& K, const int* tile_c0, const int* cstart, int b,
+                                  int* sh_i) {
+  if (threadIdx.x == 0) {
+    int c0 = min(tile_c0[b], K.nn);
+    int c1 = min(max(tile_c0[b + 1], c0), K.nn);
+    sh_i[0] = c0;
+    sh_i[1] = c1;
+    sh_i[2] = cstart[c0];
+    sh_i[3] = cstart[c1];
+  }
+  __syncthreads();
+}
+
+// Eight cloud-in-cell corner weights of an FP64 position, corner k = cz 4 + cy 2 + cx.
+__device__ inline void cic_weights_f64(const SimConst& K, const double xp[3], double w[8]) {
+  int ci[3];
+  double o[3];
+  locate(K, xp, ci, o);
+  double wx[2] = {1.0 - o[0], o[0]}, wy[2] = {1.0 - o[1], o[1]}, wz[2] = {1.0 - o[2], o[2]};
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) w[cz * 4 + cy * 2 + cx] = wx[cx] * wy[cy] * wz[cz];
+}
+
+// Cell moments (the eight corner-weight sums of each cell) by cell-aligned
+// tiles: the particles of a tile compute their weights in parallel into LDS,
+// then one lane per (cell, corner) adds its cell's weights in sorted order,
+// the order of the per-cell loop of k_deposit_moments_f64, so the two agree
+// bit for bit.  Tiles larger than the LDS slots read the positions directly.
+__global__ void __launch_bounds__(kBlock) k_deposit_tiles_f64(SimConst K, const double* x,
+                                                              const int* cstart,
+                                                              const int* tile_c0, double* mom) {
+  __shared__ double W[8 * kLdsSlots];
+  __shared__ int sh_i[4];
+  tile_range(K, tile_c0, cstart, blockIdx.x, sh_i);
+  const int c0 = sh_i[0], ncells = sh_i[1] - sh_i[0], s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
+  const bool lds = ns <= kLdsSlots;
+  const int NP = (int)K.np;
+  if (lds) {
+    for (int j = threadIdx.x; j < ns; j += kBlock) {
+      const int p = s0 + j;
+      double xp[3] = {x[p], x[NP + p], x[2 * NP + p]}, w[8];
+      cic_weights_f64(K, xp, w);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) W[k * kLdsSlots + j] = w[k];
+    }
+    __syncthreads();
+  }
+  for (int l = threadIdx.x; l < 8 * ncells; l += kBlock) {
+    const int k = l & 7, c = c0 + (l >> 3);
+    const int a = cstart[c] - s0, e = cstart[c + 1] - s0;
+    double m = 0.0;
+    if (lds) {
+      for (int j = a; j < e; ++j) m += W[k * kLdsSlots + j];
+    } else {
+      for (int j = a; j < e; ++j) {
+        const int p = s0 + j;
+        double xp[3] = {x[p], x[NP + p], x[2 * NP + p]}, w[8];
+        cic_weights_f64(K, xp, w);
+        m += w[k];
+      }
+    }
+    mom[(int64_t)k * K.nn + c] = m;
+  }
+}
+
 __device__ inline void gather_f64(const SimConst& K, const double* E, const double xp[3], double ep[3],
                                   int c[3]) {
   double o[3];

@@ -53,7 +53,8 @@ class pic_error_norms(C.Structure):
 
 class pic_stats_t(C.Structure):
     _fields_ = [("step", C.c_int64), ("cg_iters", C.c_int), ("cg_relres", C.c_double),
-                ("n_accepted", C.c_int64), ("n_gmax", C.c_int64)]
+                ("n_accepted", C.c_int64), ("n_gmax", C.c_int64),
+                ("cg_blocks", C.c_int), ("cg_brick", C.c_int * 3)]
 
 
 def _load():
@@ -165,7 +166,8 @@ def pic_stats(ctx) -> dict:
     s = pic_stats_t()
     _check(lib.pic_stats(ctx, C.byref(s)), ctx)
     return {"step": s.step, "cg_iters": s.cg_iters, "cg_relres": s.cg_relres,
-            "n_accepted": s.n_accepted, "n_gmax": s.n_gmax}
+            "n_accepted": s.n_accepted, "n_gmax": s.n_gmax,
+            "cg_blocks": s.cg_blocks, "cg_brick": list(s.cg_brick)}
 
 
 def pic_get_state(ctx, item: int, out: np.ndarray):

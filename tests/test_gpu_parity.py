@@ -300,3 +300,48 @@ def test_fused_pass_large_cells_use_global_scratch():
         o.step(1)
         _compare_state(P, g, o, prob, disc, phi_tol=_kappa(disc["nc"]) * 1e-13, xv_tol=1e-11,
                        tag=f"large cells step {s + 1}")
+
+
+# ----------------------------------------------------------------------------- Poisson solvers
+def _with_env(name, value, fn):
+    import os
+    old = os.environ.get(name)
+    os.environ[name] = value
+    try:
+        return fn()
+    finally:
+        if old is None:
+            os.environ.pop(name)
+        else:
+            os.environ[name] = old
+
+
+@pytest.mark.parametrize("n,blocks", [(8, 0), (16, 0), (32, 0), (32, 16), (64, 0)])
+def test_brick_solver_matches_global_solver_and_oracle(n, blocks):
+    """The on-chip brick CG and the global-memory CG run the same recurrence
+    and differ only in the order of the block partial sums; both stop at
+    ||r|| <= tol ||b||, so phi agrees within kappa * tol, and with the oracle.
+    Covers one brick, several bricks and (blocks=16) bricks of 2048 nodes."""
+    prob = W.cfg_problem(two_way=True, collisions=False)
+    disc = W.cfg_disc(n, 32 * n**3 if n <= 32 else 4 * n**3, 5e-4, 1, 1, cg_tol=1e-13)
+    P = _pic()
+    mk = lambda: P.Sim(prob, disc, 3, 0)  # noqa: E731
+    g = _with_env("PIC_CG_BLOCKS", str(blocks), mk) if blocks else mk()
+    st = g.stats()
+    assert st["cg_brick"][0] > 0, f"brick solver not selected for {n}^3: {st}"
+    h = _with_env("PIC_CG_GLOBAL", "1", mk)
+    assert h.stats()["cg_brick"] == [0, 0, 0]
+    pg, ph = g.get(P.STATE_PHI), h.get(P.STATE_PHI)
+    kap = _kappa(disc["nc"])
+    assert _rel(pg, ph, np.abs(ph).max()) < kap * 1e-13
+    assert abs(st["cg_iters"] - h.stats()["cg_iters"]) <= 1
+    g.step(2)
+    h.step(2)
+    pg, ph = g.get(P.STATE_PHI), h.get(P.STATE_PHI)
+    assert _rel(pg, ph, np.abs(ph).max()) < kap * 1e-13
+    if n <= 16:
+        o = O.Sim(prob, disc, 3, 0)
+        assert o.init() == 0
+        o.step(2)
+        po = o.get(o.PHI)
+        assert _rel(pg, po, np.abs(po).max()) < kap * 1e-13
