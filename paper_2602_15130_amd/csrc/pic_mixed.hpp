@@ -284,14 +284,16 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 }
 
 // The mixed-form fused pass (configuration family), same phases as the FP64 one.
+// Registers are capped for six waves per SIMD (measured best at 64^3: the pass
+// is latency bound, and the extra resident waves outweigh the spills).
 template <int SIG>
-__global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
+__global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
   __shared__ float lv0[3 * kLdsSlots], lu[3 * kLdsSlots], lD[3 * kLdsSlots];
   __shared__ int lmark[kLdsSlots], ltl[kLdsSlots];
-  __shared__ int evt[kMaxEvents];
-  __shared__ int sh_i[6];
+  __shared__ CollideLds<float> cl;
+  __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;
   if (tid == 0) {
@@ -346,7 +348,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
 
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                             evt, &sh_i[4], &sh_i[5]);
+                             cl);
     for (int j = tid; j < ns; j += kBlock) {
       int c = a.key[s0 + j];
       int n = a.cstart[c + 1] - a.cstart[c];
@@ -364,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
   if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
     if (K.collisions)
       tile_collide<SIG, float>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                               evt, &sh_i[4], &sh_i[5]);
+                               cl);
     for (int j = tid; j < ns; j += kBlock) kick(j, M.emB, K.collisions != 0);
     __syncthreads();
     if (!(a.mode & kDoA)) {
@@ -377,7 +379,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_mixed(SimConst K, MixConst
   // call A at t^{na}, first half kick, drift to t^{na+1}
   if (K.collisions)
     tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
-                             st, evt, &sh_i[4], &sh_i[5]);
+                             st, cl);
   for (int base = 0; base < ns; base += kBlock) {
     int j = base + tid;
     bool valid = j < ns;

@@ -13,10 +13,13 @@
 //
 // Collisions in a tile: (1) one lane per (cell, outcome) draws N_pairs
 // (Algorithm 1) and records the few lanes that have candidate pairs; (2) one
-// thread per cell runs those outcomes in increasing outcome order on a private
-// copy of its cell's velocities and accumulates <dv> in that order, exactly as
-// eq. avg_outcome sums them.  If the event list of a tile overflows, step (2)
-// redraws N_pairs for every outcome itself.
+// lane per such outcome with at most kSmallPairs pairs runs it on a private
+// list of the velocities it changes and stores the changes; (3) one thread per
+// cell adds, in increasing outcome order, the stored changes and runs the
+// remaining outcomes itself on a copy-on-write private copy of its cell's
+// velocities, so <dv> is summed exactly in the order of eq. avg_outcome.  If
+// the event list of a tile overflows, step (3) redraws N_pairs for every
+// outcome itself.
 #pragma once
 
 #include "pic_kernels.hpp"
@@ -25,7 +28,23 @@ namespace pic {
 
 constexpr int kTileB = 256;       // particle slots that start cells in one tile
 constexpr int kLdsSlots = 384;    // LDS-resident slots per tile
-constexpr int kMaxEvents = 512;   // (cell, outcome) lanes with pairs per tile
+constexpr int kMaxEvents = 192;   // (cell, outcome) lanes with pairs per tile
+constexpr int kSmallPairs = 4;    // outcomes with at most this many pairs run one per lane
+constexpr int kPool = 64;         // velocity-change records of those outcomes per tile
+
+// LDS of one collision call over a tile: the events ((cell, outcome) lanes
+// with candidate pairs), their pair counts, and the velocity changes of the
+// outcomes run one per lane (record start | count << 16, or -1 when the
+// outcome is left to its cell's thread).
+template <class R>
+struct CollideLds {
+  int evt[kMaxEvents];
+  int evn[kMaxEvents];
+  int evp[kMaxEvents];
+  int n_evt, overflow, pool_n;
+  int pslot[kPool];
+  R pdv[3 * kPool];
+};
 
 enum { kDoB = 1, kDoA = 2, kCollideOnly = 4 };
 
@@ -167,33 +186,112 @@ __device__ inline int64_t npairs_of(const SimConst& K, int cell, int64_t step, i
 
 
 
+// One outcome of Algorithm 1 with at most kSmallPairs candidate pairs, run by
+// one lane: the velocities the outcome changes are kept in the lane's own
+// records of the pool (slot in pslot, current value in pdv), everything else
+// is read from v0; at the end the records are turned into velocity changes.
+// Same arithmetic as ntc_outcome.  Returns the number of records.
+template <int SIG, class R>
+__device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t step, int call, int k,
+                                        int npairs, int n, const R* v0, int st, int* pslot, R* pdv,
+                                        long long* pairlog, int64_t cap,
+                                        unsigned long long* counters, unsigned long long& acc,
+                                        unsigned long long& gmx) {
+  const R sgmax = (R)K.sgmax, gmax = (R)K.g_max;
+  int cnt = 0;
+  for (int m = 0; m < npairs; ++m) {
+    U64x4 wa = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call,
+                            (uint64_t)k, (uint64_t)(1 + 2 * m));
+    U64x4 wb = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call,
+                            (uint64_t)k, (uint64_t)(2 + 2 * m));
+    int p = index_below(wa.w[0], n);
+    int q = pick_partner(K, cell, step, call, k, m, wa, wb, p, n);
+    int ip = -1, iq = -1;
+    for (int t = 0; t < cnt; ++t) {
+      if (pslot[t] == p) ip = t;
+      if (pslot[t] == q) iq = t;
+    }
+    R up[3], uq[3];
+    for (int d = 0; d < 3; ++d) {
+      up[d] = ip >= 0 ? pdv[d * kPool + ip] : v0[d * st + p];
+      uq[d] = iq >= 0 ? pdv[d * kPool + iq] : v0[d * st + q];
+    }
+    R dx = up[0] - uq[0], dy = up[1] - uq[1], dz = up[2] - uq[2];
+    R g = sqrt(dx * dx + dy * dy + dz * dz);
+    if (g > gmax) ++gmx;
+    bool ok = unif_r<R>(wa.w[2]) < sigma_g_r<SIG, R>(K, g) / sgmax;
+    if (ok) {
+      ++acc;
+      R eps = (R)2.0 * (R)kPi * unif_r<R>(wa.w[3]);
+      R cchi = (R)1.0 - (R)2.0 * unif_r<R>(wb.w[0]);  // eq. chi_iso
+      R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
+      R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
+      if (ip < 0) {
+        ip = cnt++;
+        pslot[ip] = p;
+      }
+      if (iq < 0) {
+        iq = cnt++;
+        pslot[iq] = q;
+      }
+      for (int d = 0; d < 3; ++d) {
+        R vcm = (R)0.5 * (up[d] + uq[d]);
+        pdv[d * kPool + ip] = vcm + (R)0.5 * g * nv[d];
+        pdv[d * kPool + iq] = vcm - (R)0.5 * g * nv[d];
+      }
+    }
+    if (pairlog) {
+      unsigned long long s = atomicAdd(&counters[kCntPairLog], 1ull);
+      if ((int64_t)s < cap) {
+        long long* r = pairlog + 7 * s;
+        r[0] = cell; r[1] = call; r[2] = k; r[3] = m; r[4] = p; r[5] = q; r[6] = ok;
+      }
+    }
+  }
+  for (int t = 0; t < cnt; ++t)
+    for (int d = 0; d < 3; ++d) pdv[d * kPool + t] = pdv[d * kPool + t] - v0[d * st + pslot[t]];
+  return cnt;
+}
+
 // The outcomes of one cell that have candidate pairs, in increasing outcome
 // order, summed into D (eq. avg_outcome; the division by N_avg is done where D
-// is read).  Only the particles an outcome changed contribute to the sum; the
-// others would add exact zeros.
+// is read).  Outcomes already run by a lane contribute their stored changes;
+// the others run here.  Only the particles an outcome changed contribute to
+// the sum; the others would add exact zeros.
 template <int SIG, class R>
 __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
                                      int c, int ci, int cs, int n, const R* v0, R* u, R* D,
-                                     int* mark, int* tl, int tagbase, int st, const int* evt,
-                                     int ne, bool all, unsigned long long& acc,
-                                     unsigned long long& gmx) {
+                                     int* mark, int* tl, int tagbase, int st,
+                                     const CollideLds<R>& L, int ne, bool all,
+                                     unsigned long long& acc, unsigned long long& gmx) {
   const int navg = K.navg;
   int last = -1;
   for (int it = 0; it < navg; ++it) {
-    int k;
+    int k, ev = -1;
     if (all) {
       k = it;
     } else {  // next event of this cell in increasing outcome order
       k = navg;
       for (int e = 0; e < ne; ++e) {
-        int l = evt[e];
+        int l = L.evt[e];
         int eci = l / navg, ek = l - eci * navg;
-        if (eci == ci && ek > last && ek < k) k = ek;
+        if (eci == ci && ek > last && ek < k) {
+          k = ek;
+          ev = e;
+        }
       }
       if (k == navg) break;
     }
     last = k;
-    int64_t np_ = npairs_of(K, c, step, call, k, n, a.flags);
+    if (ev >= 0 && L.evp[ev] >= 0) {  // run by a lane: add its stored changes
+      const int r0 = L.evp[ev] & 0xffff, nr = L.evp[ev] >> 16;
+      for (int t = 0; t < nr; ++t) {
+        int j = cs + L.pslot[r0 + t];
+        for (int d = 0; d < 3; ++d) D[d * st + j] += L.pdv[d * kPool + r0 + t];
+      }
+      continue;
+    }
+    int64_t np_ = ev >= 0 ? (int64_t)L.evn[ev] : npairs_of(K, c, step, call, k, n, a.flags);
     if (np_ <= 0) continue;
     int ntl = 0;
     ntc_outcome<SIG, R>(K, c, step, call, k, np_, n, v0 + cs, u + cs, mark + cs, tagbase + k + 1,
@@ -212,40 +310,73 @@ template <int SIG, class R>
 __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
                                     int64_t step, int c0, int ncells, int s0, int ns,
                                     const R* v0, R* u, R* D, int* mark, int* tl, int tagbase,
-                                    int st, int* evt, int* evt_n, int* overflow) {
+                                    int st, CollideLds<R>& L) {
   const int tid = threadIdx.x;
   if (tid == 0) {
-    *evt_n = 0;
-    *overflow = 0;
+    L.n_evt = 0;
+    L.overflow = 0;
+    L.pool_n = 0;
   }
   for (int j = tid; j < ns; j += kBlock) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
   __syncthreads();
   const int navg = K.navg;
   const int64_t lanes = (int64_t)ncells * navg;
+  // (1) N_pairs of every (cell, outcome)
   for (int64_t l = tid; l < lanes; l += kBlock) {
     int ci = (int)(l / navg), k = (int)(l - (int64_t)ci * navg);
     int c = c0 + ci;
     int n = a.cstart[c + 1] - a.cstart[c];
     if (n < 2) continue;
-    if (npairs_of(K, c, step, call, k, n, a.flags) > 0) {
-      int e = atomicAdd(evt_n, 1);
-      if (e < kMaxEvents) evt[e] = (int)l; else *overflow = 1;
+    int64_t np_ = npairs_of(K, c, step, call, k, n, a.flags);
+    if (np_ > 0) {
+      int e = atomicAdd(&L.n_evt, 1);
+      if (e < kMaxEvents) {
+        L.evt[e] = (int)l;
+        L.evn[e] = (int)np_;
+      } else {
+        L.overflow = 1;
+      }
     }
   }
   __syncthreads();
-  const int ne = min(*evt_n, kMaxEvents);
-  const bool all = *overflow != 0;
+  const int ne = min(L.n_evt, kMaxEvents);
+  const bool all = L.overflow != 0;
   unsigned long long acc = 0, gmx = 0;
+  // (2) small outcomes, one per lane, into the record pool
+  if (!all) {
+    for (int e = tid; e < ne; e += kBlock) {
+      int np_ = L.evn[e];
+      int start = -1;
+      if (np_ <= kSmallPairs) {
+        start = atomicAdd(&L.pool_n, 2 * np_);
+        if (start + 2 * np_ > kPool) start = -1;
+      }
+      if (start < 0) {
+        L.evp[e] = -1;
+        continue;
+      }
+      int l = L.evt[e];
+      int ci = l / navg, k = l - ci * navg;
+      int c = c0 + ci;
+      int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
+      int cnt = ntc_outcome_small<SIG, R>(K, c, step, call, k, np_, n, v0 + cs, st,
+                                          L.pslot + start, L.pdv + start, a.pairlog, a.cap,
+                                          a.counters, acc, gmx);
+      L.evp[e] = start | (cnt << 16);
+    }
+    __syncthreads();
+  }
+  // (3) per cell, in increasing outcome order
   for (int ci = tid; ci < ncells; ci += kBlock) {
     int c = c0 + ci;
     int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
     if (n < 2) continue;
     if (!all) {  // skip cells without events quickly
       bool any = false;
-      for (int e = 0; e < ne; ++e) any |= (evt[e] / navg) == ci;
+      for (int e = 0; e < ne; ++e) any |= (L.evt[e] / navg) == ci;
       if (!any) continue;
     }
-    cell_outcomes<SIG, R>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, evt, ne,
+    cell_outcomes<SIG, R>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, L, ne,
                           all, acc, gmx);
   }
   if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
@@ -371,13 +502,15 @@ __device__ inline void half_kick_f64(const SimConst& K, const double xp[3], cons
   }
 }
 
-// LDS (three tile arrays) allows four workgroups per CU; ask for registers to match.
+// LDS (three tile arrays) allows four workgroups per CU; registers are capped
+// to match (four waves per SIMD), accepting a few spills: the pass is latency
+// bound and gains more from resident waves than it loses to spill traffic.
 template <int FAM, int SIG>
-__global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a) {
+__global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArgs a) {
   __shared__ double lv0[3 * kLdsSlots], lu[3 * kLdsSlots], lD[3 * kLdsSlots];
   __shared__ int lmark[kLdsSlots], ltl[kLdsSlots];
-  __shared__ int evt[kMaxEvents];
-  __shared__ int sh_i[6];
+  __shared__ CollideLds<double> cl;
+  __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;
   if (tid == 0) {
@@ -409,7 +542,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
 
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                              evt, &sh_i[4], &sh_i[5]);
+                              cl);
     for (int j = tid; j < ns; j += kBlock) {
       int c = a.key[s0 + j];
       int n = a.cstart[c + 1] - a.cstart[c];
@@ -429,7 +562,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
     const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
     if (K.collisions)
       tile_collide<SIG, double>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                                evt, &sh_i[4], &sh_i[5]);
+                                cl);
     for (int j = tid; j < ns; j += kBlock) {
       int p = s0 + j;
       double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
@@ -457,7 +590,7 @@ __global__ void __launch_bounds__(kBlock) k_particles_f64(SimConst K, PartArgs a
   const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
   if (K.collisions)
     tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
-                              st, evt, &sh_i[4], &sh_i[5]);
+                              st, cl);
   for (int base = 0; base < ns; base += kBlock) {
     int j = base + tid;
     bool valid = j < ns;
