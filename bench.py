@@ -65,6 +65,29 @@ def cpu_baseline(prob, disc, seed):
                       f"{disc['nc'][0]}^3 mesh), single-threaded FP64 C, {dt:.1f} s"}
 
 
+def convergence_report(pic, W, levels=(0, 1, 2, 3)):
+    """Observed orders of the FP64 and mixed forms on the refinement ladder
+    (one-way, collisionless: second order in h and dt), from the l2 norms of
+    x, y, z, u, v, w and phi at t = 0.01."""
+    ladder = W.order_ladder(levels)
+    rep = {"ladder": "mesh 8^3 * 2^l, 8 particles per cell, dt 1e-3 / 2^l, t = 0.01, "
+                     "one-way, collisionless", "levels": [L["disc"]["nc"][0] for L in ladder]}
+    orders = {}
+    for precision in ("fp64", "mixed"):
+        norms = []
+        for L in ladder:
+            g = pic.Sim(L["problem"], L["disc"], 1, 0, precision)
+            g.step(L["disc"]["steps"])
+            norms.append(list(g.errors()["l2"]))
+            del g
+        orders[precision] = W.observed_orders(norms)
+        rep[precision] = {"l2": [[float("%.6g" % v) for v in n] for n in norms],
+                          "orders": [[round(v, 4) for v in o] for o in orders[precision]]}
+    gap = max(abs(a - b) for oa, ob in zip(orders["fp64"], orders["mixed"]) for a, b in zip(oa, ob))
+    rep["max_order_gap"] = round(gap, 5)
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +97,7 @@ def main():
     ap.add_argument("--beside", default="cfg2",
                     help="second workload timed beside the first (the FP64 form); 'none' to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-convergence", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the path is built and measured on a single "
@@ -88,6 +112,8 @@ def main():
         b = run_workload(pic, W, torch, args.beside, args.steps, args.warmup)
         out["beside"] = {k: b[k] for k in ("value", "ms_per_step", "dtype", "config", "roofline",
                                            "roofline_particle_path", "stages")}
+    if not args.no_convergence:
+        out["convergence"] = convergence_report(pic, W)
     if not args.no_cpu_baseline:
         c = W.get(args.workload)
         out["cpu_baseline"] = cpu_baseline(c["problem"], c["disc"], c["seed"])

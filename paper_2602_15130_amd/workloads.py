@@ -127,5 +127,27 @@ def ensemble_levels(n_levels=5):
     return out
 
 
+def order_ladder(levels=(0, 1, 2, 3), two_way=False, collisions=False, navg=1):
+    """Refinement ladder for observed orders: the ensemble sizing (mesh 8^3 * 2^l,
+    8 particles per cell, dt 1e-3 / 2^l, 10 * 2^l steps to t = 0.01).  One-way
+    and collisionless by default, where every error source is O(h^2) and
+    O(dt^2) and the particle count adds no noise (the field solve sees only
+    the manufactured source)."""
+    out = []
+    for lvl in levels:
+        nc = 8 << lvl
+        out.append({"level": lvl,
+                    "problem": cfg_problem(two_way=two_way, collisions=collisions),
+                    "disc": cfg_disc(nc, 8 * nc**3, 1e-3 / 2**lvl, 10 * 2**lvl, navg)})
+    return out
+
+
+def observed_orders(norms):
+    """log2 ratios of successive error norms (h halves per level)."""
+    import math
+    return [[math.log2(a / b) if a > 0 and b > 0 else float("nan") for a, b in zip(n0, n1)]
+            for n0, n1 in zip(norms, norms[1:])]
+
+
 def get(name: str) -> dict:
     return copy.deepcopy(CONFIGS[name])

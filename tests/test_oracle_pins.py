@@ -696,3 +696,18 @@ def test_collisionless_one_way_second_order():
     # positions, velocities and phi: slopes close to 2
     assert np.all(p[:7] > 1.7), p
     assert np.all(p[:7] < 2.4), p
+
+
+def test_cfg_family_one_way_collisionless_is_second_order():
+    """Sec. 5: with the field solve seeing only the manufactured source and no
+    collisions, every error source is second order; the configuration family
+    on the 8^3 -> 16^3 ladder step (8 particles per cell, dt halved) shows it
+    for positions, velocities and phi."""
+    norms = []
+    for L in W.order_ladder((0, 1)):
+        o = O.Sim(L["problem"], L["disc"], 1, 0)
+        assert o.init() == 0
+        o.step(L["disc"]["steps"])
+        norms.append(o.errors()["l2"])
+    orders = np.array(W.observed_orders(norms)[0])
+    assert np.all((orders > 1.75) & (orders < 2.25)), orders
