@@ -16,6 +16,7 @@
 #include "pic_particle.hpp"
 #include "pic_mixed.hpp"
 #include "pic_cg_brick.hpp"
+#include "pic_lowmode.hpp"
 
 using namespace pic;
 
@@ -30,7 +31,7 @@ enum Arr {
   A_X0, A_X1, A_V0, A_V1, A_SH0, A_SH1, A_ID0, A_ID1,  // FP64 particle state, two buffers
   A_OFF0, A_OFF1, A_VF0, A_VF1, A_ASF0, A_ASF1,      // mixed particle state, two buffers
   A_KEY, A_SLOT, A_TIDX, A_TKEY, A_D, A_U, A_V0G,
-  A_COUNT, A_CSTART, A_BSUM, A_TILE, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_CGV,
+  A_COUNT, A_CSTART, A_BSUM, A_TILE, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_CGV, A_LOW,
   A_PART_A, A_PART_B, A_EPART, A_NPART, A_NORMS, A_BAR, A_RESULT, A_FLAGS, A_CNT, A_CGIT, A_CGRR,
   A_NARR
 };
@@ -64,6 +65,11 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_MOM] = 64 * nn;  // 8 FP64 cell moments, or 8 FP32 moments + 8 compensations
   b[A_RHO] = b[A_B] = b[A_PHI] = nn * 8;
   b[A_CGV] = 7 * nn * 8;  // CG vectors r, w, s (two each) and p
+  {  // low-mode pre-solve: basis tables, eigenvalues, three transform buffers
+    const int64_t nmax = std::max({d->ncell[0], d->ncell[1], d->ncell[2]});
+    b[A_LOW] = (3 * kLowMaxM * nmax + 3 * kLowMaxM + (int64_t)kLowMaxM * d->ncell[1] * d->ncell[2] +
+                (int64_t)kLowMaxM * kLowMaxM * d->ncell[2] + (int64_t)kLowMaxM * kLowMaxM * d->ncell[0]) * 8;
+  }
   b[A_E] = 3 * nn * 8;
   b[A_E32] = f64 ? 0 : 3 * nn * 4;
   b[A_PART_A] = b[A_PART_B] = std::max<int64_t>(nblk_n, 4096) * 8;
@@ -260,6 +266,8 @@ struct pic_ctx {
   int cg_bd[3] = {0, 0, 0};     // brick dimensions
   int cg_nbr[3] = {0, 0, 0};    // bricks per axis
   size_t cg_lds = 0;            // padded brick, bytes of LDS
+  int low_k = 0;                // Fourier modes per axis solved exactly before the CG
+  LowArgs low{};
   bool ready = false;
   int64_t step = 0;
   int cur = 0;
@@ -278,7 +286,7 @@ struct pic_ctx {
   float* Df{};
   bool fused = true;
   void* mom{};
-  double *rho{}, *b{}, *phi{}, *E{}, *cgv{}, *partA{}, *partB{};
+  double *rho{}, *b{}, *phi{}, *E{}, *cgv{}, *lowbuf{}, *partA{}, *partB{};
   float* E32{};
   double *epart{}, *npart{}, *norms{}, *cgrr{}, *result{};
   unsigned* bar{};
@@ -448,6 +456,15 @@ int field_solve(pic_ctx* c, double t) {
     }
     k_sub_mean<<<nbn, kBlock, 0, c->stream>>>(K, c->b, c->partA, nbn);
     LAUNCH_CHECK(c, "rhs");
+  }
+  if (c->low_k > 0) {  // exact solve of the low Fourier modes of the residual
+    StageTimer tm(c, PIC_STAGE_CG);
+    const LowArgs& L = c->low;
+    k_low_project_x<<<K.nc[1] * K.nc[2], 64, 0, c->stream>>>(K, L, c->b, c->phi);
+    k_low_project_y<<<grid_for((int64_t)L.m[0] * L.m[1] * K.nc[2]), kBlock, 0, c->stream>>>(K, L);
+    k_low_solve<<<1, 1024, 0, c->stream>>>(K, L);
+    k_low_correct<<<nbn, kBlock, 0, c->stream>>>(K, L, c->phi);
+    LAUNCH_CHECK(c, "low-mode solve");
   }
   // arrival flags of every block plus the release word, zeroed before each launch
   TRY(fill<unsigned>(c, c->bar, 0u, (int64_t)(c->cg_grid + 1) * kFlagStride));
@@ -746,6 +763,7 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   c->E = carve<double>(c, A_E);
   c->E32 = carve<float>(c, A_E32);
   c->cgv = carve<double>(c, A_CGV);
+  c->lowbuf = carve<double>(c, A_LOW);
   c->partA = carve<double>(c, A_PART_A);
   c->partB = carve<double>(c, A_PART_B);
   c->epart = carve<double>(c, A_EPART);
@@ -810,6 +828,25 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     }
     (void)hipGetLastError();
   }
+  // PIC_CG_LOWMODES: Fourier modes per axis solved exactly before the CG (default
+  // 4, at most kLowMaxK; 0 switches the pre-solve off).
+  {
+    int kl = kLowMaxK;
+    if (const char* ev = std::getenv("PIC_CG_LOWMODES")) kl = std::max(0, std::min(kLowMaxK, std::atoi(ev)));
+    int nmax = std::max({c->K.nc[0], c->K.nc[1], c->K.nc[2]});
+    int md[3];
+    for (int d = 0; d < 3; ++d) md[d] = 2 * std::min(kl, (c->K.nc[d] - 1) / 2) + 1;
+    c->low_k = (md[0] * md[1] * md[2] > 1) ? kl : 0;
+    LowArgs& L = c->low;
+    for (int d = 0; d < 3; ++d) L.m[d] = md[d];
+    L.nmax = nmax;
+    double* base = c->lowbuf;
+    L.tab = base;
+    L.mu = base + 3 * kLowMaxM * nmax;
+    L.t1 = base + 3 * kLowMaxM * nmax + 3 * kLowMaxM;
+    L.t2 = L.t1 + (int64_t)kLowMaxM * c->K.nc[1] * c->K.nc[2];
+    L.d1 = L.t2 + (int64_t)kLowMaxM * kLowMaxM * c->K.nc[2];
+  }
 
   auto init = [&]() -> int {
     const SimConst& K = c->K;
@@ -817,6 +854,11 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     TRY(fill<unsigned long long>(c, c->cnt, 0ull, kCntCount));
     TRY(fill<int>(c, c->count, 0, K.nn));
     TRY(fill<double>(c, c->phi, 0.0, K.nn));
+    if (c->low_k > 0) {
+      k_low_tables<<<grid_for((int64_t)3 * kLowMaxM * c->low.nmax), kBlock, 0, c->stream>>>(
+          K, c->low, (double*)c->low.tab, (double*)c->low.mu);
+      LAUNCH_CHECK(c, "low-mode tables");
+    }
     // unsorted initial state in buffer 1, sorted into buffer 0
     c->cur = 1;
     if (c->precision == PIC_FP64)
