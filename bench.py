@@ -98,7 +98,20 @@ def main():
                     help="second workload timed beside the first (the FP64 form); 'none' to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes five times (reference for "
+                         "hardware byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU: the path is built and measured on a single "
               "MI355X (the multi-GPU sharding is a design, not a measured run)", file=sys.stderr)

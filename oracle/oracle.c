@@ -22,7 +22,7 @@
 #define PI_D 3.14159265358979323846264338327950288
 #define TWO_PI_D 6.28318530717958647692528676655900577
 
-enum { TAG_INIT = 1, TAG_COLL = 2, TAG_REDRAW = 3 };
+enum { TAG_INIT = 1, TAG_COLL = 2, TAG_REDRAW = 3, TAG_NPAIRS = 4 };
 
 /* ======================================================================== */
 /* Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11, "Parallel random       */
@@ -767,11 +767,14 @@ int orc_collide_cell(const orc_problem* P, const orc_disc* D, uint64_t seed, uin
   double* u = (double*)malloc(sizeof(double) * 3 * (size_t)n);
   for (int k = 0; k < D->navg; ++k) {
     for (int64_t j = 0; j < 3 * n; ++j) u[j] = v[j];
+    /* the N_pairs uniform of outcome k: word k mod 4 of the NPAIRS block of
+     * outcome group k / 4 (four outcomes share one block) */
     uint64_t w0[4];
-    rng_block(seed, rep, (uint64_t)cell, (uint64_t)step, TAG_COLL, (uint64_t)call, (uint64_t)k, 0,
-              w0);
+    rng_block(seed, rep, (uint64_t)cell, (uint64_t)step, TAG_NPAIRS, (uint64_t)call,
+              (uint64_t)(k >> 2), 0, w0);
     /* N_pairs = floor(N (N - 1) P_max / 2 + rand) */
-    int64_t npairs = (int64_t)floor((double)n * (double)(n - 1) * pmax / 2.0 + orc_u01(w0[0]));
+    int64_t npairs =
+        (int64_t)floor((double)n * (double)(n - 1) * pmax / 2.0 + orc_u01(w0[k & 3]));
     for (int64_t m = 0; m < npairs; ++m) {
       uint64_t wa[4], wb[4];
       rng_block(seed, rep, (uint64_t)cell, (uint64_t)step, TAG_COLL, (uint64_t)call, (uint64_t)k,

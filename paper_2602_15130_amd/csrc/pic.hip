@@ -61,7 +61,7 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_COUNT] = nn * 4;
   b[A_CSTART] = (nn + 1) * 4;
   b[A_BSUM] = (nscan + 1) * 4;
-  b[A_TILE] = ((np + kTileB - 1) / kTileB + 2) * 4;
+  b[A_TILE] = 2 * ((np + kTileB - 1) / kTileB + 2) * 4;  // first cell and first particle per tile
   b[A_MOM] = 64 * nn;  // 8 FP64 cell moments, or 8 FP32 moments + 8 compensations
   b[A_RHO] = b[A_B] = b[A_PHI] = nn * 8;
   b[A_CGV] = 7 * nn * 8;  // CG vectors r, w, s (two each) and p
@@ -281,7 +281,7 @@ struct pic_ctx {
   float* off[2]{};
   float* vf[2]{};
   float* asf[2]{};
-  int *key{}, *slot{}, *tidx{}, *tkey{}, *count{}, *cstart{}, *bsum{}, *tile_c0{};
+  int *key{}, *slot{}, *tidx{}, *tkey{}, *count{}, *cstart{}, *bsum{}, *tile_c0{}, *tile_s0{};
   double *D{}, *U{}, *V0G{};
   float* Df{};
   bool fused = true;
@@ -408,7 +408,9 @@ int sort_particles(pic_ctx* c) {
   {  // cell-aligned tiles of the fused particle pass
     const int ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
     TRY(fill<int>(c, c->tile_c0, c->K.nn, ntiles + 1));
-    k_tile_bounds<<<grid_for(c->K.nn), kBlock, 0, c->stream>>>(c->cstart, c->K.nn, c->tile_c0, ntiles);
+    TRY(fill<int>(c, c->tile_s0, (int)c->K.np, ntiles + 1));
+    k_tile_bounds<<<grid_for(c->K.nn), kBlock, 0, c->stream>>>(c->cstart, c->K.nn, c->tile_c0,
+                                                                c->tile_s0, ntiles);
     LAUNCH_CHECK(c, "tile bounds");
   }
   int np = (int)c->K.np;
@@ -549,6 +551,7 @@ PartArgs part_args(pic_ctx* c) {
   a.count = c->count;
   a.cstart = c->cstart;
   a.tile_c0 = c->tile_c0;
+  a.tile_s0 = c->tile_s0;
   a.E = c->E;
   a.gv0 = c->V0G;
   a.gu = c->U;
@@ -756,6 +759,7 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   c->cstart = carve<int>(c, A_CSTART);
   c->bsum = carve<int>(c, A_BSUM);
   c->tile_c0 = carve<int>(c, A_TILE);
+  c->tile_s0 = c->tile_c0 + (c->K.np + kTileB - 1) / kTileB + 2;
   c->mom = carve<void>(c, A_MOM);
   c->rho = carve<double>(c, A_RHO);
   c->b = carve<double>(c, A_B);

@@ -40,9 +40,11 @@ struct SimConst {
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11).  Counter layout of the random stream:
 //   c0 entity (particle id or cell), c1 step, c2 tag<<56 | call<<48 | outcome,
-//   c3 block; key = (seed, replicate).
+//   c3 block; key = (seed, replicate).  The N_pairs uniforms of four
+//   consecutive outcomes share one block: tag NPAIRS, outcome field k / 4,
+//   word k mod 4.
 // ---------------------------------------------------------------------------
-enum : uint64_t { kTagInit = 1, kTagColl = 2, kTagRedraw = 3 };
+enum : uint64_t { kTagInit = 1, kTagColl = 2, kTagRedraw = 3, kTagNpairs = 4 };
 
 struct U64x4 {
   uint64_t w[4];

@@ -606,9 +606,12 @@ __global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, in
   if (n < 2) return;
   unsigned long long acc = 0, gmx = 0;
   bool touched = false;
+  U64x4 w0{};
   for (int k = 0; k < K.navg; ++k) {
-    U64x4 w0 = stream_block(K, (uint64_t)c, (uint64_t)step, kTagColl, (uint64_t)call, (uint64_t)k, 0);
-    double xpairs = (double)n * (double)(n - 1) * K.pmax / 2.0 + unif(w0.w[0]);
+    if ((k & 3) == 0)
+      w0 = stream_block(K, (uint64_t)c, (uint64_t)step, kTagNpairs, (uint64_t)call,
+                        (uint64_t)(k >> 2), 0);
+    double xpairs = (double)n * (double)(n - 1) * K.pmax / 2.0 + unif(w0.w[k & 3]);
     if (!(xpairs < (double)kMaxPairsPerOutcome)) {
       atomicOr(&flags[kFlagCapacity], 1);
       continue;

@@ -290,50 +290,67 @@ template <int SIG>
 __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
-  __shared__ float lv0[3 * kLdsSlots], lu[3 * kLdsSlots], lD[3 * kLdsSlots];
-  __shared__ int lmark[kLdsSlots], ltl[kLdsSlots];
+  // Tile-resident copies of everything the pass reads per particle; the
+  // copy-on-write scratch of outcomes run by a cell thread is global.
+  __shared__ float lv0[3 * kLdsSlots], lD[3 * kLdsSlots], loff[3 * kLdsSlots],
+      lash[3 * kLdsSlots];
+  __shared__ int lkey[kLdsSlots], lcn[kLdsSlots];
   __shared__ CollideLds<float> cl;
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;
   if (tid == 0) {
-    int c0 = min(a.tile_c0[blockIdx.x], K.nn);
-    int c1 = min(max(a.tile_c0[blockIdx.x + 1], c0), K.nn);
-    sh_i[0] = c0;
-    sh_i[1] = c1;
-    sh_i[2] = a.cstart[c0];
-    sh_i[3] = a.cstart[c1];
+    sh_i[0] = min(a.tile_c0[blockIdx.x], K.nn);
+    sh_i[1] = min(a.tile_c0[blockIdx.x + 1], K.nn);
+    sh_i[2] = a.tile_s0[blockIdx.x];
+    sh_i[3] = a.tile_s0[blockIdx.x + 1];
   }
   __syncthreads();
-  const int c0 = sh_i[0], ncells = sh_i[1] - sh_i[0], s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
+  const int c0 = sh_i[0], ncells = max(sh_i[1] - sh_i[0], 0), s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
   if (ns <= 0) return;
   const bool lds = ns <= kLdsSlots;
   const int st = lds ? kLdsSlots : NP;
   float* v0 = lds ? lv0 : (float*)a.gv0 + s0;
-  float* u = lds ? lu : (float*)a.gu + s0;
   float* D = lds ? lD : (float*)a.gD + s0;
-  int* mark = lds ? lmark : a.gmark + s0;
-  int* tl = lds ? ltl : a.gtl + s0;
+  const float* to = lds ? loff : off + s0;   // offsets at the start of the pass
+  const float* ta = lds ? lash : ash + s0;
+  const int* tk = lds ? lkey : a.key + s0;   // cells at the start of the pass
+  float* u = (float*)a.gu + s0;
+  int* mark = a.gmark + s0;
+  int* tl = a.gtl + s0;
   const float navg_f = (float)K.navg;
 
   for (int j = tid; j < ns; j += kBlock) {
-    for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + s0 + j];
-    mark[j] = 0;
+    const int p = s0 + j;
+    for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + p];
+    if (lds) {
+      const int c = a.key[p];
+      for (int d = 0; d < 3; ++d) {
+        loff[d * kLdsSlots + j] = off[(int64_t)d * NP + p];
+        lash[d * kLdsSlots + j] = ash[(int64_t)d * NP + p];
+      }
+      lkey[j] = c;
+      lcn[j] = a.cstart[c + 1] - a.cstart[c];
+    }
   }
   __syncthreads();
+  auto cell_count = [&](int j) {
+    if (lds) return lcn[j];
+    const int c = tk[j];
+    return a.cstart[c + 1] - a.cstart[c];
+  };
 
   auto kick = [&](int j, const float amp[3], bool coll_on) {
-    int p = s0 + j;
-    int c = a.key[p];
+    int c = tk[j];
     int ci = c % K.nc[0], cj = (c / K.nc[0]) % K.nc[1], ck = c / (K.nc[0] * K.nc[1]);
-    float o[3] = {off[p], off[NP + p], off[2 * NP + p]};
+    float o[3] = {to[j], to[st + j], to[2 * st + j]};
     float ep[3], em[3];
     gather_mixed(K, E32, ci, cj, ck, o, ep);
     EM_mixed(M, ci, cj, ck, o, amp, em);
     float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
     float coll[3] = {0.0f, 0.0f, 0.0f};
     if (coll_on) {
-      int n = a.cstart[c + 1] - a.cstart[c];
+      int n = cell_count(j);
       float I[3] = {0.0f, 0.0f, 0.0f};
       float coef = M.src_w * (float)(n - 1);
       if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
@@ -348,10 +365,9 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
 
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                             cl);
+                             NP, cl);
     for (int j = tid; j < ns; j += kBlock) {
-      int c = a.key[s0 + j];
-      int n = a.cstart[c + 1] - a.cstart[c];
+      int n = cell_count(j);
       float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
       float coef = M.src_w * (float)(n - 1);
       if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
@@ -366,7 +382,7 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
   if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
     if (K.collisions)
       tile_collide<SIG, float>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                               cl);
+                               NP, cl);
     for (int j = tid; j < ns; j += kBlock) kick(j, M.emB, K.collisions != 0);
     __syncthreads();
     if (!(a.mode & kDoA)) {
@@ -379,7 +395,7 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
   // call A at t^{na}, first half kick, drift to t^{na+1}
   if (K.collisions)
     tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
-                             st, cl);
+                             st, NP, cl);
   for (int base = 0; base < ns; base += kBlock) {
     int j = base + tid;
     bool valid = j < ns;
@@ -387,12 +403,13 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
     if (valid) {
       int p = s0 + j;
       kick(j, M.emA, K.collisions != 0);
-      int c = a.key[p];
+      int c = tk[j];
       int cc[3] = {c % K.nc[0], (c / K.nc[0]) % K.nc[1], c / (K.nc[0] * K.nc[1])};
+      float on[3];
       for (int d = 0; d < 3; ++d) {
         // x += dt (v - v^M) in cell units; v^M = vbar a (time independent)
-        float vm = M.vbar * ash[(int64_t)d * NP + p];
-        float o = off[(int64_t)d * NP + p] + M.dt * (v0[d * st + j] - vm) * M.inv_h[d];
+        float vm = M.vbar * ta[d * st + j];
+        float o = to[d * st + j] + M.dt * (v0[d * st + j] - vm) * M.inv_h[d];
         float fl = floorf(o);
         o -= fl;
         int shift = (int)fl;
@@ -409,7 +426,12 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
         int ni = cc[d] + (shift % nd);
         ni = ni < 0 ? ni + nd : (ni >= nd ? ni - nd : ni);
         cc[d] = ni;
-        off[(int64_t)d * NP + p] = o;
+        on[d] = o;
+      }
+      // (the global copies are written only now: in a large tile `to` and
+      // `tk` read the global arrays themselves)
+      for (int d = 0; d < 3; ++d) {
+        off[(int64_t)d * NP + p] = on[d];
         vf[(int64_t)d * NP + p] = v0[d * st + j];
       }
       kk = (cc[2] * K.nc[1] + cc[1]) * K.nc[0] + cc[0];

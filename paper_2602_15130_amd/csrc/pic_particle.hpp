@@ -58,6 +58,7 @@ struct PartArgs {
   int* count;           // per-cell counts for the next sort (zeroed by the caller)
   const int* cstart;
   const int* tile_c0;   // first cell of each tile, [ntiles + 1]
+  const int* tile_s0;   // first particle of each tile, [ntiles + 1]
   const double* E;      // nodal field [3][nn]
   double* gv0;          // global fallback scratch [3][np]
   double* gu;           // global fallback scratch [3][np]
@@ -79,14 +80,21 @@ struct PartArgs {
 // First cell of every tile: tile_c0[t] = min{c : cstart[c] >= t B}.  For c >= 1
 // that is c exactly when cstart[c-1] < t B <= cstart[c], so each cell marks the
 // tiles whose boundary falls in its range; tile_c0 is filled with ncells first
-// and tile 0 starts at cell 0.
+// and tile 0 starts at cell 0.  tile_s0[t] = cstart[tile_c0[t]], the tile's first
+// particle (filled with np first).
 __global__ void __launch_bounds__(kBlock) k_tile_bounds(const int* cstart, int nn, int* tile_c0,
-                                                        int ntiles) {
+                                                        int* tile_s0, int ntiles) {
   int c = blockIdx.x * kBlock + threadIdx.x + 1;
   if (c > nn) return;
   int lo = cstart[c - 1], hi = cstart[c];
-  for (int t = lo / kTileB + 1; t * kTileB <= hi && t <= ntiles; ++t) tile_c0[t] = c;
-  if (c == 1) tile_c0[0] = 0;
+  for (int t = lo / kTileB + 1; t * kTileB <= hi && t <= ntiles; ++t) {
+    tile_c0[t] = c;
+    tile_s0[t] = hi;
+  }
+  if (c == 1) {
+    tile_c0[0] = 0;
+    tile_s0[0] = 0;
+  }
 }
 
 __device__ inline int lower_bound_i(const int* a, int n, int key) {
@@ -122,9 +130,9 @@ __device__ inline R sigma_g_r(const SimConst& K, R g) {
 template <int SIG, class R>
 __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, int call, int k,
                                    int64_t npairs, int n, const R* v0, R* u, int* mark, int tag,
-                                   int* tl, int& ntl, int st, long long* pairlog, int64_t cap,
-                                   unsigned long long* counters, unsigned long long& acc,
-                                   unsigned long long& gmx) {
+                                   int* tl, int& ntl, int st, int stu, long long* pairlog,
+                                   int64_t cap, unsigned long long* counters,
+                                   unsigned long long& acc, unsigned long long& gmx) {
   const R sgmax = (R)K.sgmax, gmax = (R)K.g_max;
   for (int64_t m = 0; m < npairs; ++m) {
     U64x4 wa = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call,
@@ -133,10 +141,12 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
                             (uint64_t)k, (uint64_t)(2 + 2 * m));
     int p = index_below(wa.w[0], n);
     int q = pick_partner(K, cell, step, call, k, m, wa, wb, p, n);
-    const R* sp = mark[p] == tag ? u : v0;
-    const R* sq = mark[q] == tag ? u : v0;
-    R up[3] = {sp[p], sp[st + p], sp[2 * st + p]};
-    R uq[3] = {sq[q], sq[st + q], sq[2 * st + q]};
+    const bool pp = mark[p] == tag, pq = mark[q] == tag;
+    R up[3], uq[3];
+    for (int d = 0; d < 3; ++d) {
+      up[d] = pp ? u[d * stu + p] : v0[d * st + p];
+      uq[d] = pq ? u[d * stu + q] : v0[d * st + q];
+    }
     R dx = up[0] - uq[0], dy = up[1] - uq[1], dz = up[2] - uq[2];
     R g = sqrt(dx * dx + dy * dy + dz * dz);
     if (g > gmax) ++gmx;
@@ -149,8 +159,8 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
       R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
       for (int d = 0; d < 3; ++d) {
         R vcm = (R)0.5 * (up[d] + uq[d]);
-        u[d * st + p] = vcm + (R)0.5 * g * nv[d];
-        u[d * st + q] = vcm - (R)0.5 * g * nv[d];
+        u[d * stu + p] = vcm + (R)0.5 * g * nv[d];
+        u[d * stu + q] = vcm - (R)0.5 * g * nv[d];
       }
       if (mark[p] != tag) {
         mark[p] = tag;
@@ -171,17 +181,26 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
   }
 }
 
-// Algorithm 1: N_pairs = floor(N (N - 1) P_max / 2 + U), in FP64 in both forms.
-// Beyond kMaxPairsPerOutcome (a degenerate state) it raises kFlagCapacity.
-__device__ inline int64_t npairs_of(const SimConst& K, int cell, int64_t step, int call, int k,
-                                    int n, int* flags) {
-  U64x4 w0 = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call, (uint64_t)k, 0);
-  double x = (double)n * (double)(n - 1) * K.pmax / 2.0 + unif(w0.w[0]);
+// Algorithm 1: N_pairs = floor(N (N - 1) P_max / 2 + U), in FP64 in both forms,
+// from the uniform word w.  Beyond kMaxPairsPerOutcome (a degenerate state) it
+// raises kFlagCapacity.
+__device__ inline int64_t npairs_from(const SimConst& K, int n, uint64_t w, int* flags) {
+  double x = (double)n * (double)(n - 1) * K.pmax / 2.0 + unif(w);
   if (!(x < (double)kMaxPairsPerOutcome)) {
     atomicOr(&flags[kFlagCapacity], 1);
     return 0;
   }
   return (int64_t)floor(x);
+}
+
+__device__ inline U64x4 npairs_block(const SimConst& K, int cell, int64_t step, int call, int group) {
+  return stream_block(K, (uint64_t)cell, (uint64_t)step, kTagNpairs, (uint64_t)call,
+                      (uint64_t)group, 0);
+}
+
+__device__ inline int64_t npairs_of(const SimConst& K, int cell, int64_t step, int call, int k,
+                                    int n, int* flags) {
+  return npairs_from(K, n, npairs_block(K, cell, step, call, k >> 2).w[k & 3], flags);
 }
 
 
@@ -261,11 +280,12 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
 template <int SIG, class R>
 __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
                                      int c, int ci, int cs, int n, const R* v0, R* u, R* D,
-                                     int* mark, int* tl, int tagbase, int st,
+                                     int* mark, int* tl, int tagbase, int st, int stu,
                                      const CollideLds<R>& L, int ne, bool all,
                                      unsigned long long& acc, unsigned long long& gmx) {
   const int navg = K.navg;
   int last = -1;
+  bool marks_clear = false;  // this cell's marks are reset before its first own outcome
   for (int it = 0; it < navg; ++it) {
     int k, ev = -1;
     if (all) {
@@ -293,24 +313,29 @@ __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int c
     }
     int64_t np_ = ev >= 0 ? (int64_t)L.evn[ev] : npairs_of(K, c, step, call, k, n, a.flags);
     if (np_ <= 0) continue;
+    if (!marks_clear) {
+      for (int t = 0; t < n; ++t) mark[cs + t] = 0;
+      marks_clear = true;
+    }
     int ntl = 0;
     ntc_outcome<SIG, R>(K, c, step, call, k, np_, n, v0 + cs, u + cs, mark + cs, tagbase + k + 1,
-                        tl + cs, ntl, st, a.pairlog, a.cap, a.counters, acc, gmx);
+                        tl + cs, ntl, st, stu, a.pairlog, a.cap, a.counters, acc, gmx);
     for (int t = 0; t < ntl; ++t) {
       int j = cs + tl[cs + t];
-      for (int d = 0; d < 3; ++d) D[d * st + j] += u[d * st + j] - v0[d * st + j];
+      for (int d = 0; d < 3; ++d) D[d * st + j] += u[d * stu + j] - v0[d * st + j];
     }
   }
 }
 
 // Collision call over the tile: v0 (pre-collision velocities, tile slots,
-// stride st) -> D = N_avg <dv> per slot.  u, mark and tl are scratch of the
-// tile's slots; mark must hold values below tagbase + 1 on entry.
+// stride st) -> D = N_avg <dv> per slot.  u (stride stu), mark and tl are
+// scratch of the tile's slots for the outcomes a cell thread runs itself; a
+// cell's marks are cleared before its first such outcome in a call.
 template <int SIG, class R>
 __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
                                     int64_t step, int c0, int ncells, int s0, int ns,
                                     const R* v0, R* u, R* D, int* mark, int* tl, int tagbase,
-                                    int st, CollideLds<R>& L) {
+                                    int st, int stu, CollideLds<R>& L) {
   const int tid = threadIdx.x;
   if (tid == 0) {
     L.n_evt = 0;
@@ -320,21 +345,27 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
   for (int j = tid; j < ns; j += kBlock) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
   __syncthreads();
   const int navg = K.navg;
-  const int64_t lanes = (int64_t)ncells * navg;
-  // (1) N_pairs of every (cell, outcome)
+  const int ngroups = (navg + 3) >> 2;
+  const int64_t lanes = (int64_t)ncells * ngroups;
+  // (1) N_pairs of every (cell, outcome), one random block per four outcomes
   for (int64_t l = tid; l < lanes; l += kBlock) {
-    int ci = (int)(l / navg), k = (int)(l - (int64_t)ci * navg);
+    int ci = (int)(l / ngroups), g = (int)(l - (int64_t)ci * ngroups);
     int c = c0 + ci;
     int n = a.cstart[c + 1] - a.cstart[c];
     if (n < 2) continue;
-    int64_t np_ = npairs_of(K, c, step, call, k, n, a.flags);
-    if (np_ > 0) {
-      int e = atomicAdd(&L.n_evt, 1);
-      if (e < kMaxEvents) {
-        L.evt[e] = (int)l;
-        L.evn[e] = (int)np_;
-      } else {
-        L.overflow = 1;
+    U64x4 w = npairs_block(K, c, step, call, g);
+    for (int kk = 0; kk < 4; ++kk) {
+      int k = 4 * g + kk;
+      if (k >= navg) break;
+      int64_t np_ = npairs_from(K, n, w.w[kk], a.flags);
+      if (np_ > 0) {
+        int e = atomicAdd(&L.n_evt, 1);
+        if (e < kMaxEvents) {
+          L.evt[e] = ci * navg + k;
+          L.evn[e] = (int)np_;
+        } else {
+          L.overflow = 1;
+        }
       }
     }
   }
@@ -376,8 +407,8 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
       for (int e = 0; e < ne; ++e) any |= (L.evt[e] / navg) == ci;
       if (!any) continue;
     }
-    cell_outcomes<SIG, R>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, L, ne,
-                          all, acc, gmx);
+    cell_outcomes<SIG, R>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, stu, L,
+                          ne, all, acc, gmx);
   }
   if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
   if (gmx) atomicAdd(&a.counters[kCntGmax], gmx);
@@ -507,42 +538,38 @@ __device__ inline void half_kick_f64(const SimConst& K, const double xp[3], cons
 // bound and gains more from resident waves than it loses to spill traffic.
 template <int FAM, int SIG>
 __global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArgs a) {
-  __shared__ double lv0[3 * kLdsSlots], lu[3 * kLdsSlots], lD[3 * kLdsSlots];
-  __shared__ int lmark[kLdsSlots], ltl[kLdsSlots];
+  // the copy-on-write scratch of outcomes run by a cell thread is global
+  __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots];
   __shared__ CollideLds<double> cl;
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;
   if (tid == 0) {
-    int c0 = min(a.tile_c0[blockIdx.x], K.nn);
-    int c1 = min(max(a.tile_c0[blockIdx.x + 1], c0), K.nn);
-    sh_i[0] = c0;
-    sh_i[1] = c1;
-    sh_i[2] = a.cstart[c0];
-    sh_i[3] = a.cstart[c1];
+    sh_i[0] = min(a.tile_c0[blockIdx.x], K.nn);
+    sh_i[1] = min(a.tile_c0[blockIdx.x + 1], K.nn);
+    sh_i[2] = a.tile_s0[blockIdx.x];
+    sh_i[3] = a.tile_s0[blockIdx.x + 1];
   }
   __syncthreads();
-  const int c0 = sh_i[0], ncells = sh_i[1] - sh_i[0], s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
+  const int c0 = sh_i[0], ncells = max(sh_i[1] - sh_i[0], 0), s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
   if (ns <= 0) return;
   const bool lds = ns <= kLdsSlots;
   const int st = lds ? kLdsSlots : NP;
   double* v0 = lds ? lv0 : a.gv0 + s0;
-  double* u = lds ? lu : a.gu + s0;
+  double* u = a.gu + s0;
   double* D = lds ? lD : a.gD + s0;
-  int* mark = lds ? lmark : a.gmark + s0;
-  int* tl = lds ? ltl : a.gtl + s0;
+  int* mark = a.gmark + s0;
+  int* tl = a.gtl + s0;
   const double dt = K.dt;
   const double inv_navg_den = (double)K.navg;
 
-  for (int j = tid; j < ns; j += kBlock) {
+  for (int j = tid; j < ns; j += kBlock)
     for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
-    mark[j] = 0;
-  }
   __syncthreads();
 
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                              cl);
+                              NP, cl);
     for (int j = tid; j < ns; j += kBlock) {
       int c = a.key[s0 + j];
       int n = a.cstart[c + 1] - a.cstart[c];
@@ -562,7 +589,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArg
     const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
     if (K.collisions)
       tile_collide<SIG, double>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                                cl);
+                                NP, cl);
     for (int j = tid; j < ns; j += kBlock) {
       int p = s0 + j;
       double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
@@ -590,7 +617,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArg
   const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
   if (K.collisions)
     tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
-                              st, cl);
+                              st, NP, cl);
   for (int base = 0; base < ns; base += kBlock) {
     int j = base + tid;
     bool valid = j < ns;

@@ -534,7 +534,8 @@ def test_npairs_follow_table1_pmax_and_philox():
     x = n * (n - 1) / 2 / 108.28
     counts = np.bincount([p[2] for p in pairs], minlength=disc["navg"])
     for k in range(disc["navg"]):
-        u = O.lib().orc_u01(O.philox_block((9, 2, (2 << 56) | k, 0), (1, 0))[0])
+        # the N_pairs uniform of outcome k: NPAIRS block of group k // 4, word k % 4
+        u = O.lib().orc_u01(O.philox_block((9, 2, (4 << 56) | (k >> 2), 0), (1, 0))[k & 3])
         if abs((x + u) - round(x + u)) > 1e-3:
             assert counts[k] == math.floor(x + u)
 
