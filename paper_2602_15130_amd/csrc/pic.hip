@@ -416,15 +416,15 @@ int sort_particles(pic_ctx* c) {
   int np = (int)c->K.np;
   k_scatter<<<grid_for(np), kBlock, 0, c->stream>>>(c->key, c->slot, c->cstart, c->tidx, c->tkey, np);
   int s = c->cur, d = 1 - c->cur;
+  const int ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
   if (c->precision == PIC_FP64)
-    k_order_f64<<<grid_for(np), kBlock, 0, c->stream>>>(c->tidx, c->tkey, c->cstart, c->x[s], c->v[s],
-                                                         c->sh[s], c->id[s], c->x[d], c->v[d],
-                                                         c->sh[d], c->id[d], c->key, np, c->flags);
+    k_order_tiles<double><<<ntiles, kBlock, 0, c->stream>>>(
+        c->tile_c0, c->tile_s0, c->tidx, c->tkey, c->cstart, c->x[s], c->v[s], c->sh[s], c->id[s],
+        c->x[d], c->v[d], c->sh[d], c->id[d], c->key, np, c->flags);
   else
-    k_order_mixed<<<grid_for(np), kBlock, 0, c->stream>>>(c->tidx, c->tkey, c->cstart, c->off[s],
-                                                           c->vf[s], c->asf[s], c->id[s], c->off[d],
-                                                           c->vf[d], c->asf[d], c->id[d], c->key, np,
-                                                           c->flags);
+    k_order_tiles<float><<<ntiles, kBlock, 0, c->stream>>>(
+        c->tile_c0, c->tile_s0, c->tidx, c->tkey, c->cstart, c->off[s], c->vf[s], c->asf[s],
+        c->id[s], c->off[d], c->vf[d], c->asf[d], c->id[d], c->key, np, c->flags);
   LAUNCH_CHECK(c, "sort");
   c->cur = d;
   return PIC_OK;

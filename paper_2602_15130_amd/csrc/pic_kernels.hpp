@@ -216,26 +216,6 @@ __device__ inline int order_dst(const int* tidx, const int* tkey, const int* cst
   return s + stable_rank(tidx, s, e, tidx[j]);
 }
 
-__global__ void __launch_bounds__(kBlock) k_order_f64(const int* tidx, const int* tkey,
-                                                      const int* cstart, const double* xs,
-                                                      const double* vs, const double* as,
-                                                      const int* ids, double* xd, double* vd,
-                                                      double* ad, int* idd, int* keyd, int n,
-                                                      int* flags) {
-  int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
-  int c = tkey[j], my = tidx[j];
-  int dst = order_dst(tidx, tkey, cstart, j, flags);
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    xd[(int64_t)d * n + dst] = xs[(int64_t)d * n + my];
-    vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
-    ad[(int64_t)d * n + dst] = as[(int64_t)d * n + my];
-  }
-  idd[dst] = ids[my];
-  keyd[dst] = c;
-}
-
 // ---------------------------------------------------------------------------
 // Initial state: xi -> x^M(0), v^M(0) in id order (eq. mms_sol), cell keys and
 // counts for the sort.

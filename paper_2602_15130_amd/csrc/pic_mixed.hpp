@@ -51,26 +51,6 @@ __global__ void __launch_bounds__(kBlock) k_init_mixed(SimConst K, float* off, f
   if (valid) slot[p] = s;
 }
 
-__global__ void __launch_bounds__(kBlock) k_order_mixed(const int* tidx, const int* tkey,
-                                                        const int* cstart, const float* os,
-                                                        const float* vs, const float* as,
-                                                        const int* ids, float* od, float* vd,
-                                                        float* ad, int* idd, int* keyd, int n,
-                                                        int* flags) {
-  int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
-  int c = tkey[j], my = tidx[j];
-  int dst = order_dst(tidx, tkey, cstart, j, flags);
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    od[(int64_t)d * n + dst] = os[(int64_t)d * n + my];
-    vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
-    ad[(int64_t)d * n + dst] = as[(int64_t)d * n + my];
-  }
-  idd[dst] = ids[my];
-  keyd[dst] = c;
-}
-
 // Neumaier-compensated accumulation: s + c carries the sum to about FP64 accuracy.
 __device__ inline void neumaier_add(float& s, float& c, float x) {
   float t = s + x;

@@ -415,6 +415,57 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
   __syncthreads();
 }
 
+// Stable in-cell order by cell-aligned tiles: a tile's slots (the sort's
+// scatter slots of its cells) load their source indices into LDS; each
+// slot's rank among the source indices of its own cell, which is its place in
+// the stable order, is counted in LDS, and the particle's state moves from its
+// source to (cell start) + rank.  Same destinations as order_dst; tiles larger
+// than the LDS slots use order_dst itself.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_order_tiles(const int* tile_c0, const int* tile_s0,
+                                                        const int* tidx, const int* tkey,
+                                                        const int* cstart, const T* xs,
+                                                        const T* vs, const T* as, const int* ids,
+                                                        T* xd, T* vd, T* ad, int* idd, int* keyd,
+                                                        int n, int* flags) {
+  __shared__ int lidx[kLdsSlots];
+  __shared__ int sh_i[2];
+  if (threadIdx.x == 0) {
+    sh_i[0] = tile_s0[blockIdx.x];
+    sh_i[1] = tile_s0[blockIdx.x + 1];
+  }
+  __syncthreads();
+  const int s0 = sh_i[0], ns = sh_i[1] - sh_i[0];
+  if (ns <= 0) return;
+  const bool lds = ns <= kLdsSlots;
+  if (lds) {
+    for (int j = threadIdx.x; j < ns; j += kBlock) lidx[j] = tidx[s0 + j];
+    __syncthreads();
+  }
+  for (int j = threadIdx.x; j < ns; j += kBlock) {
+    const int slot = s0 + j, c = tkey[slot];
+    int my, dst;
+    if (lds) {
+      my = lidx[j];
+      const int cs = cstart[c] - s0, ce = cstart[c + 1] - s0;
+      int r = 0;
+      for (int k = cs; k < ce; ++k) r += lidx[k] < my;
+      dst = s0 + cs + r;
+    } else {
+      my = tidx[slot];
+      dst = order_dst(tidx, tkey, cstart, slot, flags);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xd[(int64_t)d * n + dst] = xs[(int64_t)d * n + my];
+      vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
+      ad[(int64_t)d * n + dst] = as[(int64_t)d * n + my];
+    }
+    idd[dst] = ids[my];
+    keyd[dst] = c;
+  }
+}
+
 // Tile bounds of block b: first cell, cell count, first particle, particle count.
 __device__ inline void tile_range(const SimConst& K, const int* tile_c0, const int* cstart, int b,
                                   int* sh_i) {
