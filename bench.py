@@ -50,6 +50,32 @@ def stage_bytes(stage, prob, disc, precision, cg_iters):
     return 0
 
 
+DEVICE_SOURCES = ("pic_device.hpp", "pic_kernels.hpp", "pic_particle.hpp", "pic_mixed.hpp")
+
+
+def measured_traffic(stage, workload):
+    """HBM bytes per step of a stage from the committed hardware-counter record
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when the record is for another
+    workload or the device sources have changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_15130_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec["device_sources_sha256_16"] or rec["workload"] != workload:
+        return None
+    m = rec["per_step_MiB"].get(stage)
+    if m is None:
+        return None
+    f = rec["copy_factor"]
+    return int((m["FETCH_SIZE"] * f["FETCH_SIZE"] + m["WRITE_SIZE"] * f["WRITE_SIZE"]) * 2**20)
+
+
 def cpu_baseline(prob, disc, seed):
     """The oracle on the host cores: init (untimed), then one timed step of the
     same workload; particle-steps/s."""
@@ -124,7 +150,7 @@ def main():
     if args.beside and args.beside != "none":
         b = run_workload(pic, W, torch, args.beside, args.steps, args.warmup)
         out["beside"] = {k: b[k] for k in ("value", "ms_per_step", "dtype", "config", "roofline",
-                                           "roofline_particle_path", "stages")}
+                                           "roofline_particle_path", "stages", "cg_iters_last")}
     if not args.no_convergence:
         out["convergence"] = convergence_report(pic, W)
     if not args.no_cpu_baseline:
@@ -154,30 +180,38 @@ def run_workload(pic, W, torch, workload, steps, warmup):
     elapsed = t1 - t0
     value = disc["np"] * steps / elapsed
 
+    # Stages are timed with HIP events on the library's stream over the timed
+    # region.  Every stage runs once per step (the fused particle pass runs as
+    # step-straddling launches: the B half of one step with the A half of the
+    # next), so rates are per step: algorithmic bytes of one step's worth of
+    # the stage over its time per step.
     per_stage = {}
     for name, (ms, n) in stages.items():
         if n == 0:
             continue
         b = stage_bytes(name, prob, disc, precision, st["cg_iters"])
         per_stage[name] = {"ms_total": round(ms, 3), "launches": n,
-                           "us_per_launch": round(1e3 * ms / n, 2),
-                           "GBs": round(b / (ms / n * 1e-3) / 1e9, 1)}
+                           "us_per_step": round(1e3 * ms / steps, 2),
+                           "GBs": round(b / (ms / steps * 1e-3) / 1e9, 1)}
     dom = max(per_stage, key=lambda k: per_stage[k]["ms_total"])
     dom_bytes = stage_bytes(dom, prob, disc, precision, st["cg_iters"])
-    ach = dom_bytes / (per_stage[dom]["ms_total"] / per_stage[dom]["launches"] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-            "algorithmic_bytes_per_launch": dom_bytes}
+    ach = dom_bytes / (per_stage[dom]["ms_total"] / steps * 1e-3) / 1e9
+    kernel_names = {"particle": "k_particles_" + ("f64" if precision == "fp64" else "mixed"),
+                    "cg": "k_cg_brick / k_cg (+ low-mode pre-solve)", "sort": "k_order_tiles",
+                    "deposit": "k_deposit_tiles"}
+    roof = {"bound": "hbm", "kernel": kernel_names.get(dom, dom), "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, workload), "algorithmic_bytes_per_step": dom_bytes,
+            "per": "time step"}
     # the particle path (push, deposit, collide: the fused pass, sort and deposit)
     part_names = [k for k in ("particle", "collide", "kick", "drift", "sort", "deposit") if k in per_stage]
-    pb = sum(stage_bytes(k, prob, disc, precision, st["cg_iters"]) * per_stage[k]["launches"]
-             for k in part_names)
-    pms = sum(per_stage[k]["ms_total"] for k in part_names)
+    pb = sum(stage_bytes(k, prob, disc, precision, st["cg_iters"]) for k in part_names)
+    pms = sum(per_stage[k]["ms_total"] for k in part_names) / steps
     pach = pb / (pms * 1e-3) / 1e9
     roof_part = {"bound": "hbm", "kernels": part_names, "achieved": round(pach, 1),
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
-                 "ms_per_step": round(pms / steps, 3),
-                 "algorithmic_bytes_per_particle_step": round(pb / steps / disc["np"], 1)}
+                 "ms_per_step": round(pms, 3),
+                 "algorithmic_bytes_per_particle_step": round(pb / disc["np"], 1)}
     out = {
         "metric": "particle-steps/s", "value": value, "unit": "particle-steps/s", "n_gpus": 1,
         "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * elapsed / steps,
