@@ -146,6 +146,9 @@ def main():
     import torch
     from paper_2602_15130_amd import pic, workloads as W
 
+    if args.workload == "cfg4":
+        print(json.dumps(run_ensemble_bench()), flush=True)
+        return
     out = run_workload(pic, W, torch, args.workload, args.steps, args.warmup)
     if args.beside and args.beside != "none":
         b = run_workload(pic, W, torch, args.beside, args.steps, args.warmup)
@@ -157,6 +160,25 @@ def main():
         c = W.get(args.workload)
         out["cpu_baseline"] = cpu_baseline(c["problem"], c["disc"], c["seed"])
     print(json.dumps(out), flush=True)
+
+
+def run_ensemble_bench():
+    """The batched refinement ensemble: 5 levels (8^3 .. 128^3, 8 particles per
+    cell, dt halved per level to t = 0.01) x 32 replicates, mixed form, two-way,
+    hard-sphere NTC with 16 outcomes; throughput over all members."""
+    from paper_2602_15130_amd import ensemble
+
+    out = ensemble.run_ensemble(replicates=32, precision="mixed")
+    lv = [{k: x[k] for k in ("mesh", "particles", "steps", "cg_blocks", "solver", "wall_s",
+                             "particle_steps_per_s", "l2_mean", "l2_std")} for x in out["levels"]]
+    return {"metric": "particle-steps/s", "value": out["particle_steps_per_s"],
+            "unit": "particle-steps/s", "n_gpus": 1, "steps": None, "warmup": 0,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic (manufactured solution, Philox seed 1)",
+            "config": {"workload": "cfg4", "levels": [x["mesh"] for x in out["levels"]],
+                       "replicates": 32, "precision": "mixed"},
+            "particle_steps": out["particle_steps"], "wall_s": out["wall_s"], "levels": lv,
+            "orders_l2_mean": out["orders_l2_mean"]}
 
 
 def run_workload(pic, W, torch, workload, steps, warmup):

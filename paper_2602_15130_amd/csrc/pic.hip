@@ -64,7 +64,7 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_TILE] = 2 * ((np + kTileB - 1) / kTileB + 2) * 4;  // first cell and first particle per tile
   b[A_MOM] = 64 * nn;  // 8 FP64 cell moments, or 8 FP32 moments + 8 compensations
   b[A_RHO] = b[A_B] = b[A_PHI] = nn * 8;
-  b[A_CGV] = 7 * nn * 8;  // CG vectors r, w, s (two each) and p
+  b[A_CGV] = 9 * nn * 8;  // CG vectors r, w, s (two each) and p, or the brick solver's faces
   {  // low-mode pre-solve: basis tables, eigenvalues, three transform buffers
     const int64_t nmax = std::max({d->ncell[0], d->ncell[1], d->ncell[2]});
     b[A_LOW] = (3 * kLowMaxM * nmax + 3 * kLowMaxM + (int64_t)kLowMaxM * d->ncell[1] * d->ncell[2] +
@@ -201,52 +201,55 @@ SimConst derive(const pic_problem* p, const pic_discretization* d, uint64_t seed
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
 
-// The Poisson solver kernel for q nodes per thread (0: the global-memory one).
-const void* cg_kernel(int q) {
-  switch (q) {
-    case 1: return (const void*)k_cg_brick<1>;
-    case 2: return (const void*)k_cg_brick<2>;
-    case 4: return (const void*)k_cg_brick<4>;
-    case 8: return (const void*)k_cg_brick<8>;
-    case 16: return (const void*)k_cg_brick<16>;
-    default: return (const void*)k_cg;
-  }
-}
-
-// Brick decomposition for the on-chip solver: bricks of kBlock * q nodes
-// (q in 1..16) that tile the mesh exactly, whose padded copy fits 64 KB of LDS,
-// and whose count fits the co-resident grid and the reduction scratch.  Among
-// those, the count closest to `target` (ties: smallest face area, then the
-// longest x extent for coalesced rows) wins.  Returns false when none exists.
-struct BrickChoice {
-  int q, bd[3], nbr[3];
+// Instances of the brick solver: nodes per thread and threads per workgroup.
+struct BrickKernel {
+  int q, nt;
+  const void* fn;
 };
-bool choose_bricks(const int nc[3], int max_blocks, int target, BrickChoice& out) {
+const BrickKernel kBrickKernels[] = {
+    {1, 256, (const void*)k_cg_brick<1, 256>},   {2, 256, (const void*)k_cg_brick<2, 256>},
+    {4, 256, (const void*)k_cg_brick<4, 256>},   {8, 256, (const void*)k_cg_brick<8, 256>},
+    {16, 256, (const void*)k_cg_brick<16, 256>}, {16, 512, (const void*)k_cg_brick<16, 512>},
+    {8, 1024, (const void*)k_cg_brick<8, 1024>},  {4, 1024, (const void*)k_cg_brick<4, 1024>},
+};
+constexpr int kNumBrickKernels = sizeof(kBrickKernels) / sizeof(kBrickKernels[0]);
+
+// Brick decomposition for the on-chip solver: bricks of nt columns
+// (bx x by = nt) of q nodes along z for one of the instances above that tile
+// the mesh exactly, whose padded copy and halo table fit `lds_max` bytes,
+// whose published faces fit the space they reuse, and whose count fits the
+// co-resident grid of that instance (per_cu workgroups per CU) and the
+// reduction scratch.  Among those, the count closest
+// to `target` (ties: smallest face area, then the longest x extent for
+// coalesced rows) wins.  Returns false when none exists.
+struct BrickChoice {
+  int kernel, bd[3], nbr[3];
+};
+bool choose_bricks(const int nc[3], const int per_cu[], int ncu, size_t lds_max, int target,
+                   BrickChoice& out) {
   bool found = false;
   long best_cost = 0;
-  for (int q = 1; q <= 16; q *= 2) {
-    const int m = kBlock * q;
+  for (int ki = 0; ki < kNumBrickKernels; ++ki) {
+    const int nt = kBrickKernels[ki].nt, bz = kBrickKernels[ki].q, m = nt * bz;
+    if (nc[2] % bz) continue;
     for (int bx = 1; bx <= nc[0]; ++bx) {
-      if (nc[0] % bx || m % bx) continue;
-      for (int by = 1; by <= nc[1]; ++by) {
-        if (nc[1] % by || (m / bx) % by) continue;
-        int bz = m / (bx * by);
-        if (bz < 1 || bz > nc[2] || nc[2] % bz) continue;
-        const int bdv[3] = {bx, by, bz};
-        if (brick_lds_bytes(bdv) > 65536) continue;
-        // published faces (6 per node of surface) must fit the 6 nn doubles they reuse
-        if (2L * (bx * by + by * bz + bx * bz) > m) continue;
-        int64_t nb = (int64_t)(nc[0] / bx) * (nc[1] / by) * (nc[2] / bz);
-        if (nb > max_blocks || nb > 1024) continue;
-        long area = 2L * (bx * by + by * bz + bx * bz);
-        long cost = std::labs((long)nb - target) * 1000000L + area * 100L + (100 - std::min(bx, 99));
-        if (!found || cost < best_cost) {
-          found = true;
-          best_cost = cost;
-          out.q = q;
-          out.bd[0] = bx; out.bd[1] = by; out.bd[2] = bz;
-          out.nbr[0] = nc[0] / bx; out.nbr[1] = nc[1] / by; out.nbr[2] = nc[2] / bz;
-        }
+      if (nc[0] % bx || nt % bx) continue;
+      const int by = nt / bx;
+      if (by > nc[1] || nc[1] % by) continue;
+      const int bdv[3] = {bx, by, bz};
+      if (brick_lds_bytes(bdv) > lds_max) continue;
+      // published faces (6 per surface node) must fit the 9 nn doubles they reuse
+      const long area = 2L * (bx * by + by * bz + bx * bz);
+      if (2 * area > 3L * m) continue;
+      int64_t nb = (int64_t)(nc[0] / bx) * (nc[1] / by) * (nc[2] / bz);
+      if (nb > (int64_t)ncu * per_cu[ki] || nb > 1024) continue;
+      long cost = std::labs((long)nb - target) * 1000000L + area * 100L + (100 - std::min(bx, 99));
+      if (!found || cost < best_cost) {
+        found = true;
+        best_cost = cost;
+        out.kernel = ki;
+        out.bd[0] = bx; out.bd[1] = by; out.bd[2] = bz;
+        out.nbr[0] = nc[0] / bx; out.nbr[1] = nc[1] / by; out.nbr[2] = nc[2] / bz;
       }
     }
   }
@@ -263,6 +266,8 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   int cg_grid = 1;
   int cg_q = 0;                 // nodes per thread of the brick solver; 0 = global solver
+  int cg_nt = kBlock;           // threads per workgroup of the solver
+  const void* cg_fn = nullptr;  // the solver kernel
   int cg_bd[3] = {0, 0, 0};     // brick dimensions
   int cg_nbr[3] = {0, 0, 0};    // bricks per axis
   size_t cg_lds = 0;            // padded brick, bytes of LDS
@@ -485,7 +490,7 @@ int field_solve(pic_ctx* c, double t) {
     a.s[k] = c->cgv + (int64_t)(4 + k) * K.nn;
   }
   a.p = c->cgv + 6 * (int64_t)K.nn;
-  a.pub = c->cgv;  // the brick solver's face buffers reuse the global solver's vectors
+  a.pub = c->cgv;  // the brick solver's face buffers reuse the global solver's vectors (9 nn)
   a.part = c->partA;
   a.result = c->result;
   a.arrive = c->bar;
@@ -501,7 +506,7 @@ int field_solve(pic_ctx* c, double t) {
   }
   SimConst Kc = K;
   void* args[] = {&Kc, &a};
-  HIP_TRY(c, hipLaunchCooperativeKernel(cg_kernel(c->cg_q), dim3(c->cg_grid), dim3(kBlock), args,
+  HIP_TRY(c, hipLaunchCooperativeKernel(c->cg_fn, dim3(c->cg_grid), dim3(c->cg_nt), args,
                                         c->cg_lds, c->stream));
   tm_solve.stop();
   StageTimer tm(c, PIC_STAGE_GRADIENT);
@@ -808,30 +813,51 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
       c->cg_grid = std::min(c->cg_grid, want);
     }
   }
+  c->cg_fn = (const void*)k_cg;
+  c->cg_nt = kBlock;
   const char* force_global = std::getenv("PIC_CG_GLOBAL");
   if (!(force_global && std::atoi(force_global) == 1)) {
+    // co-resident workgroups per CU of each instance at its largest LDS use
+    int lds_max = 65536;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    lds_max = std::max(lds_max, 65536);
+    // PIC_CG_INSTANCE="q,nt" restricts the choice to one solver instance
+    int only_q = 0, only_nt = 0;
+    if (const char* ev = std::getenv("PIC_CG_INSTANCE")) {
+      if (std::sscanf(ev, "%d,%d", &only_q, &only_nt) != 2) only_q = only_nt = 0;
+    }
+    int per[kNumBrickKernels];
+    for (int ki = 0; ki < kNumBrickKernels; ++ki) {
+      per[ki] = 0;
+      if (only_q && (kBrickKernels[ki].q != only_q || kBrickKernels[ki].nt != only_nt)) continue;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[ki], kBrickKernels[ki].fn,
+                                                       kBrickKernels[ki].nt, 0) != hipSuccess)
+        per[ki] = 0;
+    }
     BrickChoice bc{};
-    // co-resident bound for the largest padded brick (64 KB of LDS)
-    int per_cu_b = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_b, k_cg_brick<16>, kBlock, 65536);
-    if (e == hipSuccess && per_cu_b >= 1 &&
-        choose_bricks(c->K.nc, ncu * per_cu_b, std::min(target, ncu), bc)) {
-      c->cg_q = bc.q;
-      for (int d = 0; d < 3; ++d) {
-        c->cg_bd[d] = bc.bd[d];
-        c->cg_nbr[d] = bc.nbr[d];
-      }
-      c->cg_grid = bc.nbr[0] * bc.nbr[1] * bc.nbr[2];
-      c->cg_lds = brick_lds_bytes(bc.bd);
-      // the chosen instance must be co-resident at this grid, else keep the global solver
-      int per = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, cg_kernel(c->cg_q), kBlock,
-                                                       c->cg_lds) != hipSuccess ||
-          (int64_t)per * ncu < c->cg_grid) {
-        c->cg_q = 0;
-        c->cg_lds = 0;
-        c->cg_grid = (int)std::min<int64_t>({(int64_t)ncu, (int64_t)ncu * per_cu,
-                                             (int64_t)grid_for(c->K.nn), (int64_t)target});
+    if (choose_bricks(c->K.nc, per, ncu, (size_t)lds_max, std::min(target, ncu), bc)) {
+      const BrickKernel& bk = kBrickKernels[bc.kernel];
+      const size_t lds = brick_lds_bytes(bc.bd);
+      const int grid = bc.nbr[0] * bc.nbr[1] * bc.nbr[2];
+      bool ok = true;
+      if (lds > 65536)
+        ok = hipFuncSetAttribute(bk.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+             hipSuccess;
+      // the chosen instance must be co-resident at this grid with its LDS
+      int occ = 0;
+      if (ok && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, bk.fn, bk.nt, lds) != hipSuccess ||
+                 (int64_t)occ * ncu < grid))
+        ok = false;
+      if (ok) {
+        c->cg_q = bk.q;
+        c->cg_nt = bk.nt;
+        c->cg_fn = bk.fn;
+        for (int d = 0; d < 3; ++d) {
+          c->cg_bd[d] = bc.bd[d];
+          c->cg_nbr[d] = bc.nbr[d];
+        }
+        c->cg_grid = grid;
+        c->cg_lds = lds;
       }
     }
     (void)hipGetLastError();

@@ -139,40 +139,48 @@ inline size_t brick_lds_bytes(const int bd[3]) {
   return pad * sizeof(double) + 2 * nh * sizeof(int);
 }
 
-template <int Q>
-__global__ void __launch_bounds__(kBlock) k_cg_brick(SimConst K, CgArgs a) {
+// Bricks are NT columns (bdim[0] x bdim[1] = NT) of Q nodes along z: thread t
+// owns the column (li, lj) = (t mod bdim[0], t / bdim[0]) and its nodes
+// lk = 0..Q-1, so its node q sits at padded index pl0 + q pxy and mesh node
+// gn0 + q nx ny (a brick never wraps inside).
+template <int Q, int NT>
+__global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
   extern __shared__ double R[];
-  __shared__ double sh[kWaves];
-  const int bd[3] = {a.bdim[0], a.bdim[1], a.bdim[2]};
+  __shared__ double sh[NT / 64];
+  const int bd[3] = {a.bdim[0], a.bdim[1], Q};
   int foff[7];
   brick_face_offsets(bd, foff);
   const int px = bd[0] + 2, pxy = (bd[0] + 2) * (bd[1] + 2);
   const int nh = foff[6];
   const int bi = blockIdx.x % a.nbr[0], bj = (blockIdx.x / a.nbr[0]) % a.nbr[1],
             bk = blockIdx.x / (a.nbr[0] * a.nbr[1]);
-  const int ox = bi * bd[0], oy = bj * bd[1], oz = bk * bd[2];
+  const int ox = bi * bd[0], oy = bj * bd[1], oz = bk * Q;
   const int tid = threadIdx.x;
   double* pub = a.pub;
   double* own = pub + (int64_t)blockIdx.x * 6 * nh;  // this brick's face buffers
   // halo table, built once per solve: padded index and published source
-  int* hp = (int*)(R + pxy * (bd[2] + 2));
+  int* hp = (int*)(R + pxy * (Q + 2));
   int* hs = hp + nh;
-  for (int h = tid; h < nh; h += kBlock) brick_halo_src(bd, a.nbr, foff, bi, bj, bk, h, hp[h], hs[h]);
+  for (int h = tid; h < nh; h += NT) brick_halo_src(bd, a.nbr, foff, bi, bj, bk, h, hp[h], hs[h]);
 
-  int gn[Q], pl[Q], lc[Q];
-  bool face[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    int l = tid + kBlock * q;
-    int li = l % bd[0], lj = (l / bd[0]) % bd[1], lk = l / (bd[0] * bd[1]);
-    gn[q] = lin(K, ox + li, oy + lj, oz + lk);
-    pl[q] = ((lk + 1) * (bd[1] + 2) + (lj + 1)) * px + (li + 1);
-    lc[q] = li | (lj << 10) | (lk << 20);
-    face[q] = li == 0 || li == bd[0] - 1 || lj == 0 || lj == bd[1] - 1 || lk == 0 ||
-              lk == bd[2] - 1;
-  }
-  auto publish = [&](double* fb, int q, double v) {
-    brick_publish(fb, bd, foff, lc[q] & 1023, (lc[q] >> 10) & 1023, lc[q] >> 20, v);
+  const int li = tid % bd[0], lj = tid / bd[0];
+  const int pl0 = (bd[1] + 2 + lj + 1) * px + (li + 1);  // padded index of lk = 0
+  const int plane = K.nc[0] * K.nc[1];
+  const int gn0 = ((oz * K.nc[1]) + oy + lj) * K.nc[0] + ox + li;
+  const bool side = li == 0 || li == bd[0] - 1 || lj == 0 || lj == bd[1] - 1;
+  auto pl = [&](int q) { return pl0 + q * pxy; };
+  auto gn = [&](int q) { return gn0 + q * plane; };
+  auto face = [&](int q) { return side || q == 0 || q == Q - 1; };
+  auto publish = [&](double* fb, int q, double v) { brick_publish(fb, bd, foff, li, lj, q, v); };
+  // -L at own node q from its value v and its z neighbours zm, zp (own
+  // registers inside the column, the LDS halo at its ends); the x and y
+  // neighbours come from LDS.  Same association as neg_lap_pad.
+  auto col_lap = [&](int q, double v, double zm, double zp) {
+    const int c = pl(q);
+    double lx = R[c + 1] - 2.0 * v + R[c - 1];
+    double ly = R[c + px] - 2.0 * v + R[c - px];
+    double lz = zp - 2.0 * v + zm;
+    return -(lx * K.ih2[0] + ly * K.ih2[1] + lz * K.ih2[2]);
   };
   double xr[Q], rr[Q], wr[Q], sr[Q], pr[Q];
   unsigned gen = 0;
@@ -180,10 +188,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_brick(SimConst K, CgArgs a) {
   // r_0 = -b - A x_0 from the stored iterate (own nodes and halo straight from x)
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    xr[q] = a.x[gn[q]];
-    R[pl[q]] = xr[q];
+    xr[q] = a.x[gn(q)];
+    R[pl(q)] = xr[q];
   }
-  for (int h = tid; h < nh; h += kBlock) {
+  for (int h = tid; h < nh; h += NT) {
     int pi, gi;
     brick_halo(K, bd, ox, oy, oz, h, pi, gi);
     R[pi] = a.x[gi];
@@ -192,14 +200,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_brick(SimConst K, CgArgs a) {
   double v2[kMaxRed] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    double bv = a.b[gn[q]];
-    double rv = -bv - neg_lap_pad(K, R, pl[q], px, pxy);
+    double bv = a.b[gn(q)];
+    double rv = -bv - neg_lap_pad(K, R, pl(q), px, pxy);
     rr[q] = rv;
     v2[0] += rv * rv;
     v2[1] += bv * bv;
-    if (face[q]) publish(own, q, rv);  // parity 0, r
+    if (face(q)) publish(own, q, rv);  // parity 0, r
   }
-  if (!grid_sum(a, v2, 2, ++gen, sh)) return;
+  if (!grid_sum_t<NT>(a, v2, 2, ++gen, sh)) return;
   double gamma = v2[0];
   const double bnorm = sqrt(v2[1]);
   int it = 0;
@@ -210,18 +218,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_brick(SimConst K, CgArgs a) {
   } else if (sqrt(gamma) > a.tol * bnorm) {
     // w_0 = A r_0
 #pragma unroll
-    for (int q = 0; q < Q; ++q) R[pl[q]] = rr[q];
-    for (int h = tid; h < nh; h += kBlock) R[hp[h]] = face_load(pub + hs[h]);
+    for (int q = 0; q < Q; ++q) R[pl(q)] = rr[q];
+    for (int h = tid; h < nh; h += NT) R[hp[h]] = face_load(pub + hs[h]);
     __syncthreads();
     double v1[kMaxRed] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      double wv = neg_lap_pad(K, R, pl[q], px, pxy);
+      double wv = neg_lap_pad(K, R, pl(q), px, pxy);
       wr[q] = wv;
       v1[0] += wv * rr[q];
-      if (face[q]) publish(own + nh, q, wv);  // parity 0, w
+      if (face(q)) publish(own + nh, q, wv);  // parity 0, w
     }
-    if (!grid_sum(a, v1, 1, ++gen, sh)) return;
+    if (!grid_sum_t<NT>(a, v1, 1, ++gen, sh)) return;
     double alpha = gamma / v1[0], beta = 0.0;
     int cur = 0;
     while (true) {
@@ -239,13 +247,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_brick(SimConst K, CgArgs a) {
         sr[q] = sv;
         xr[q] += alpha * pv;
         rr[q] = rr[q] - alpha * sv;
-        R[pl[q]] = rr[q];
+        R[pl(q)] = rr[q];
       }
       // halo: the neighbours' r_{i+1} from their published r_i, w_i, s_{i-1}
       {
         const double* src = pub + (int64_t)cur * 3 * nh;
 #pragma unroll 4
-        for (int h = tid; h < nh; h += kBlock) {
+        for (int h = tid; h < nh; h += NT) {
           const double* f = src + hs[h];
           double f0 = face_load(f), f1 = face_load(f + nh);
           double sv = first ? f1 : f1 + beta * face_load(f + 2 * nh);
@@ -255,13 +263,15 @@ __global__ void __launch_bounds__(kBlock) k_cg_brick(SimConst K, CgArgs a) {
       __syncthreads();
       double* dst = own + (int64_t)(cur ^ 1) * 3 * nh;
       double gd[kMaxRed] = {0.0, 0.0, 0.0};
+      const double zlo = R[pl(0) - pxy], zhi = R[pl(Q - 1) + pxy];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        double wv = neg_lap_pad(K, R, pl[q], px, pxy);
+        double wv = col_lap(q, rr[q], q > 0 ? rr[q > 0 ? q - 1 : 0] : zlo,
+                            q < Q - 1 ? rr[q < Q - 1 ? q + 1 : 0] : zhi);
         wr[q] = wv;
         gd[0] += rr[q] * rr[q];
         gd[1] += wv * rr[q];
-        if (face[q]) {
+        if (face(q)) {
           publish(dst, q, rr[q]);
           publish(dst + nh, q, wv);
           publish(dst + 2 * nh, q, sr[q]);
@@ -269,7 +279,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_brick(SimConst K, CgArgs a) {
       }
       // (grid_sum's block barrier also orders these stencil reads of R before
       // the next sweep overwrites it)
-      if (!grid_sum(a, gd, 2, ++gen, sh)) return;
+      if (!grid_sum_t<NT>(a, gd, 2, ++gen, sh)) return;
       cur ^= 1;
       ++it;
       beta = gd[0] / gamma;
@@ -282,10 +292,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_brick(SimConst K, CgArgs a) {
   double s_x[kMaxRed] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < Q; ++q) s_x[0] += xr[q];
-  if (!grid_sum(a, s_x, 1, ++gen, sh)) return;
+  if (!grid_sum_t<NT>(a, s_x, 1, ++gen, sh)) return;
   const double mean = s_x[0] / (double)K.nn;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) a.x[gn[q]] = xr[q] - mean;
+  for (int q = 0; q < Q; ++q) a.x[gn(q)] = xr[q] - mean;
   if (blockIdx.x == 0 && tid == 0) {
     *a.iters_out = it;
     *a.relres_out = bnorm == 0.0 ? 0.0 : sqrt(gamma) / bnorm;

@@ -33,8 +33,10 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// Sum over the block; every thread receives the same value.
-__device__ inline double block_sum(double v, double* sh) {
+// Sum over a block of NT threads (sh holds NT / 64 values); every thread
+// receives the same value.
+template <int NT>
+__device__ inline double block_sum_t(double v, double* sh) {
   v = wave_sum(v);
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
   __syncthreads();
@@ -42,9 +44,10 @@ __device__ inline double block_sum(double v, double* sh) {
   __syncthreads();
   double r = 0.0;
 #pragma unroll
-  for (int i = 0; i < kWaves; ++i) r += sh[i];
+  for (int i = 0; i < NT / 64; ++i) r += sh[i];
   return r;
 }
+__device__ inline double block_sum(double v, double* sh) { return block_sum_t<kBlock>(v, sh); }
 __device__ inline double block_max(double v, double* sh) {
   v = wave_max(v);
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
@@ -376,9 +379,11 @@ __device__ inline bool spin_until(const unsigned* addr, unsigned want, int* flag
   return true;
 }
 
-// Grid-wide sum of nv block values; every thread of every block gets the same
-// nv results.  `gen` increases by one per call within a launch.
-__device__ inline bool grid_sum(const CgArgs& a, double* vals, int nv, unsigned gen, double* sh) {
+// Grid-wide sum of nv block values; every thread of every block (NT threads
+// each) gets the same nv results.  `gen` increases by one per call within a
+// launch.
+template <int NT>
+__device__ inline bool grid_sum_t(const CgArgs& a, double* vals, int nv, unsigned gen, double* sh) {
   __shared__ int ok;
   __shared__ double res[kMaxRed];
   double tot[kMaxRed];
@@ -387,7 +392,7 @@ __device__ inline bool grid_sum(const CgArgs& a, double* vals, int nv, unsigned 
   // and so publishes the whole block's stores with its flag.  (A workgroup
   // barrier alone does not wait for outstanding vector-memory stores.)
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  for (int i = 0; i < nv; ++i) tot[i] = block_sum(vals[i], sh);
+  for (int i = 0; i < nv; ++i) tot[i] = block_sum_t<NT>(vals[i], sh);
   if (threadIdx.x == 0) {
     for (int i = 0; i < nv; ++i) a.part[blockIdx.x * kMaxRed + i] = tot[i];
     __hip_atomic_store(&a.arrive[blockIdx.x * kFlagStride], gen, __ATOMIC_RELEASE,
@@ -397,15 +402,15 @@ __device__ inline bool grid_sum(const CgArgs& a, double* vals, int nv, unsigned 
   __syncthreads();
   if (blockIdx.x == 0) {
     int good = 1;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += NT)
       if (!spin_until(&a.arrive[b * kFlagStride], gen, a.flags)) good = 0;
     if (!good) ok = 0;
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     for (int i = 0; i < nv; ++i) {
       double acc = 0.0;
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) acc += a.part[b * kMaxRed + i];
-      double s = block_sum(acc, sh);
+      for (int b = threadIdx.x; b < (int)gridDim.x; b += NT) acc += a.part[b * kMaxRed + i];
+      double s = block_sum_t<NT>(acc, sh);
       if (threadIdx.x == 0) a.result[i] = s;
     }
     if (threadIdx.x == 0)
@@ -419,6 +424,9 @@ __device__ inline bool grid_sum(const CgArgs& a, double* vals, int nv, unsigned 
   __syncthreads();
   for (int i = 0; i < nv; ++i) vals[i] = res[i];
   return ok != 0;
+}
+__device__ inline bool grid_sum(const CgArgs& a, double* vals, int nv, unsigned gen, double* sh) {
+  return grid_sum_t<kBlock>(a, vals, nv, gen, sh);
 }
 
 // (-L f)(n) for f given by a callable.

@@ -316,14 +316,16 @@ def _with_env(name, value, fn):
             os.environ[name] = old
 
 
-@pytest.mark.parametrize("n,blocks", [(8, 0), (16, 0), (32, 0), (32, 16), (64, 0)])
+@pytest.mark.parametrize("n,blocks", [(16, 0), (32, 0), (32, 16), (64, 0), (128, 0)])
 def test_brick_solver_matches_global_solver_and_oracle(n, blocks):
     """The on-chip brick CG and the global-memory CG run the same recurrence
     and differ only in the order of the block partial sums; both stop at
     ||r|| <= tol ||b||, so phi agrees within kappa * tol, and with the oracle.
-    Covers one brick, several bricks and (blocks=16) bricks of 2048 nodes."""
+    Covers few bricks (16^3), bricks of 2048 nodes (blocks=16) and the
+    512- or 1024-thread instances (128^3).  (A brick's xy face holds one
+    workgroup's threads, so meshes below 16 x 16 use the global solver.)"""
     prob = W.cfg_problem(two_way=True, collisions=False)
-    disc = W.cfg_disc(n, 32 * n**3 if n <= 32 else 4 * n**3, 5e-4, 1, 1, cg_tol=1e-13)
+    disc = W.cfg_disc(n, 32 * n**3 if n <= 32 else 2 * n**3, 5e-4, 1, 1, cg_tol=1e-13)
     P = _pic()
     mk = lambda: P.Sim(prob, disc, 3, 0)  # noqa: E731
     g = _with_env("PIC_CG_BLOCKS", str(blocks), mk) if blocks else mk()
