@@ -124,6 +124,7 @@ def main():
                     help="second workload timed beside the first (the FP64 form); 'none' to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--levels", default="1,2,3", help="Table 1 levels for --workload table1")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes five times (reference for "
                          "hardware byte counters) and exit")
@@ -148,6 +149,9 @@ def main():
 
     if args.workload == "cfg4":
         print(json.dumps(run_ensemble_bench()), flush=True)
+        return
+    if args.workload == "table1":
+        print(json.dumps(run_table1(args.levels)), flush=True)
         return
     out = run_workload(pic, W, torch, args.workload, args.steps, args.warmup)
     if args.beside and args.beside != "none":
@@ -179,6 +183,50 @@ def run_ensemble_bench():
                        "replicates": 32, "precision": "mixed"},
             "particle_steps": out["particle_steps"], "wall_s": out["wall_s"], "levels": lv,
             "orders_l2_mean": out["orders_l2_mean"]}
+
+
+def run_table1(levels):
+    """The paper's Table 1 ladder, FP64 form: isolated collisions, fully coupled
+    collisional and fully coupled collisionless; l2 / linf norms per level and
+    observed orders (progress to stderr, one line per step)."""
+    import math
+
+    import torch
+    from paper_2602_15130_amd import pic, workloads as W
+
+    levels = [int(x) for x in levels.split(",")]
+    cases = {"isolated": dict(collisions=True, field_to_particles=False, particles_to_field=False,
+                              isolate=True),
+             "coupled": dict(collisions=True), "collisionless": dict(collisions=False)}
+    out = {"workload": "table1", "levels": levels, "cases": {}}
+    for name, kw in cases.items():
+        prob = W.paper_problem(**kw)
+        rows = []
+        for lv in levels:
+            disc = W.paper_level(lv, collisions=kw.get("collisions", True))
+            g = pic.Sim(prob, disc, 1, 0, "fp64")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(disc["steps"]):
+                g.step(1)
+                torch.cuda.synchronize()
+                print(f"{name} level {lv} step {s + 1}/{disc['steps']} {time.perf_counter() - t0:.1f}s",
+                      file=sys.stderr, flush=True)
+            wall = time.perf_counter() - t0
+            e = g.errors()
+            rows.append({"level": lv, "ncell": disc["nc"][0], "particles": disc["np"],
+                         "n_avg": disc["navg"], "steps": disc["steps"], "wall_s": round(wall, 2),
+                         "accepted": g.stats()["n_accepted"], "l2": [float(x) for x in e["l2"]],
+                         "linf": [float(x) for x in e["linf"]]})
+            del g
+        orders = []
+        for a, b in zip(rows, rows[1:]):
+            r = math.log(b["ncell"] / a["ncell"])
+            orders.append({"levels": [a["level"], b["level"]],
+                           "l2": [round(math.log(x / y) / r, 3) for x, y in zip(a["l2"], b["l2"])],
+                           "linf": [round(math.log(x / y) / r, 3) for x, y in zip(a["linf"], b["linf"])]})
+        out["cases"][name] = {"runs": rows, "orders": orders}
+    return out
 
 
 def run_workload(pic, W, torch, workload, steps, warmup):
