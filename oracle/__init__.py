@@ -75,6 +75,10 @@ def lib():
         L.orc_rhs.argtypes = [P(OrcProblem), P(OrcDisc), P(d), d, P(d)]
         L.orc_cg.argtypes = [P(OrcDisc), P(OrcProblem), P(d), P(d), d, C.c_int, P(C.c_int), P(d)]
         L.orc_cg_textbook.argtypes = L.orc_cg.argtypes
+        L.orc_angle_record_start.argtypes = [P(d), C.c_int64]
+        L.orc_angle_record_stop.argtypes = []
+        L.orc_angle_record_stop.restype = C.c_int64
+        L.orc_angle_errors.argtypes = [P(d), C.c_int64, P(d)]
         L.orc_laplacian.argtypes = [P(OrcDisc), P(OrcProblem), P(d), P(d)]
         L.orc_gradient.argtypes = [P(OrcProblem), P(OrcDisc), P(d), P(d)]
         L.orc_gather.argtypes = [P(OrcProblem), P(OrcDisc), P(d), i64, P(d), P(d)]
@@ -388,3 +392,33 @@ class Sim:
     @property
     def gmax_events(self):
         return lib().orc_gmax_events(self.h)
+
+
+class AngleRecorder:
+    """Collects (chi, eps) of every accepted oracle collision inside a with-block
+    (eq. angle_recovery); .records is an [n, 2] array afterwards."""
+
+    def __init__(self, capacity=1 << 22):
+        self.buf = np.zeros(2 * capacity)
+        self.capacity = capacity
+        self.records = None
+        self.total = 0
+
+    def __enter__(self):
+        lib().orc_angle_record_start(_dp(self.buf), self.capacity)
+        return self
+
+    def __exit__(self, *exc):
+        self.total = lib().orc_angle_record_stop()
+        n = min(self.total, self.capacity)
+        self.records = self.buf[: 2 * n].reshape(n, 2).copy()
+        return False
+
+
+def angle_errors(records):
+    """Empirical-CDF errors of (chi, eps) records against the isotropic analytic
+    CDFs: (eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps)."""
+    rec = np.ascontiguousarray(records, dtype=np.float64).reshape(-1)
+    out = np.zeros(4)
+    lib().orc_angle_errors(_dp(rec), len(rec) // 2, _dp(out))
+    return out

@@ -753,6 +753,71 @@ static uint64_t redraw_word(uint64_t seed, uint32_t rep, int64_t cell, int64_t s
   return blk[(r - 3) % 4];
 }
 
+/* ---- scattering-angle recovery (eq. angle_recovery and the empirical-CDF
+ * errors that follow it) ---- */
+static struct {
+  double* buf;
+  int64_t cap, n;
+} angle_rec = {NULL, 0, 0};
+
+void orc_angle_record_start(double* buf, int64_t cap) {
+  angle_rec.buf = buf;
+  angle_rec.cap = cap;
+  angle_rec.n = 0;
+}
+
+int64_t orc_angle_record_stop(void) {
+  int64_t n = angle_rec.n;
+  angle_rec.buf = NULL;
+  angle_rec.cap = 0;
+  return n;
+}
+
+/* chi = acos(g'_z / g), eps = atan2(g'_y, g'_x) in [0, 2 pi), from the
+ * post-collision relative velocity g' and the pre-collision speed g. */
+static void record_angles(double gx, double gy, double gz, double g) {
+  if (!angle_rec.buf) return;
+  double cz = gz / g;
+  if (cz > 1.0) cz = 1.0;
+  if (cz < -1.0) cz = -1.0;
+  double eps = atan2(gy, gx);
+  if (eps < 0.0) eps += TWO_PI_D;
+  if (angle_rec.n < angle_rec.cap) {
+    angle_rec.buf[2 * angle_rec.n] = acos(cz);
+    angle_rec.buf[2 * angle_rec.n + 1] = eps;
+  }
+  ++angle_rec.n;
+}
+
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+/* e_r = F(alpha_r) - F^M(alpha_r) with the empirical CDF F(alpha) =
+ * (1/N) sum_r theta(alpha - alpha_r), theta(0) = 1, and the isotropic
+ * analytic CDFs F^M_chi = (1 - cos chi)/2, F^M_eps = eps / (2 pi):
+ * out = {eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps}. */
+void orc_angle_errors(const double* rec, int64_t n, double out[4]) {
+  double* a = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int which = 0; which < 2; ++which) {
+    for (int64_t r = 0; r < n; ++r) a[r] = rec[2 * r + which];
+    qsort(a, (size_t)n, sizeof(double), cmp_double);
+    double s2 = 0.0, mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t j = i;  /* theta(0) = 1: equal values share the largest rank */
+      while (j + 1 < n && a[j + 1] == a[i]) ++j;
+      double fm = which == 0 ? 0.5 * (1.0 - cos(a[i])) : a[i] / TWO_PI_D;
+      double e = (double)(j + 1) / (double)n - fm;
+      s2 += e * e;
+      if (fabs(e) > mx) mx = fabs(e);
+    }
+    out[2 * which] = n > 0 ? sqrt(s2 / (double)n) : 0.0;
+    out[2 * which + 1] = mx;
+  }
+  free(a);
+}
+
 int orc_collide_cell(const orc_problem* P, const orc_disc* D, uint64_t seed, uint32_t rep,
                      int64_t step, int call, int64_t cell, int64_t n, const double* v,
                      double* dv_avg, orc_pair* log, int64_t log_cap, int64_t* log_n,
@@ -818,6 +883,7 @@ int orc_collide_cell(const orc_problem* P, const orc_disc* D, uint64_t seed, uin
             u[d * n + q] = vcm - 0.5 * g * nv[d];
           }
         }
+        record_angles(u[p] - u[q], u[n + p] - u[n + q], u[2 * n + p] - u[2 * n + q], g);
       }
       if (log && *log_n < log_cap) {
         orc_pair rec = {cell, call, k, m, p, q, accepted};

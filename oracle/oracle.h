@@ -122,6 +122,15 @@ int orc_collide_cell(const orc_problem* P, const orc_disc* D, uint64_t seed, uin
                      double* dv_avg, orc_pair* log, int64_t log_cap, int64_t* log_n,
                      int64_t* n_accepted, int64_t* n_gmax);
 
+/* Scattering-angle records (chi, eps) of every accepted collision between
+ * start and stop (eq. angle_recovery); stop returns the number of collisions
+ * (records beyond cap are counted, not stored). */
+void orc_angle_record_start(double* buf, int64_t cap);
+int64_t orc_angle_record_stop(void);
+/* Empirical-CDF errors of n records against the isotropic analytic CDFs:
+ * {eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps}. */
+void orc_angle_errors(const double* rec, int64_t n, double out[4]);
+
 /* ---- whole simulation ---- */
 orc_sim* orc_create(const orc_problem* P, const orc_disc* D, uint64_t seed, uint32_t rep);
 void orc_destroy(orc_sim* s);

@@ -712,3 +712,86 @@ def test_cfg_family_one_way_collisionless_is_second_order():
         norms.append(o.errors()["l2"])
     orders = np.array(W.observed_orders(norms)[0])
     assert np.all((orders > 1.75) & (orders < 2.25)), orders
+
+
+# ----------------------------------------------------------------------------- angle recovery
+def test_angle_metric_matches_order_statistics_closed_form():
+    """eps_2 of the empirical-CDF error for an exact sample: e_i = i/n - U_(i)
+    has mean square i(n+1-i)/((n+1)^2 (n+2)) + (i/n - i/(n+1))^2 (order
+    statistics of the uniform law), so eps_2^2 averages that over i; eps_inf
+    sqrt(n) stays in the bulk of the Kolmogorov law."""
+    n, trials = 4000, 60
+    rng = np.random.default_rng(31)
+    i = np.arange(1, n + 1)
+    expect = np.mean(i * (n + 1 - i) / ((n + 1) ** 2 * (n + 2)) + (i / n - i / (n + 1)) ** 2)
+    e2 = []
+    for _ in range(trials):
+        u = rng.random(n)
+        rec = np.stack([np.arccos(1 - 2 * u), 2 * np.pi * rng.random(n)], axis=1)
+        out = O.angle_errors(rec)
+        e2.append(out[0] ** 2)
+        assert out[1] * math.sqrt(n) < 2.2 and out[3] * math.sqrt(n) < 2.2
+    assert np.mean(e2) == pytest.approx(expect, rel=0.08)
+
+
+def test_angle_metric_ties_take_the_largest_rank():
+    # three equal chi values and one larger: F(alpha) counts alpha_s <= alpha
+    chi = np.arccos(1 - 2 * np.array([0.25, 0.25, 0.25, 0.75]))
+    rec = np.stack([chi, np.array([0.5, 1.0, 1.5, 2.0]) * np.pi], axis=1)
+    out = O.angle_errors(rec)
+    e = np.array([0.75 - 0.25, 0.75 - 0.25, 0.75 - 0.25, 1.0 - 0.75])
+    assert out[1] == pytest.approx(0.5, abs=1e-15)
+    assert out[0] == pytest.approx(math.sqrt(np.mean(e ** 2)), abs=1e-15)
+
+
+def _angle_run(prob, disc, steps, seed=1):
+    o = O.Sim(prob, disc, seed, 0)
+    assert o.init() == 0
+    with O.AngleRecorder() as rec:
+        o.step(steps)
+    return rec.records, O.angle_errors(rec.records)
+
+
+def test_angles_of_correct_collisions_follow_the_isotropic_law():
+    """Sec. 4.4: for the correct algorithm the recovered chi and eps follow
+    p_chi and p_eps, so sqrt(N_coll) eps_inf stays O(1) while N_coll grows."""
+    prob = W.paper_problem(collisions=True, field_to_particles=False, particles_to_field=False,
+                           isolate=True)
+    disc = dict(W.paper_level(1))
+    disc["navg"] = 8
+    rec, out = _angle_run(prob, disc, 4)
+    n = len(rec)
+    assert n > 20000
+    assert np.all(out[[1, 3]] * math.sqrt(n) < 2.0), out * math.sqrt(n)
+
+
+def test_error2_is_caught_by_the_angle_metric_and_error1_is_not():
+    """Sec. 5.4.1: Error 1 (v_cm = (v_p - v_q)/2) leaves chi and eps intact;
+    Error 2 (swap with probability 1/2) replaces g' = g n by +-g, whose
+    direction follows the non-isotropic relative velocities of the paper's
+    f_v, so the empirical CDFs do not converge to the analytic ones."""
+    disc = dict(W.paper_level(1))
+    disc["navg"] = 8
+    out = {}
+    for err in (0, 1, 2):
+        prob = W.paper_problem(collisions=True, field_to_particles=False, particles_to_field=False,
+                               isolate=True, coding_error=err)
+        rec, e = _angle_run(prob, disc, 8)
+        assert len(rec) > 100000
+        out[err] = e * math.sqrt(len(rec))
+    # sqrt(N) eps_inf beyond 3 has probability below 1e-7 under the analytic law
+    assert np.all(out[0][[1, 3]] < 2.0) and np.all(out[1][[1, 3]] < 2.0)
+    assert out[2][1] > 3.0 and out[2][3] > 3.0, out[2]
+
+
+def test_error2_hides_from_the_angle_metric_for_isotropic_velocities():
+    """With the configuration family's isotropic Gaussian f_v the relative
+    velocity of a pair is isotropic too, so the swapped g' of Error 2 still
+    looks isotropic: the angle metric cannot see Error 2 there (the paper's
+    demonstration relies on its anisotropic f_v)."""
+    prob = W.cfg_problem(two_way=False, collisionality=30.0)
+    prob["coding_error"] = 2
+    disc = W.cfg_disc(8, 16384, 1e-3, 1, 8)
+    rec, e = _angle_run(prob, disc, 3)
+    assert len(rec) > 20000
+    assert np.all(e[[1, 3]] * math.sqrt(len(rec)) < 2.0)
