@@ -167,6 +167,25 @@ typedef struct {
 } pic_error_norms;
 int pic_errors(pic_ctx* ctx, pic_error_norms* out);
 
+/* Scattering-angle recovery (eq. angle_recovery and the empirical-CDF errors
+ * defined after it).  While a log is enabled, every accepted collision of
+ * pic_step and pic_collide appends chi = acos(g'_z / g) and
+ * eps = atan2(g'_y, g'_x) in [0, 2 pi) (from the post-collision relative
+ * velocity g' and the pre-collision speed g) to a caller-owned device buffer
+ * of pic_angle_buffer_bytes(capacity) bytes, 256-byte aligned, which also
+ * holds the metric's sort scratch.  The record order depends on scheduling;
+ * the set of records and the metric do not.  pic_angle_log resets the count;
+ * a zero capacity switches recording off.  Enqueued on the context stream. */
+int64_t pic_angle_buffer_bytes(int64_t capacity);
+int pic_angle_log(pic_ctx* ctx, void* device_buffer, int64_t capacity);
+/* out = {eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps}: root mean square and
+ * maximum over the N records of e_r = F(alpha_r) - F^M(alpha_r), F the
+ * empirical CDF with theta(0) = 1 and F^M the isotropic analytic CDF
+ * ((1 - cos chi) / 2, eps / (2 pi)).  *n_records = N.  Synchronises;
+ * PIC_ESPACE (and no metric) when more collisions occurred than the log holds,
+ * PIC_EINVAL when no log is enabled. */
+int pic_angle_errors(pic_ctx* ctx, double out[4], int64_t* n_records);
+
 /* Counters of the last completed work (synchronises). */
 typedef struct {
   int64_t step;             /* completed time steps */

@@ -17,6 +17,7 @@
 #include "pic_mixed.hpp"
 #include "pic_cg_brick.hpp"
 #include "pic_lowmode.hpp"
+#include "pic_angles.hpp"
 
 using namespace pic;
 
@@ -272,6 +273,8 @@ struct pic_ctx {
   int cg_nbr[3] = {0, 0, 0};    // bricks per axis
   size_t cg_lds = 0;            // padded brick, bytes of LDS
   int low_k = 0;                // Fourier modes per axis solved exactly before the CG
+  double* angbuf = nullptr;     // scattering-angle records and their sort scratch
+  int64_t angcap = 0;
   LowArgs low{};
   bool ready = false;
   int64_t step = 0;
@@ -999,6 +1002,73 @@ int pic_errors(pic_ctx* c, pic_error_norms* out) {
     }
   }
   return PIC_OK;
+}
+
+namespace {
+int64_t angle_pad(int64_t cap) {
+  int64_t P = 1;
+  while (P < cap) P <<= 1;
+  return P;
+}
+}  // namespace
+
+int64_t pic_angle_buffer_bytes(int64_t capacity) {
+  if (capacity < 1) return 0;
+  const int64_t P = angle_pad(capacity);
+  return (2 * capacity + 2 * P + 4 * ((P + kBlock - 1) / kBlock) + 4) * (int64_t)sizeof(double);
+}
+
+int pic_angle_log(pic_ctx* c, void* buffer, int64_t capacity) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (capacity < 0 || (capacity > 0 && !buffer)) {
+    c->err = "angle log: a buffer is needed for a positive capacity";
+    return PIC_EINVAL;
+  }
+  if (capacity > 0 && ((uintptr_t)buffer) % 256) {
+    c->err = "angle log: buffer must be 256-byte aligned";
+    return PIC_EINVAL;
+  }
+  c->angbuf = capacity > 0 ? (double*)buffer : nullptr;
+  c->angcap = capacity;
+  c->K.anglog = c->angbuf;
+  c->K.angcap = capacity;
+  TRY(fill<unsigned long long>(c, c->cnt + kCntAngles, 0ull, 1));
+  return PIC_OK;
+}
+
+int pic_angle_errors(pic_ctx* c, double out[4], int64_t* n_records) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (!out || !c->angbuf) {
+    c->err = "angle errors: no angle log is enabled";
+    return PIC_EINVAL;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned long long total = 0;
+  HIP_TRY(c, hipMemcpy(&total, c->cnt + kCntAngles, sizeof(total), hipMemcpyDeviceToHost));
+  if (n_records) *n_records = (int64_t)total;
+  if ((int64_t)total > c->angcap) {
+    c->err = "angle errors: more collisions than the angle log holds";
+    return PIC_ESPACE;
+  }
+  const int64_t n = (int64_t)total, P = angle_pad(std::max<int64_t>(n, 1));
+  if (n == 0) {
+    for (int i = 0; i < 4; ++i) out[i] = 0.0;
+    return check_flags(c);
+  }
+  double* u = c->angbuf + 2 * c->angcap;
+  double* part = u + 2 * angle_pad(c->angcap);
+  const int nb = (int)((P + kBlock - 1) / kBlock);
+  double* res = part + 4 * ((angle_pad(c->angcap) + kBlock - 1) / kBlock);
+  k_angle_map<<<nb, kBlock, 0, c->stream>>>(c->angbuf, n, P, u);
+  for (int64_t k = 2; k <= P; k <<= 1)
+    for (int64_t j = k >> 1; j > 0; j >>= 1)
+      k_bitonic_stage<<<(int)((2 * P + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(u, P, k, j);
+  k_angle_err<<<nb, kBlock, 0, c->stream>>>(u, n, P, part);
+  k_angle_final<<<1, kBlock, 0, c->stream>>>(part, nb, n, res);
+  LAUNCH_CHECK(c, "angle errors");
+  HIP_TRY(c, hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return check_flags(c);
 }
 
 int pic_stats(pic_ctx* c, pic_stats_t* out) {

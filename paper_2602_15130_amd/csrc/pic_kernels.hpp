@@ -17,7 +17,7 @@ enum { kFlagCgNoConv = 0, kFlagBarrier = 1, kFlagNonFinite = 2, kFlagCapacity = 
 constexpr int64_t kMaxPairsPerOutcome = int64_t(1) << 22;
 constexpr int kMaxStableCell = 1 << 16;
 // 64-bit counters: accepted collisions, candidate pairs with g > g_max, pair-log records.
-enum { kCntAccepted = 0, kCntGmax = 1, kCntPairLog = 2, kCntCount = 4 };
+enum { kCntAccepted = 0, kCntGmax = 1, kCntPairLog = 2, kCntAngles = 3, kCntCount = 4 };
 
 // ---------------------------------------------------------------------------
 // Block reductions with a fixed combination order (bitwise reproducible).
@@ -555,6 +555,27 @@ __global__ void __launch_bounds__(kBlock) k_gradient(SimConst K, const double* p
 // (eq. avg_outcome).  One thread per cell; the private velocity copy of an
 // outcome lives in `u` at the cell's own particle slots.
 // ---------------------------------------------------------------------------
+// Scattering angles of an accepted collision recovered from the post-collision
+// relative velocity g' = v_p' - v_q' with the pre-collision speed g
+// (eq. angle_recovery): chi = acos(g'_z / g), eps = atan2(g'_y, g'_x) in
+// [0, 2 pi).  Appended to `log` (chi, eps pairs) while it has room; the
+// counter keeps counting past the capacity.
+template <class R>
+__device__ inline void record_angles(const R up[3], const R uq[3], R g, double* log, int64_t cap,
+                                     unsigned long long* counters) {
+  if (!log) return;
+  double gx = (double)(up[0] - uq[0]), gy = (double)(up[1] - uq[1]), gz = (double)(up[2] - uq[2]);
+  double cz = gz / (double)g;
+  cz = fmin(1.0, fmax(-1.0, cz));
+  double chi = acos(cz), eps = atan2(gy, gx);
+  if (eps < 0.0) eps += 2.0 * kPi;
+  unsigned long long s = atomicAdd(&counters[kCntAngles], 1ull);
+  if ((int64_t)s < cap) {
+    log[2 * s] = chi;
+    log[2 * s + 1] = eps;
+  }
+}
+
 __device__ inline uint64_t redraw_word(const SimConst& K, int cell, int64_t step, int call, int k,
                                        int64_t m, const U64x4& wb, int r) {
   if (r < 3) return wb.w[1 + r];
@@ -632,6 +653,8 @@ __global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, in
           *up[d] = vcm + 0.5 * g * nv[d];
           *uq[d] = vcm - 0.5 * g * nv[d];
         }
+        const double pv[3] = {*up[0], *up[1], *up[2]}, qv[3] = {*uq[0], *uq[1], *uq[2]};
+        record_angles<double>(pv, qv, g, K.anglog, K.angcap, counters);
       }
       if (pairlog) {
         unsigned long long slot = atomicAdd(&counters[kCntPairLog], 1ull);

@@ -157,11 +157,15 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
       R cchi = (R)1.0 - (R)2.0 * unif_r<R>(wb.w[0]);  // eq. chi_iso
       R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
       R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
+      R pn[3], qn[3];
       for (int d = 0; d < 3; ++d) {
         R vcm = (R)0.5 * (up[d] + uq[d]);
-        u[d * stu + p] = vcm + (R)0.5 * g * nv[d];
-        u[d * stu + q] = vcm - (R)0.5 * g * nv[d];
+        pn[d] = vcm + (R)0.5 * g * nv[d];
+        qn[d] = vcm - (R)0.5 * g * nv[d];
+        u[d * stu + p] = pn[d];
+        u[d * stu + q] = qn[d];
       }
+      record_angles<R>(pn, qn, g, K.anglog, K.angcap, counters);
       if (mark[p] != tag) {
         mark[p] = tag;
         tl[ntl++] = p;
@@ -253,11 +257,15 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
         iq = cnt++;
         pslot[iq] = q;
       }
+      R pn[3], qn[3];
       for (int d = 0; d < 3; ++d) {
         R vcm = (R)0.5 * (up[d] + uq[d]);
-        pdv[d * kPool + ip] = vcm + (R)0.5 * g * nv[d];
-        pdv[d * kPool + iq] = vcm - (R)0.5 * g * nv[d];
+        pn[d] = vcm + (R)0.5 * g * nv[d];
+        qn[d] = vcm - (R)0.5 * g * nv[d];
+        pdv[d * kPool + ip] = pn[d];
+        pdv[d * kPool + iq] = qn[d];
       }
+      record_angles<R>(pn, qn, g, K.anglog, K.angcap, counters);
     }
     if (pairlog) {
       unsigned long long s = atomicAdd(&counters[kCntPairLog], 1ull);

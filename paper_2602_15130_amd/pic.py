@@ -72,6 +72,10 @@ def _load():
     L.pic_get_state.argtypes = [vp, C.c_int, vp, i64]
     L.pic_timing_enable.argtypes = [vp, C.c_int]
     L.pic_timing_read.argtypes = [vp, P(C.c_double), P(i64)]
+    L.pic_angle_buffer_bytes.argtypes = [i64]
+    L.pic_angle_buffer_bytes.restype = i64
+    L.pic_angle_log.argtypes = [vp, vp, i64]
+    L.pic_angle_errors.argtypes = [vp, P(C.c_double), P(i64)]
     L.pic_destroy.argtypes = [vp]
     L.pic_destroy.restype = None
     L.pic_last_error.argtypes = [vp]
@@ -83,6 +87,7 @@ lib = _load()
 
 EXPORTED = ("pic_workspace_size", "pic_init_manufactured", "pic_step", "pic_collide", "pic_errors",
             "pic_stats", "pic_get_state", "pic_timing_enable", "pic_timing_read", "pic_destroy",
+            "pic_angle_buffer_bytes", "pic_angle_log", "pic_angle_errors",
             "pic_last_error")
 STAGES = ("collide", "kick", "drift", "sort", "deposit", "cg", "gradient", "particle")
 
@@ -186,6 +191,21 @@ def pic_timing_read(ctx) -> dict:
     return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
 
 
+def pic_angle_buffer_bytes(capacity: int) -> int:
+    return lib.pic_angle_buffer_bytes(int(capacity))
+
+
+def pic_angle_log(ctx, buffer_ptr, capacity: int):
+    _check(lib.pic_angle_log(ctx, buffer_ptr, int(capacity)), ctx)
+
+
+def pic_angle_errors(ctx):
+    out = (C.c_double * 4)()
+    n = C.c_int64()
+    _check(lib.pic_angle_errors(ctx, out, C.byref(n)), ctx)
+    return list(out), n.value
+
+
 def pic_destroy(ctx):
     lib.pic_destroy(ctx)
 
@@ -232,6 +252,29 @@ class Sim:
 
     def errors(self) -> dict:
         return pic_errors(self.ctx)
+
+    def angle_log(self, capacity: int):
+        """Record (chi, eps) of every accepted collision from now on, up to `capacity`."""
+        import torch
+
+        nbytes = pic_angle_buffer_bytes(capacity)
+        self._ang = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._ang.data_ptr() + 255) // 256 * 256 if capacity > 0 else 0
+        self._ang_ptr, self._ang_cap = ptr, capacity
+        pic_angle_log(self.ctx, ptr, capacity)
+
+    def angle_errors(self):
+        """(eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps), number of records."""
+        return pic_angle_errors(self.ctx)
+
+    def angle_records(self, n: int) -> np.ndarray:
+        """The first n records as an [n, 2] host array (chi, eps)."""
+        import torch
+
+        self.stream.synchronize()
+        off = self._ang_ptr - self._ang.data_ptr()
+        raw = self._ang[off: off + 16 * n].view(torch.float64)
+        return raw.cpu().numpy().reshape(n, 2)
 
     def timing(self, enable: bool):
         pic_timing_enable(self.ctx, enable)

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "pic.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(pic_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(pic_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_four_core_calls():
