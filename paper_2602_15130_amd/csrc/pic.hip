@@ -18,6 +18,7 @@
 #include "pic_cg_brick.hpp"
 #include "pic_lowmode.hpp"
 #include "pic_angles.hpp"
+#include "pic_collide_heavy.hpp"
 
 using namespace pic;
 
@@ -273,6 +274,8 @@ struct pic_ctx {
   int cg_nbr[3] = {0, 0, 0};    // bricks per axis
   size_t cg_lds = 0;            // padded brick, bytes of LDS
   int low_k = 0;                // Fourier modes per axis solved exactly before the CG
+  bool heavy = false;           // collision calls by k_collide_heavy (many pairs per outcome)
+  int heavy_bits = 0;           // its fixed-point scale
   double* angbuf = nullptr;     // scattering-angle records and their sort scratch
   int64_t angcap = 0;
   LowArgs low{};
@@ -521,8 +524,12 @@ int field_solve(pic_ctx* c, double t) {
 int collide(pic_ctx* c, int call, int64_t step, double* D, long long* pairlog, int64_t cap) {
   const SimConst& K = c->K;
   StageTimer tm(c, PIC_STAGE_COLLIDE);
-  k_collide_f64<<<grid_for(K.nn), kBlock, 0, c->stream>>>(K, call, step, c->v[c->cur], c->cstart, D,
-                                                          c->U, pairlog, cap, c->cnt, c->flags);
+  if (c->heavy)
+    k_collide_heavy<<<K.nn, 64 * kHeavyWaves, kHeavyLdsBytes, c->stream>>>(
+        K, call, step, c->v[c->cur], c->cstart, D, c->heavy_bits, pairlog, cap, c->cnt, c->flags);
+  else
+    k_collide_f64<<<grid_for(K.nn), kBlock, 0, c->stream>>>(K, call, step, c->v[c->cur], c->cstart,
+                                                            D, c->U, pairlog, cap, c->cnt, c->flags);
   LAUNCH_CHECK(c, "collide");
   return PIC_OK;
 }
@@ -740,6 +747,22 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   {
     const char* e = std::getenv("PIC_UNFUSED");
     c->fused = !(e && e[0] == '1') || precision == PIC_MIXED;
+    // Many candidate pairs per outcome at the mean cell occupancy (the paper's
+    // refinement ladder): the FP64 form runs its collision calls with
+    // k_collide_heavy in the separate-kernel step.  PIC_HEAVY=0/1 overrides.
+    const double nbar = (double)disc->n_particles / ((double)disc->ncell[0] * disc->ncell[1] * disc->ncell[2]);
+    const double pairs = nbar * (nbar - 1.0) * c->K.pmax / 2.0;
+    bool heavy = precision == PIC_FP64 && c->K.collisions && (double)c->K.navg * pairs >= 64.0;
+    if (const char* h = std::getenv("PIC_HEAVY")) heavy = precision == PIC_FP64 && h[0] == '1';
+    if (heavy && hipFuncSetAttribute((const void*)k_collide_heavy,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kHeavyLdsBytes) != hipSuccess) {
+      (void)hipGetLastError();
+      heavy = false;
+    }
+    c->heavy = heavy;
+    c->heavy_bits = heavy_scale_bits(c->K.g_max, c->K.navg);
+    if (heavy) c->fused = false;
   }
   c->cg_tol = disc->cg_tol;
   c->cg_max_iter = disc->cg_max_iter;

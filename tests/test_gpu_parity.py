@@ -374,3 +374,39 @@ def test_lowmode_presolve_matches_plain_cg(nc):
         o.step(2)
         po = o.get(o.PHI)
         assert _rel(g.get(P.STATE_PHI), po, np.abs(po).max()) < kap * 1e-13
+
+
+# ----------------------------------------------------------------------------- collision-heavy regime
+def test_heavy_collision_kernel_matches_serial_and_oracle():
+    """Table 1 level 2 (101 particles per cell, N_avg = 243, ~6 candidate pairs
+    per outcome) runs its collision calls in k_collide_heavy: its pair list is
+    identical to the serial kernel's, its <dv> agrees to the fixed-point
+    quantum (far below FP64 state rounding), and sampled cells agree with the
+    oracle's Algorithm 1."""
+    prob = W.paper_problem(collisions=True)
+    disc = dict(W.paper_level(2))
+    P = _pic()
+    g = P.Sim(prob, disc, 1, 0)
+    h = _with_env("PIC_HEAVY", "0", lambda: P.Sim(prob, disc, 1, 0))
+    cap = 4_000_000
+    dg, sg, lg, ng = g.collide(0, 0.0, pairlog_cap=cap)
+    dh, sh, lh, nh = h.collide(0, 0.0, pairlog_cap=cap)
+    assert ng == nh and 0 < ng <= cap
+
+    def srt(a):
+        a = np.asarray(a, dtype=np.int64).reshape(-1, 7)
+        return a[np.lexsort((a[:, 3], a[:, 2], a[:, 1], a[:, 0]))]
+
+    np.testing.assert_array_equal(srt(lg), srt(lh))
+    scale = np.abs(g.get(P.STATE_V)).max()
+    assert _rel(dg, dh, scale) < 1e-13
+    np.testing.assert_array_equal(sg, sh)
+    v = g.get(P.STATE_V)
+    cs = g.get(P.STATE_CELL_START)
+    for cell in np.random.default_rng(3).choice(12**3, size=6, replace=False):
+        s, e = cs[cell], cs[cell + 1]
+        do, _, _, _ = O.collide_cell(prob, disc, 1, 0, 0, 0, int(cell), v[:, s:e])
+        assert _rel(dg[:, s:e], do, scale) < 1e-12
+    g.step(2)
+    h.step(2)
+    assert _rel(g.get(P.STATE_V), h.get(P.STATE_V), scale) < 1e-11
