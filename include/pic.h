@@ -186,6 +186,16 @@ int pic_angle_log(pic_ctx* ctx, void* device_buffer, int64_t capacity);
  * PIC_EINVAL when no log is enabled. */
 int pic_angle_errors(pic_ctx* ctx, double out[4], int64_t* n_records);
 
+/* Checkpoint and resume: the whole evolving state (particles in their current
+ * cell-sorted order, cells, tile tables, charge, potential, field, counters,
+ * step) to and from host memory.  A context created with the same problem,
+ * discretization, seed, replicate and precision and loaded from a checkpoint
+ * continues bit for bit as the saved one would.  Save and load synchronise;
+ * load returns PIC_EINVAL for a checkpoint of another problem. */
+int pic_checkpoint_bytes(pic_ctx* ctx, int64_t* bytes);
+int pic_checkpoint_save(pic_ctx* ctx, void* host_dst, int64_t bytes);
+int pic_checkpoint_load(pic_ctx* ctx, const void* host_src, int64_t bytes);
+
 /* Counters of the last completed work (synchronises). */
 typedef struct {
   int64_t step;             /* completed time steps */

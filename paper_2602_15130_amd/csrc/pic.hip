@@ -1035,6 +1035,117 @@ int64_t angle_pad(int64_t cap) {
 }
 }  // namespace
 
+namespace {
+// Checkpoint: a header, then the arrays that carry the state from one pic_step
+// call to the next: the particle arrays of the current buffer (in their cell-
+// sorted order), the cells and cell starts, the tile tables, the charge, the
+// potential (the next solve's warm start), the nodal field and the counters.
+struct CkptHeader {
+  uint32_t magic, version;
+  int32_t precision, cur;
+  int64_t np, nn, step;
+  uint64_t seed;
+  uint32_t rep;
+  int32_t navg;
+  double dt;
+};
+constexpr uint32_t kCkptMagic = 0x31434950u;  // "PIC1"
+
+int ckpt_arrays(const pic_ctx* c, int* a) {
+  int n = 0;
+  const int k = c->cur;
+  if (c->precision == PIC_FP64) {
+    a[n++] = k ? A_X1 : A_X0;
+    a[n++] = k ? A_V1 : A_V0;
+    a[n++] = k ? A_SH1 : A_SH0;
+  } else {
+    a[n++] = k ? A_OFF1 : A_OFF0;
+    a[n++] = k ? A_VF1 : A_VF0;
+    a[n++] = k ? A_ASF1 : A_ASF0;
+    a[n++] = A_E32;
+  }
+  a[n++] = k ? A_ID1 : A_ID0;
+  a[n++] = A_KEY;
+  a[n++] = A_CSTART;
+  a[n++] = A_TILE;
+  a[n++] = A_RHO;
+  a[n++] = A_PHI;
+  a[n++] = A_E;
+  a[n++] = A_CNT;
+  return n;
+}
+
+int64_t ckpt_bytes(const pic_ctx* c) {
+  int a[16];
+  const int n = ckpt_arrays(c, a);
+  int64_t t = sizeof(CkptHeader);
+  for (int i = 0; i < n; ++i) t += c->layout.bytes[a[i]];
+  return t;
+}
+}  // namespace
+
+int pic_checkpoint_bytes(pic_ctx* c, int64_t* bytes) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (!bytes) return PIC_EINVAL;
+  *bytes = ckpt_bytes(c);
+  return PIC_OK;
+}
+
+int pic_checkpoint_save(pic_ctx* c, void* host_dst, int64_t bytes) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (!host_dst || bytes != ckpt_bytes(c)) {
+    c->err = "checkpoint save: buffer size must equal pic_checkpoint_bytes";
+    return PIC_EINVAL;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  TRY(check_flags(c));
+  CkptHeader h{kCkptMagic, 1u, c->precision, c->cur, c->K.np, (int64_t)c->K.nn, c->step,
+               c->K.seed, c->K.rep, c->K.navg, c->K.dt};
+  char* dst = (char*)host_dst;
+  std::memcpy(dst, &h, sizeof(h));
+  dst += sizeof(h);
+  int a[16];
+  const int n = ckpt_arrays(c, a);
+  for (int i = 0; i < n; ++i) {
+    HIP_TRY(c, hipMemcpy(dst, c->ws + c->layout.off[a[i]], c->layout.bytes[a[i]],
+                         hipMemcpyDeviceToHost));
+    dst += c->layout.bytes[a[i]];
+  }
+  return PIC_OK;
+}
+
+int pic_checkpoint_load(pic_ctx* c, const void* host_src, int64_t bytes) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (!host_src || bytes < (int64_t)sizeof(CkptHeader)) {
+    c->err = "checkpoint load: no header";
+    return PIC_EINVAL;
+  }
+  CkptHeader h;
+  std::memcpy(&h, host_src, sizeof(h));
+  if (h.magic != kCkptMagic || h.version != 1u || h.precision != c->precision ||
+      h.np != c->K.np || h.nn != (int64_t)c->K.nn || h.seed != c->K.seed || h.rep != c->K.rep ||
+      h.navg != c->K.navg || h.dt != c->K.dt || (h.cur != 0 && h.cur != 1)) {
+    c->err = "checkpoint load: the checkpoint belongs to another problem, seed or precision";
+    return PIC_EINVAL;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->cur = h.cur;
+  if (bytes != ckpt_bytes(c)) {
+    c->err = "checkpoint load: size mismatch";
+    return PIC_EINVAL;
+  }
+  const char* src = (const char*)host_src + sizeof(h);
+  int a[16];
+  const int n = ckpt_arrays(c, a);
+  for (int i = 0; i < n; ++i) {
+    HIP_TRY(c, hipMemcpy(c->ws + c->layout.off[a[i]], src, c->layout.bytes[a[i]],
+                         hipMemcpyHostToDevice));
+    src += c->layout.bytes[a[i]];
+  }
+  c->step = h.step;
+  return PIC_OK;
+}
+
 int64_t pic_angle_buffer_bytes(int64_t capacity) {
   if (capacity < 1) return 0;
   const int64_t P = angle_pad(capacity);

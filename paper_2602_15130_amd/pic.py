@@ -76,6 +76,9 @@ def _load():
     L.pic_angle_buffer_bytes.restype = i64
     L.pic_angle_log.argtypes = [vp, vp, i64]
     L.pic_angle_errors.argtypes = [vp, P(C.c_double), P(i64)]
+    L.pic_checkpoint_bytes.argtypes = [vp, P(i64)]
+    L.pic_checkpoint_save.argtypes = [vp, vp, i64]
+    L.pic_checkpoint_load.argtypes = [vp, vp, i64]
     L.pic_destroy.argtypes = [vp]
     L.pic_destroy.restype = None
     L.pic_last_error.argtypes = [vp]
@@ -88,6 +91,7 @@ lib = _load()
 EXPORTED = ("pic_workspace_size", "pic_init_manufactured", "pic_step", "pic_collide", "pic_errors",
             "pic_stats", "pic_get_state", "pic_timing_enable", "pic_timing_read", "pic_destroy",
             "pic_angle_buffer_bytes", "pic_angle_log", "pic_angle_errors",
+            "pic_checkpoint_bytes", "pic_checkpoint_save", "pic_checkpoint_load",
             "pic_last_error")
 STAGES = ("collide", "kick", "drift", "sort", "deposit", "cg", "gradient", "particle")
 
@@ -206,6 +210,19 @@ def pic_angle_errors(ctx):
     return list(out), n.value
 
 
+def pic_checkpoint_save(ctx) -> bytes:
+    n = C.c_int64()
+    _check(lib.pic_checkpoint_bytes(ctx, C.byref(n)), ctx)
+    buf = C.create_string_buffer(n.value)
+    _check(lib.pic_checkpoint_save(ctx, buf, n.value), ctx)
+    return buf.raw
+
+
+def pic_checkpoint_load(ctx, data: bytes):
+    buf = C.create_string_buffer(data, len(data))
+    _check(lib.pic_checkpoint_load(ctx, buf, len(data)), ctx)
+
+
 def pic_destroy(ctx):
     lib.pic_destroy(ctx)
 
@@ -252,6 +269,12 @@ class Sim:
 
     def errors(self) -> dict:
         return pic_errors(self.ctx)
+
+    def checkpoint(self) -> bytes:
+        return pic_checkpoint_save(self.ctx)
+
+    def restore(self, data: bytes):
+        pic_checkpoint_load(self.ctx, data)
 
     def angle_log(self, capacity: int):
         """Record (chi, eps) of every accepted collision from now on, up to `capacity`."""

@@ -410,3 +410,26 @@ def test_heavy_collision_kernel_matches_serial_and_oracle():
     g.step(2)
     h.step(2)
     assert _rel(g.get(P.STATE_V), h.get(P.STATE_V), scale) < 1e-11
+
+
+# ----------------------------------------------------------------------------- checkpoint
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_checkpoint_resume_is_bitwise(precision):
+    """A context restored from a checkpoint continues exactly as the original;
+    a checkpoint of another seed is refused."""
+    prob, disc = _small(16, 60000, 1e-3, 4, collisionality=3.0)
+    P = _pic()
+    g = P.Sim(prob, disc, 4, 0, precision)
+    g.step(3)
+    data = g.checkpoint()
+    h = P.Sim(prob, disc, 4, 0, precision)
+    h.restore(data)
+    g.step(2)
+    h.step(2)
+    for item in (P.STATE_X, P.STATE_V, P.STATE_ID, P.STATE_CELL_START, P.STATE_PHI, P.STATE_RHO):
+        np.testing.assert_array_equal(g.get(item), h.get(item))
+    assert g.stats()["n_accepted"] == h.stats()["n_accepted"] and h.stats()["step"] == 5
+    other = P.Sim(prob, disc, 5, 0, precision)
+    with pytest.raises(P.PicError) as ei:
+        other.restore(data)
+    assert ei.value.code == P.PIC_EINVAL

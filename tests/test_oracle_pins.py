@@ -795,3 +795,19 @@ def test_error2_hides_from_the_angle_metric_for_isotropic_velocities():
     rec, e = _angle_run(prob, disc, 3)
     assert len(rec) > 20000
     assert np.all(e[[1, 3]] * math.sqrt(len(rec)) < 2.0)
+
+
+def test_fixed_navg_collisional_error_does_not_converge():
+    """The collision error of one step is a random walk over N_avg outcomes;
+    with N_avg held fixed while h and dt shrink it does not decrease (the
+    paper ties N_avg to the refinement for that reason), whereas phi, which
+    the one-way field solve never couples to the particles, stays second order."""
+    norms = []
+    for L in W.order_ladder((0, 1), collisions=True, navg=16):
+        o = O.Sim(L["problem"], L["disc"], 1, 0)
+        assert o.init() == 0
+        o.step(L["disc"]["steps"])
+        norms.append(o.errors()["l2"])
+    orders = np.array(W.observed_orders(norms)[0])
+    assert np.all(orders[3:6] < 1.0), orders      # velocities
+    assert 1.8 < orders[6] < 2.2, orders          # phi
