@@ -434,11 +434,11 @@ int sort_particles(pic_ctx* c) {
   int s = c->cur, d = 1 - c->cur;
   const int ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
   if (c->precision == PIC_FP64)
-    k_order_tiles<double><<<ntiles, kBlock, 0, c->stream>>>(
+    k_order_tiles<double><<<ntiles, kTileThreads, 0, c->stream>>>(
         c->tile_c0, c->tile_s0, c->tidx, c->tkey, c->cstart, c->x[s], c->v[s], c->sh[s], c->id[s],
         c->x[d], c->v[d], c->sh[d], c->id[d], c->key, np, c->flags);
   else
-    k_order_tiles<float><<<ntiles, kBlock, 0, c->stream>>>(
+    k_order_tiles<float><<<ntiles, kTileThreads, 0, c->stream>>>(
         c->tile_c0, c->tile_s0, c->tidx, c->tkey, c->cstart, c->off[s], c->vf[s], c->asf[s],
         c->id[s], c->off[d], c->vf[d], c->asf[d], c->id[d], c->key, np, c->flags);
   LAUNCH_CHECK(c, "sort");
@@ -455,7 +455,7 @@ int field_solve(pic_ctx* c, double t) {
     const int ntiles = (int)((K.np + kTileB - 1) / kTileB);
     if (c->precision == PIC_FP64) {
       if (c->fused)
-        k_deposit_tiles_f64<<<ntiles, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
+        k_deposit_tiles_f64<<<ntiles, kTileThreads, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
                                                               c->tile_c0, (double*)c->mom);
       else
         k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
@@ -464,7 +464,7 @@ int field_solve(pic_ctx* c, double t) {
                                                         c->partA);
     } else {
       if (c->fused)
-        k_deposit_tiles_mixed<<<ntiles, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
+        k_deposit_tiles_mixed<<<ntiles, kTileThreads, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
                                                                 c->tile_c0, (float*)c->mom);
       else
         k_deposit_moments_mixed<<<nbn, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
@@ -611,21 +611,21 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
     MixConst M = mix_const(K, tA, tB);
     const int s = c->cur;
     if (sig == kSigHS)
-      k_particles_mixed<kSigHS><<<tiles, kBlock, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+      k_particles_mixed<kSigHS><<<tiles, kTileThreads, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
     else if (sig == kSigMaxwell)
-      k_particles_mixed<kSigMaxwell><<<tiles, kBlock, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+      k_particles_mixed<kSigMaxwell><<<tiles, kTileThreads, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
     else
-      k_particles_mixed<kSigPoly><<<tiles, kBlock, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+      k_particles_mixed<kSigPoly><<<tiles, kTileThreads, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
     LAUNCH_CHECK(c, "particles (mixed)");
     return PIC_OK;
   }
   if (K.family == 1) {
-    if (sig == kSigHS) k_particles_f64<1, kSigHS><<<tiles, kBlock, 0, c->stream>>>(K, a);
-    else if (sig == kSigMaxwell) k_particles_f64<1, kSigMaxwell><<<tiles, kBlock, 0, c->stream>>>(K, a);
-    else k_particles_f64<1, kSigPoly><<<tiles, kBlock, 0, c->stream>>>(K, a);
+    if (sig == kSigHS) k_particles_f64<1, kSigHS><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
+    else if (sig == kSigMaxwell) k_particles_f64<1, kSigMaxwell><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
+    else k_particles_f64<1, kSigPoly><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
   } else {
-    if (sig == kSigMaxwell) k_particles_f64<0, kSigMaxwell><<<tiles, kBlock, 0, c->stream>>>(K, a);
-    else k_particles_f64<0, kSigPoly><<<tiles, kBlock, 0, c->stream>>>(K, a);
+    if (sig == kSigMaxwell) k_particles_f64<0, kSigMaxwell><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
+    else k_particles_f64<0, kSigPoly><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
   }
   LAUNCH_CHECK(c, "particles");
   return PIC_OK;

@@ -100,7 +100,7 @@ __device__ inline void cic_weights_mixed(const float o[3], float w[8]) {
       for (int cx = 0; cx < 2; ++cx) w[cz * 4 + cy * 2 + cx] = wx[cx] * wy[cy] * wz[cz];
 }
 
-__global__ void __launch_bounds__(kBlock) k_deposit_tiles_mixed(SimConst K, const float* off,
+__global__ void __launch_bounds__(kTileThreads) k_deposit_tiles_mixed(SimConst K, const float* off,
                                                                 const int* cstart,
                                                                 const int* tile_c0, float* mom) {
   __shared__ float W[8 * kLdsSlots];
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles_mixed(SimConst K, cons
   const bool lds = ns <= kLdsSlots;
   const int NP = (int)K.np;
   if (lds) {
-    for (int j = threadIdx.x; j < ns; j += kBlock) {
+    for (int j = threadIdx.x; j < ns; j += kTileThreads) {
       const int p = s0 + j;
       float o[3] = {off[p], off[NP + p], off[2 * NP + p]}, w[8];
       cic_weights_mixed(o, w);
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles_mixed(SimConst K, cons
     }
     __syncthreads();
   }
-  for (int l = threadIdx.x; l < 8 * ncells; l += kBlock) {
+  for (int l = threadIdx.x; l < 8 * ncells; l += kTileThreads) {
     const int k = l & 7, c = c0 + (l >> 3);
     const int a = cstart[c] - s0, e = cstart[c + 1] - s0;
     float sum = 0.0f, comp = 0.0f;
@@ -267,7 +267,7 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 // Registers are capped for six waves per SIMD (measured best at 64^3: the pass
 // is latency bound, and the extra resident waves outweigh the spills).
 template <int SIG>
-__global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
+__global__ void __launch_bounds__(kTileThreads, 6) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
   // Tile-resident copies of everything the pass reads per particle; the
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
   int* tl = a.gtl + s0;
   const float navg_f = (float)K.navg;
 
-  for (int j = tid; j < ns; j += kBlock) {
+  for (int j = tid; j < ns; j += kTileThreads) {
     const int p = s0 + j;
     for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + p];
     if (lds) {
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                              NP, cl);
-    for (int j = tid; j < ns; j += kBlock) {
+    for (int j = tid; j < ns; j += kTileThreads) {
       int n = cell_count(j);
       float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
       float coef = M.src_w * (float)(n - 1);
@@ -363,10 +363,10 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
     if (K.collisions)
       tile_collide<SIG, float>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                NP, cl);
-    for (int j = tid; j < ns; j += kBlock) kick(j, M.emB, K.collisions != 0);
+    for (int j = tid; j < ns; j += kTileThreads) kick(j, M.emB, K.collisions != 0);
     __syncthreads();
     if (!(a.mode & kDoA)) {
-      for (int j = tid; j < ns; j += kBlock)
+      for (int j = tid; j < ns; j += kTileThreads)
         for (int d = 0; d < 3; ++d) vf[(int64_t)d * NP + s0 + j] = v0[d * st + j];
       return;
     }
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(kBlock, 6) k_particles_mixed(SimConst K, MixCo
   if (K.collisions)
     tile_collide<SIG, float>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
                              st, NP, cl);
-  for (int base = 0; base < ns; base += kBlock) {
+  for (int base = 0; base < ns; base += kTileThreads) {
     int j = base + tid;
     bool valid = j < ns;
     int kk = 0;

@@ -26,8 +26,15 @@
 
 namespace pic {
 
-constexpr int kTileB = 256;       // particle slots that start cells in one tile
-constexpr int kLdsSlots = 384;    // LDS-resident slots per tile
+#ifndef PIC_TILE_B
+#define PIC_TILE_B 256
+#endif
+#ifndef PIC_TILE_THREADS
+#define PIC_TILE_THREADS 256
+#endif
+constexpr int kTileB = PIC_TILE_B;               // particle slots that start cells in one tile
+constexpr int kTileThreads = PIC_TILE_THREADS;   // threads of the tile kernels
+constexpr int kLdsSlots = kTileB + kTileB / 2;   // LDS-resident slots per tile
 constexpr int kMaxEvents = 192;   // (cell, outcome) lanes with pairs per tile
 constexpr int kSmallPairs = 4;    // outcomes with at most this many pairs run one per lane
 constexpr int kPool = 64;         // velocity-change records of those outcomes per tile
@@ -350,13 +357,13 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
     L.overflow = 0;
     L.pool_n = 0;
   }
-  for (int j = tid; j < ns; j += kBlock) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
+  for (int j = tid; j < ns; j += kTileThreads) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
   __syncthreads();
   const int navg = K.navg;
   const int ngroups = (navg + 3) >> 2;
   const int64_t lanes = (int64_t)ncells * ngroups;
   // (1) N_pairs of every (cell, outcome), one random block per four outcomes
-  for (int64_t l = tid; l < lanes; l += kBlock) {
+  for (int64_t l = tid; l < lanes; l += kTileThreads) {
     int ci = (int)(l / ngroups), g = (int)(l - (int64_t)ci * ngroups);
     int c = c0 + ci;
     int n = a.cstart[c + 1] - a.cstart[c];
@@ -383,7 +390,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
   unsigned long long acc = 0, gmx = 0;
   // (2) small outcomes, one per lane, into the record pool
   if (!all) {
-    for (int e = tid; e < ne; e += kBlock) {
+    for (int e = tid; e < ne; e += kTileThreads) {
       int np_ = L.evn[e];
       int start = -1;
       if (np_ <= kSmallPairs) {
@@ -406,7 +413,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
     __syncthreads();
   }
   // (3) per cell, in increasing outcome order
-  for (int ci = tid; ci < ncells; ci += kBlock) {
+  for (int ci = tid; ci < ncells; ci += kTileThreads) {
     int c = c0 + ci;
     int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
     if (n < 2) continue;
@@ -430,7 +437,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
 // source to (cell start) + rank.  Same destinations as order_dst; tiles larger
 // than the LDS slots use order_dst itself.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_order_tiles(const int* tile_c0, const int* tile_s0,
+__global__ void __launch_bounds__(kTileThreads) k_order_tiles(const int* tile_c0, const int* tile_s0,
                                                         const int* tidx, const int* tkey,
                                                         const int* cstart, const T* xs,
                                                         const T* vs, const T* as, const int* ids,
@@ -447,10 +454,10 @@ __global__ void __launch_bounds__(kBlock) k_order_tiles(const int* tile_c0, cons
   if (ns <= 0) return;
   const bool lds = ns <= kLdsSlots;
   if (lds) {
-    for (int j = threadIdx.x; j < ns; j += kBlock) lidx[j] = tidx[s0 + j];
+    for (int j = threadIdx.x; j < ns; j += kTileThreads) lidx[j] = tidx[s0 + j];
     __syncthreads();
   }
-  for (int j = threadIdx.x; j < ns; j += kBlock) {
+  for (int j = threadIdx.x; j < ns; j += kTileThreads) {
     const int slot = s0 + j, c = tkey[slot];
     int my, dst;
     if (lds) {
@@ -507,7 +514,7 @@ __device__ inline void cic_weights_f64(const SimConst& K, const double xp[3], do
 // then one lane per (cell, corner) adds its cell's weights in sorted order,
 // the order of the per-cell loop of k_deposit_moments_f64, so the two agree
 // bit for bit.  Tiles larger than the LDS slots read the positions directly.
-__global__ void __launch_bounds__(kBlock) k_deposit_tiles_f64(SimConst K, const double* x,
+__global__ void __launch_bounds__(kTileThreads) k_deposit_tiles_f64(SimConst K, const double* x,
                                                               const int* cstart,
                                                               const int* tile_c0, double* mom) {
   __shared__ double W[8 * kLdsSlots];
@@ -517,7 +524,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles_f64(SimConst K, const 
   const bool lds = ns <= kLdsSlots;
   const int NP = (int)K.np;
   if (lds) {
-    for (int j = threadIdx.x; j < ns; j += kBlock) {
+    for (int j = threadIdx.x; j < ns; j += kTileThreads) {
       const int p = s0 + j;
       double xp[3] = {x[p], x[NP + p], x[2 * NP + p]}, w[8];
       cic_weights_f64(K, xp, w);
@@ -526,7 +533,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles_f64(SimConst K, const 
     }
     __syncthreads();
   }
-  for (int l = threadIdx.x; l < 8 * ncells; l += kBlock) {
+  for (int l = threadIdx.x; l < 8 * ncells; l += kTileThreads) {
     const int k = l & 7, c = c0 + (l >> 3);
     const int a = cstart[c] - s0, e = cstart[c + 1] - s0;
     double m = 0.0;
@@ -596,7 +603,7 @@ __device__ inline void half_kick_f64(const SimConst& K, const double xp[3], cons
 // to match (four waves per SIMD), accepting a few spills: the pass is latency
 // bound and gains more from resident waves than it loses to spill traffic.
 template <int FAM, int SIG>
-__global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArgs a) {
+__global__ void __launch_bounds__(kTileThreads, 4) k_particles_f64(SimConst K, PartArgs a) {
   // the copy-on-write scratch of outcomes run by a cell thread is global
   __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots];
   __shared__ CollideLds<double> cl;
@@ -622,14 +629,14 @@ __global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArg
   const double dt = K.dt;
   const double inv_navg_den = (double)K.navg;
 
-  for (int j = tid; j < ns; j += kBlock)
+  for (int j = tid; j < ns; j += kTileThreads)
     for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
   __syncthreads();
 
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                               NP, cl);
-    for (int j = tid; j < ns; j += kBlock) {
+    for (int j = tid; j < ns; j += kTileThreads) {
       int c = a.key[s0 + j];
       int n = a.cstart[c + 1] - a.cstart[c];
       double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
@@ -649,7 +656,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArg
     if (K.collisions)
       tile_collide<SIG, double>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                 NP, cl);
-    for (int j = tid; j < ns; j += kBlock) {
+    for (int j = tid; j < ns; j += kTileThreads) {
       int p = s0 + j;
       double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
       int cc[3];
@@ -666,7 +673,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArg
     }
     __syncthreads();
     if (!(a.mode & kDoA)) {
-      for (int j = tid; j < ns; j += kBlock)
+      for (int j = tid; j < ns; j += kTileThreads)
         for (int d = 0; d < 3; ++d) a.v[(int64_t)d * NP + s0 + j] = v0[d * st + j];
       return;
     }
@@ -677,7 +684,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_particles_f64(SimConst K, PartArg
   if (K.collisions)
     tile_collide<SIG, double>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
                               st, NP, cl);
-  for (int base = 0; base < ns; base += kBlock) {
+  for (int base = 0; base < ns; base += kTileThreads) {
     int j = base + tid;
     bool valid = j < ns;
     int kk = 0;
