@@ -67,10 +67,12 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_MOM] = 64 * nn;  // 8 FP64 cell moments, or 8 FP32 moments + 8 compensations
   b[A_RHO] = b[A_B] = b[A_PHI] = nn * 8;
   b[A_CGV] = 9 * nn * 8;  // CG vectors r, w, s (two each) and p, or the brick solver's faces
-  {  // low-mode pre-solve: basis tables, eigenvalues, three transform buffers
+  {  // low-mode pre-solve: basis tables, eigenvalues, slab projections, x back-transform
     const int64_t nmax = std::max({d->ncell[0], d->ncell[1], d->ncell[2]});
-    b[A_LOW] = (3 * kLowMaxM * nmax + 3 * kLowMaxM + (int64_t)kLowMaxM * d->ncell[1] * d->ncell[2] +
-                (int64_t)kLowMaxM * kLowMaxM * d->ncell[2] + (int64_t)kLowMaxM * kLowMaxM * d->ncell[0]) * 8;
+    int rows = 0;
+    const int64_t slabs = low_slabs((int)d->ncell[1], (int)d->ncell[2], rows);
+    b[A_LOW] = (3 * kLowMaxM * nmax + 3 * kLowMaxM + slabs * kLowMaxM * kLowMaxM * d->ncell[2] +
+                (int64_t)kLowMaxM * d->ncell[0] * d->ncell[2]) * 8;
   }
   b[A_E] = 3 * nn * 8;
   b[A_E32] = f64 ? 0 : 3 * nn * 4;
@@ -274,6 +276,7 @@ struct pic_ctx {
   int cg_nbr[3] = {0, 0, 0};    // bricks per axis
   size_t cg_lds = 0;            // padded brick, bytes of LDS
   int low_k = 0;                // Fourier modes per axis solved exactly before the CG
+  size_t low_lds[3] = {0, 0, 0};  // dynamic LDS of the three pre-solve passes
   bool heavy = false;           // collision calls by k_collide_heavy (many pairs per outcome)
   int heavy_bits = 0;           // its fixed-point scale
   double* angbuf = nullptr;     // scattering-angle records and their sort scratch
@@ -479,10 +482,10 @@ int field_solve(pic_ctx* c, double t) {
   StageTimer tm_solve(c, PIC_STAGE_CG);
   if (c->low_k > 0) {  // exact solve of the low Fourier modes of the residual
     const LowArgs& L = c->low;
-    k_low_project_x<<<K.nc[1] * K.nc[2], 64, 0, c->stream>>>(K, L, c->b, c->phi);
-    k_low_project_y<<<grid_for((int64_t)L.m[0] * L.m[1] * K.nc[2]), kBlock, 0, c->stream>>>(K, L);
-    k_low_solve<<<1, 1024, 0, c->stream>>>(K, L);
-    k_low_correct<<<nbn, kBlock, 0, c->stream>>>(K, L, c->phi);
+    const int planes = L.slabs * K.nc[2];
+    k_low_project<<<planes, kLowThreads, c->low_lds[0], c->stream>>>(K, L, c->b, c->phi);
+    k_low_solve<<<L.m[1], kLowThreads, c->low_lds[1], c->stream>>>(K, L);
+    k_low_correct<<<planes, kLowThreads, c->low_lds[2], c->stream>>>(K, L, c->phi);
     LAUNCH_CHECK(c, "low-mode solve");
   }
   // arrival flags of every block plus the release word, zeroed before each launch
@@ -889,23 +892,39 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     (void)hipGetLastError();
   }
   // PIC_CG_LOWMODES: Fourier modes per axis solved exactly before the CG (default
-  // 4, at most kLowMaxK; 0 switches the pre-solve off).
+  // kLowDefaultK, at most kLowMaxK; 0 switches the pre-solve off).
   {
-    int kl = kLowMaxK;
+    int kl = kLowDefaultK;
     if (const char* ev = std::getenv("PIC_CG_LOWMODES")) kl = std::max(0, std::min(kLowMaxK, std::atoi(ev)));
-    int nmax = std::max({c->K.nc[0], c->K.nc[1], c->K.nc[2]});
-    int md[3];
-    for (int d = 0; d < 3; ++d) md[d] = 2 * std::min(kl, (c->K.nc[d] - 1) / 2) + 1;
-    c->low_k = (md[0] * md[1] * md[2] > 1) ? kl : 0;
+    const int nmax = std::max({c->K.nc[0], c->K.nc[1], c->K.nc[2]});
+    int lds_cap = 65536;
+    (void)hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const void* fns[3] = {(const void*)k_low_project, (const void*)k_low_solve,
+                          (const void*)k_low_correct};
     LowArgs& L = c->low;
-    for (int d = 0; d < 3; ++d) L.m[d] = md[d];
     L.nmax = nmax;
+    L.slabs = low_slabs(c->K.nc[1], c->K.nc[2], L.rows);
     double* base = c->lowbuf;
     L.tab = base;
     L.mu = base + 3 * kLowMaxM * nmax;
-    L.t1 = base + 3 * kLowMaxM * nmax + 3 * kLowMaxM;
-    L.t2 = L.t1 + (int64_t)kLowMaxM * c->K.nc[1] * c->K.nc[2];
-    L.d1 = L.t2 + (int64_t)kLowMaxM * kLowMaxM * c->K.nc[2];
+    L.t2 = base + 3 * kLowMaxM * nmax + 3 * kLowMaxM;
+    L.e = L.t2 + (int64_t)L.slabs * kLowMaxM * kLowMaxM * c->K.nc[2];
+    // fewer modes where a pass would exceed the LDS of a workgroup
+    c->low_k = 0;
+    for (; kl > 0 && c->low_k == 0; --kl) {
+      for (int d = 0; d < 3; ++d) L.m[d] = 2 * std::min(kl, (c->K.nc[d] - 1) / 2) + 1;
+      if (L.m[0] * L.m[1] * L.m[2] <= 1) break;
+      c->low_lds[0] = (size_t)low_project_lds(L, c->K.nc[0]) * 8;
+      c->low_lds[1] = (size_t)low_solve_lds(L, c->K.nc[0], c->K.nc[2]) * 8;
+      c->low_lds[2] = (size_t)low_correct_lds(L, c->K.nc[0]) * 8;
+      bool fits = true;
+      for (int q = 0; q < 3 && fits; ++q) fits = c->low_lds[q] <= (size_t)lds_cap;
+      for (int q = 0; q < 3 && fits; ++q)
+        fits = hipFuncSetAttribute(fns[q], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)c->low_lds[q]) == hipSuccess;
+      (void)hipGetLastError();
+      if (fits) c->low_k = kl;
+    }
   }
 
   auto init = [&]() -> int {
