@@ -277,6 +277,7 @@ struct pic_ctx {
   size_t cg_lds = 0;            // padded brick, bytes of LDS
   int low_k = 0;                // Fourier modes per axis solved exactly before the CG
   size_t low_lds[3] = {0, 0, 0};  // dynamic LDS of the three pre-solve passes
+  bool count_zero = false;        // cell counts known to be zero (left so by the scan)
   bool heavy = false;           // collision calls by k_collide_heavy (many pairs per outcome)
   int heavy_bits = 0;           // its fixed-point scale
   double* angbuf = nullptr;     // scattering-angle records and their sort scratch
@@ -409,14 +410,29 @@ int fill(pic_ctx* c, T* p, T v, int64_t n) {
   return PIC_OK;
 }
 
-// Exclusive scan of the cell counts into cell_start.
+// Cell counts at zero before a counting pass; the scan leaves them there.
+int zero_counts(pic_ctx* c) {
+  if (!c->count_zero) TRY(fill<int>(c, c->count, 0, c->K.nn));
+  c->count_zero = false;  // the counting pass that follows raises them
+  return PIC_OK;
+}
+
+// Exclusive scan of the cell counts into cell_start; the counts are left at
+// zero and the tile tables of the sorted order are written on the way.
 int scan_counts(pic_ctx* c) {
   int n = c->K.nn;
   int nb = (n + kScanTile - 1) / kScanTile;
-  k_scan_local<<<nb, kBlock, 0, c->stream>>>(c->count, c->cstart, c->bsum, n);
+  TileInit ti;
+  ti.c0 = c->tile_c0;
+  ti.s0 = c->tile_s0;
+  ti.ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
+  ti.ncell = n;
+  ti.np = (int)c->K.np;
+  k_scan_local<<<nb, kBlock, 0, c->stream>>>(c->count, c->cstart, c->bsum, n, ti);
   k_scan_blocks<<<1, kBlock, 0, c->stream>>>(c->bsum, nb, c->cstart, n);
-  k_scan_add<<<nb, kBlock, 0, c->stream>>>(c->cstart, c->bsum, n);
+  k_scan_add<<<nb, kBlock, 0, c->stream>>>(c->cstart, c->bsum, n, c->count, ti);
   LAUNCH_CHECK(c, "scan");
+  c->count_zero = true;
   return PIC_OK;
 }
 
@@ -424,16 +440,9 @@ int scan_counts(pic_ctx* c) {
 int sort_particles(pic_ctx* c) {
   StageTimer tm(c, PIC_STAGE_SORT);
   TRY(scan_counts(c));
-  {  // cell-aligned tiles of the fused particle pass
-    const int ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
-    TRY(fill<int>(c, c->tile_c0, c->K.nn, ntiles + 1));
-    TRY(fill<int>(c, c->tile_s0, (int)c->K.np, ntiles + 1));
-    k_tile_bounds<<<grid_for(c->K.nn), kBlock, 0, c->stream>>>(c->cstart, c->K.nn, c->tile_c0,
-                                                                c->tile_s0, ntiles);
-    LAUNCH_CHECK(c, "tile bounds");
-  }
   int np = (int)c->K.np;
-  k_scatter<<<grid_for(np), kBlock, 0, c->stream>>>(c->key, c->slot, c->cstart, c->tidx, c->tkey, np);
+  k_scatter<<<(int)(((int64_t)np + kBlock * kScatterPer - 1) / (kBlock * kScatterPer)), kBlock, 0,
+              c->stream>>>(c->key, c->slot, c->cstart, c->tidx, c->tkey, np);
   int s = c->cur, d = 1 - c->cur;
   const int ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
   if (c->precision == PIC_FP64)
@@ -475,7 +484,9 @@ int field_solve(pic_ctx* c, double t) {
       k_node_rhs_mixed<<<nbn, kBlock, 0, c->stream>>>(K, (const float*)c->mom, t, c->rho, c->b,
                                                       c->partA);
     }
-    k_sub_mean<<<nbn, kBlock, 0, c->stream>>>(K, c->b, c->partA, nbn);
+    // also zeroes the solver's arrival flags and release word
+    k_sub_mean<<<nbn, kBlock, 0, c->stream>>>(K, c->b, c->partA, nbn, c->bar,
+                                              (c->cg_grid + 1) * kFlagStride);
     LAUNCH_CHECK(c, "rhs");
   }
   // the Poisson solve (low-mode pre-solve and CG) is timed as one stage
@@ -488,8 +499,6 @@ int field_solve(pic_ctx* c, double t) {
     k_low_correct<<<planes, kLowThreads, c->low_lds[2], c->stream>>>(K, L, c->phi);
     LAUNCH_CHECK(c, "low-mode solve");
   }
-  // arrival flags of every block plus the release word, zeroed before each launch
-  TRY(fill<unsigned>(c, c->bar, 0u, (int64_t)(c->cg_grid + 1) * kFlagStride));
   CgArgs a;
   a.b = c->b;
   a.x = c->phi;
@@ -551,7 +560,7 @@ int kick(pic_ctx* c, double t, double t_from, double t_to, double t_src) {
 int drift(pic_ctx* c, double t0, double th, double t1) {
   const SimConst& K = c->K;
   StageTimer tm(c, PIC_STAGE_DRIFT);
-  TRY(fill<int>(c, c->count, 0, K.nn));
+  TRY(zero_counts(c));
   int s = c->cur;
   k_drift_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, t0, th, t1, c->x[s], c->v[s], c->sh[s],
                                                         c->id[s], c->key, c->slot, c->count,
@@ -637,7 +646,7 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
 int particle_pass(pic_ctx* c, int mode, int64_t nb, int64_t na) {
   const SimConst& K = c->K;
   StageTimer tm(c, PIC_STAGE_PARTICLE);
-  if (mode & kDoA) TRY(fill<int>(c, c->count, 0, K.nn));
+  if (mode & kDoA) TRY(zero_counts(c));
   PartArgs a = part_args(c);
   a.mode = mode;
   a.nb = nb;
@@ -931,7 +940,8 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     const SimConst& K = c->K;
     TRY(fill<int>(c, c->flags, 0, kFlagCount));
     TRY(fill<unsigned long long>(c, c->cnt, 0ull, kCntCount));
-    TRY(fill<int>(c, c->count, 0, K.nn));
+    c->count_zero = false;
+    TRY(zero_counts(c));
     TRY(fill<double>(c, c->phi, 0.0, K.nn));
     if (c->low_k > 0) {
       k_low_tables<<<grid_for((int64_t)3 * kLowMaxM * c->low.nmax), kBlock, 0, c->stream>>>(
@@ -1162,6 +1172,7 @@ int pic_checkpoint_load(pic_ctx* c, const void* host_src, int64_t bytes) {
     src += c->layout.bytes[a[i]];
   }
   c->step = h.step;
+  c->count_zero = false;
   return PIC_OK;
 }
 

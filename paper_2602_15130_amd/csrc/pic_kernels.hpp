@@ -9,6 +9,17 @@ namespace pic {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 
+// Cell-aligned particle tiles of the sort and the fused particle pass.
+#ifndef PIC_TILE_B
+#define PIC_TILE_B 256
+#endif
+#ifndef PIC_TILE_THREADS
+#define PIC_TILE_THREADS 256
+#endif
+constexpr int kTileB = PIC_TILE_B;               // particle slots that start cells in one tile
+constexpr int kTileThreads = PIC_TILE_THREADS;   // threads of the tile kernels
+constexpr int kLdsSlots = kTileB + kTileB / 2;   // LDS-resident slots per tile
+
 // Flags raised by kernels and read back at the next synchronising call.
 enum { kFlagCgNoConv = 0, kFlagBarrier = 1, kFlagNonFinite = 2, kFlagCapacity = 3, kFlagCount = 4 };
 // Work bounds that keep every kernel finite on degenerate input (a run-away
@@ -130,7 +141,21 @@ __global__ void __launch_bounds__(kBlock) k_count(const int* key, int* slot, int
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kBlock * kScanItems;
 
-__global__ void __launch_bounds__(kBlock) k_scan_local(const int* in, int* out, int* bsum, int n) {
+// Tile tables of the sort, filled before the third pass writes their bounds.
+struct TileInit {
+  int* c0;     // first cell per tile, filled with the cell count
+  int* s0;     // first particle per tile, filled with the particle count
+  int ntiles;  // entries 0..ntiles
+  int ncell, np;
+};
+
+// Pass 1: per-block exclusive scans and block totals; also fills the tile tables.
+__global__ void __launch_bounds__(kBlock) k_scan_local(const int* in, int* out, int* bsum, int n,
+                                                       TileInit ti) {
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t <= ti.ntiles; t += gridDim.x * kBlock) {
+    ti.c0[t] = ti.ncell;
+    ti.s0[t] = ti.np;
+  }
   __shared__ int sh[kBlock];
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int v[kScanItems], tot = 0;
@@ -182,22 +207,58 @@ __global__ void __launch_bounds__(kBlock) k_scan_blocks(int* bsum, int nb, int* 
   if (threadIdx.x == 0) out[n] = carry;
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_add(int* out, const int* bsum, int n) {
+// Pass 3: adds the block prefixes, giving the cell starts; resets the counts
+// to zero for the next counting pass; and writes the bounds of the cell-aligned
+// tiles, tile_c0[t] = min{c : cstart[c] >= t kTileB} and tile_s0[t] =
+// cstart[tile_c0[t]]: with lo = cstart[j] and hi = cstart[j + 1] = lo + count[j],
+// cell c = j + 1 is that minimum for every t with lo < t kTileB <= hi.  Tile 0
+// starts at cell 0; tiles past the end keep the fill of pass 1.
+__global__ void __launch_bounds__(kBlock) k_scan_add(int* out, const int* bsum, int n, int* count,
+                                                     TileInit ti) {
   int base = blockIdx.x * kScanTile;
   int add = bsum[blockIdx.x];
-  for (int j = threadIdx.x; j < kScanTile; j += kBlock)
-    if (base + j < n) out[base + j] += add;
+  for (int j = threadIdx.x; j < kScanTile; j += kBlock) {
+    const int jj = base + j;
+    if (jj >= n) continue;
+    const int lo = out[jj] + add, hi = lo + count[jj];
+    out[jj] = lo;
+    count[jj] = 0;
+    for (int t = lo / kTileB + 1; t * kTileB <= hi && t <= ti.ntiles; ++t) {
+      ti.c0[t] = jj + 1;
+      ti.s0[t] = hi;
+    }
+    if (jj == 0) {
+      ti.c0[0] = 0;
+      ti.s0[0] = 0;
+    }
+  }
 }
 
+// Scatter slot of every particle: cell start + its slot in the cell;
+// kScatterPer particles per thread, loads issued before the dependent ones.
+constexpr int kScatterPer = 4;
 __global__ void __launch_bounds__(kBlock) k_scatter(const int* key, const int* slot,
                                                     const int* cstart, int* tidx, int* tkey,
                                                     int n) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  int k = key[i];
-  int dst = cstart[k] + slot[i];
-  tidx[dst] = i;
-  tkey[dst] = k;
+  const int base = blockIdx.x * (kBlock * kScatterPer) + threadIdx.x;
+  int k[kScatterPer], sl[kScatterPer];
+#pragma unroll
+  for (int q = 0; q < kScatterPer; ++q) {
+    const int i = base + q * kBlock;
+    if (i < n) {
+      k[q] = key[i];
+      sl[q] = slot[i];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kScatterPer; ++q) {
+    const int i = base + q * kBlock;
+    if (i < n) {
+      const int dst = cstart[k[q]] + sl[q];
+      tidx[dst] = i;
+      tkey[dst] = k[q];
+    }
+  }
 }
 
 // Rank of `my` among the source indices of its cell segment.
@@ -313,8 +374,11 @@ __global__ void __launch_bounds__(kBlock) k_node_rhs(SimConst K, const MomT* mom
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// Removes the mean of b; also zeroes the Poisson solver's barrier words
+// (nbar of them), which must read zero when the solver starts.
 __global__ void __launch_bounds__(kBlock) k_sub_mean(SimConst K, double* b, const double* part,
-                                                     int nparts) {
+                                                     int nparts, unsigned* bar, int nbar) {
+  for (int t = blockIdx.x * kBlock + threadIdx.x; t < nbar; t += gridDim.x * kBlock) bar[t] = 0u;
   __shared__ double sh[kWaves];
   double acc = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kBlock) acc += part[i];

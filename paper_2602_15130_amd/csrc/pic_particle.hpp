@@ -26,15 +26,6 @@
 
 namespace pic {
 
-#ifndef PIC_TILE_B
-#define PIC_TILE_B 256
-#endif
-#ifndef PIC_TILE_THREADS
-#define PIC_TILE_THREADS 256
-#endif
-constexpr int kTileB = PIC_TILE_B;               // particle slots that start cells in one tile
-constexpr int kTileThreads = PIC_TILE_THREADS;   // threads of the tile kernels
-constexpr int kLdsSlots = kTileB + kTileB / 2;   // LDS-resident slots per tile
 constexpr int kMaxEvents = 192;   // (cell, outcome) lanes with pairs per tile
 constexpr int kSmallPairs = 4;    // outcomes with at most this many pairs run one per lane
 constexpr int kPool = 64;         // velocity-change records of those outcomes per tile
@@ -83,26 +74,6 @@ struct PartArgs {
   int callB, callA;     // random-stream call tags (collide-only mode uses callA)
   double tB;            // collide-only: time of the source
 };
-
-// First cell of every tile: tile_c0[t] = min{c : cstart[c] >= t B}.  For c >= 1
-// that is c exactly when cstart[c-1] < t B <= cstart[c], so each cell marks the
-// tiles whose boundary falls in its range; tile_c0 is filled with ncells first
-// and tile 0 starts at cell 0.  tile_s0[t] = cstart[tile_c0[t]], the tile's first
-// particle (filled with np first).
-__global__ void __launch_bounds__(kBlock) k_tile_bounds(const int* cstart, int nn, int* tile_c0,
-                                                        int* tile_s0, int ntiles) {
-  int c = blockIdx.x * kBlock + threadIdx.x + 1;
-  if (c > nn) return;
-  int lo = cstart[c - 1], hi = cstart[c];
-  for (int t = lo / kTileB + 1; t * kTileB <= hi && t <= ntiles; ++t) {
-    tile_c0[t] = c;
-    tile_s0[t] = hi;
-  }
-  if (c == 1) {
-    tile_c0[0] = 0;
-    tile_s0[0] = 0;
-  }
-}
 
 __device__ inline int lower_bound_i(const int* a, int n, int key) {
   int lo = 0, hi = n;
@@ -435,7 +406,9 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
 // slot's rank among the source indices of its own cell, which is its place in
 // the stable order, is counted in LDS, and the particle's state moves from its
 // source to (cell start) + rank.  Same destinations as order_dst; tiles larger
-// than the LDS slots use order_dst itself.
+// than the LDS slots use order_dst itself.  Every global load a slot needs
+// (source index, cell, cell bounds, the state itself) is issued before the
+// block waits for the LDS copy, so a tile costs two dependent load rounds.
 template <class T>
 __global__ void __launch_bounds__(kTileThreads) k_order_tiles(const int* tile_c0, const int* tile_s0,
                                                         const int* tidx, const int* tkey,
@@ -443,41 +416,68 @@ __global__ void __launch_bounds__(kTileThreads) k_order_tiles(const int* tile_c0
                                                         const T* vs, const T* as, const int* ids,
                                                         T* xd, T* vd, T* ad, int* idd, int* keyd,
                                                         int n, int* flags) {
+  constexpr int kPer = (kLdsSlots + kTileThreads - 1) / kTileThreads;
   __shared__ int lidx[kLdsSlots];
-  __shared__ int sh_i[2];
-  if (threadIdx.x == 0) {
-    sh_i[0] = tile_s0[blockIdx.x];
-    sh_i[1] = tile_s0[blockIdx.x + 1];
+  const int s0 = tile_s0[blockIdx.x], ns = tile_s0[blockIdx.x + 1] - s0;
+  if (ns <= 0) return;
+  if (ns > kLdsSlots) {
+    for (int j = threadIdx.x; j < ns; j += kTileThreads) {
+      const int slot = s0 + j, my = tidx[slot];
+      const int dst = order_dst(tidx, tkey, cstart, slot, flags);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        xd[(int64_t)d * n + dst] = xs[(int64_t)d * n + my];
+        vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
+        ad[(int64_t)d * n + dst] = as[(int64_t)d * n + my];
+      }
+      idd[dst] = ids[my];
+      keyd[dst] = tkey[slot];
+    }
+    return;
+  }
+  int my[kPer], cc[kPer], cs[kPer], ce[kPer], idv[kPer];
+  T sv[kPer][9];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int j = threadIdx.x + q * kTileThreads;
+    if (j < ns) {
+      my[q] = tidx[s0 + j];
+      cc[q] = tkey[s0 + j];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int j = threadIdx.x + q * kTileThreads;
+    if (j < ns) {
+      lidx[j] = my[q];
+      cs[q] = cstart[cc[q]] - s0;
+      ce[q] = cstart[cc[q] + 1] - s0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        sv[q][d] = xs[(int64_t)d * n + my[q]];
+        sv[q][3 + d] = vs[(int64_t)d * n + my[q]];
+        sv[q][6 + d] = as[(int64_t)d * n + my[q]];
+      }
+      idv[q] = ids[my[q]];
+    }
   }
   __syncthreads();
-  const int s0 = sh_i[0], ns = sh_i[1] - sh_i[0];
-  if (ns <= 0) return;
-  const bool lds = ns <= kLdsSlots;
-  if (lds) {
-    for (int j = threadIdx.x; j < ns; j += kTileThreads) lidx[j] = tidx[s0 + j];
-    __syncthreads();
-  }
-  for (int j = threadIdx.x; j < ns; j += kTileThreads) {
-    const int slot = s0 + j, c = tkey[slot];
-    int my, dst;
-    if (lds) {
-      my = lidx[j];
-      const int cs = cstart[c] - s0, ce = cstart[c + 1] - s0;
-      int r = 0;
-      for (int k = cs; k < ce; ++k) r += lidx[k] < my;
-      dst = s0 + cs + r;
-    } else {
-      my = tidx[slot];
-      dst = order_dst(tidx, tkey, cstart, slot, flags);
-    }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      xd[(int64_t)d * n + dst] = xs[(int64_t)d * n + my];
-      vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
-      ad[(int64_t)d * n + dst] = as[(int64_t)d * n + my];
+  for (int q = 0; q < kPer; ++q) {
+    const int j = threadIdx.x + q * kTileThreads;
+    if (j < ns) {
+      int r = 0;
+      for (int k = cs[q]; k < ce[q]; ++k) r += lidx[k] < my[q];
+      const int dst = s0 + cs[q] + r;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        xd[(int64_t)d * n + dst] = sv[q][d];
+        vd[(int64_t)d * n + dst] = sv[q][3 + d];
+        ad[(int64_t)d * n + dst] = sv[q][6 + d];
+      }
+      idd[dst] = idv[q];
+      keyd[dst] = cc[q];
     }
-    idd[dst] = ids[my];
-    keyd[dst] = c;
   }
 }
 

@@ -244,13 +244,16 @@ class Sim:
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         ptr = (base + 255) // 256 * 256
+        # held by the instance so that teardown at interpreter exit still finds it
+        self._destroy = lib.pic_destroy
         self.ctx, self.init_status = pic_init_manufactured(
             prob, disc, seed, replicate, precision, ptr, nbytes, self.stream.cuda_stream)
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
-            pic_destroy(ctx)
+        destroy = getattr(self, "_destroy", None)
+        if ctx and destroy is not None:
+            destroy(ctx)
             self.ctx = None
 
     def step(self, n: int = 1):
