@@ -234,8 +234,13 @@ enum pic_stage {
   PIC_STAGE_PARTICLE = 7,   /* the fused particle kernel of the mixed form */
   PIC_STAGE_COUNT = 8
 };
-/* enable != 0 starts (and resets) the accumulation; 0 stops it. */
+/* enable != 0 starts (and resets) the accumulation for every stage; 0 stops it. */
 int pic_timing_enable(pic_ctx* ctx, int enable);
+/* Starts (and resets) the accumulation for the stages whose bit (1u << stage)
+ * is set in mask, so that a measurement can time one stage without the event
+ * records of the others; mask 0 stops it.  Bits at or above PIC_STAGE_COUNT
+ * are ignored.  Synchronises the context stream. */
+int pic_timing_stages(pic_ctx* ctx, uint32_t mask);
 /* ms (host, PIC_STAGE_COUNT doubles): summed milliseconds per stage;
  * launches (host, PIC_STAGE_COUNT int64): number of timed stage instances.
  * Synchronises the context stream. */

@@ -309,6 +309,7 @@ struct pic_ctx {
   unsigned long long* cnt{};
   // stage timing with HIP events on the context stream
   bool timing = false;
+  uint32_t timing_mask = 0;  // stages timed while timing is on (bit 1 << stage)
   struct Timed {
     int stage;
     hipEvent_t a, b;
@@ -365,7 +366,7 @@ struct StageTimer {
   int stage;
   hipEvent_t a = nullptr;
   StageTimer(pic_ctx* ctx, int st) : c(ctx), stage(st) {
-    if (!c->timing) return;
+    if (!c->timing || !((c->timing_mask >> st) & 1u)) return;
     a = take_event(c);
     if (a) (void)hipEventRecord(a, c->stream);
   }
@@ -1305,7 +1306,7 @@ int pic_get_state(pic_ctx* c, int item, void* host_dst, int64_t bytes) {
   return check_flags(c);
 }
 
-int pic_timing_enable(pic_ctx* c, int enable) {
+int pic_timing_stages(pic_ctx* c, uint32_t mask) {
   if (!c || !c->ready) return PIC_ESTATE;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   collect_timing(c);
@@ -1313,8 +1314,13 @@ int pic_timing_enable(pic_ctx* c, int enable) {
     c->stage_ms[i] = 0.0;
     c->stage_n[i] = 0;
   }
-  c->timing = enable != 0;
+  c->timing_mask = mask & ((1u << PIC_STAGE_COUNT) - 1u);
+  c->timing = c->timing_mask != 0;
   return PIC_OK;
+}
+
+int pic_timing_enable(pic_ctx* c, int enable) {
+  return pic_timing_stages(c, enable ? (1u << PIC_STAGE_COUNT) - 1u : 0u);
 }
 
 int pic_timing_read(pic_ctx* c, double* ms, int64_t* launches) {

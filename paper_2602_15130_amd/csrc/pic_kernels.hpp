@@ -19,6 +19,14 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kTileB = PIC_TILE_B;               // particle slots that start cells in one tile
 constexpr int kTileThreads = PIC_TILE_THREADS;   // threads of the tile kernels
 constexpr int kLdsSlots = kTileB + kTileB / 2;   // LDS-resident slots per tile
+// Minimum resident waves per SIMD requested for the fused particle kernels
+// (their register budget is 512 / waves per lane).
+#ifndef PIC_MIXED_WAVES
+#define PIC_MIXED_WAVES 6
+#endif
+#ifndef PIC_F64_WAVES
+#define PIC_F64_WAVES 3
+#endif
 
 // Flags raised by kernels and read back at the next synchronising call.
 enum { kFlagCgNoConv = 0, kFlagBarrier = 1, kFlagNonFinite = 2, kFlagCapacity = 3, kFlagCount = 4 };

@@ -267,7 +267,7 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 // Registers are capped for six waves per SIMD (measured best at 64^3: the pass
 // is latency bound, and the extra resident waves outweigh the spills).
 template <int SIG>
-__global__ void __launch_bounds__(kTileThreads, 6) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
+__global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
   // Tile-resident copies of everything the pass reads per particle; the

@@ -603,7 +603,7 @@ __device__ inline void half_kick_f64(const SimConst& K, const double xp[3], cons
 // to match (four waves per SIMD), accepting a few spills: the pass is latency
 // bound and gains more from resident waves than it loses to spill traffic.
 template <int FAM, int SIG>
-__global__ void __launch_bounds__(kTileThreads, 4) k_particles_f64(SimConst K, PartArgs a) {
+__global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(SimConst K, PartArgs a) {
   // the copy-on-write scratch of outcomes run by a cell thread is global
   __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots];
   __shared__ CollideLds<double> cl;

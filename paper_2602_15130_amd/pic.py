@@ -71,6 +71,7 @@ def _load():
     L.pic_stats.argtypes = [vp, P(pic_stats_t)]
     L.pic_get_state.argtypes = [vp, C.c_int, vp, i64]
     L.pic_timing_enable.argtypes = [vp, C.c_int]
+    L.pic_timing_stages.argtypes = [vp, C.c_uint32]
     L.pic_timing_read.argtypes = [vp, P(C.c_double), P(i64)]
     L.pic_angle_buffer_bytes.argtypes = [i64]
     L.pic_angle_buffer_bytes.restype = i64
@@ -89,7 +90,8 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pic_workspace_size", "pic_init_manufactured", "pic_step", "pic_collide", "pic_errors",
-            "pic_stats", "pic_get_state", "pic_timing_enable", "pic_timing_read", "pic_destroy",
+            "pic_stats", "pic_get_state", "pic_timing_enable", "pic_timing_stages", "pic_timing_read",
+            "pic_destroy",
             "pic_angle_buffer_bytes", "pic_angle_log", "pic_angle_errors",
             "pic_checkpoint_bytes", "pic_checkpoint_save", "pic_checkpoint_load",
             "pic_last_error")
@@ -186,6 +188,14 @@ def pic_get_state(ctx, item: int, out: np.ndarray):
 
 def pic_timing_enable(ctx, enable: bool):
     return _check(lib.pic_timing_enable(ctx, int(bool(enable))), ctx)
+
+
+def pic_timing_stages(ctx, stages):
+    """Time only the named stages (an empty list stops timing)."""
+    mask = 0
+    for name in stages:
+        mask |= 1 << STAGES.index(name)
+    return _check(lib.pic_timing_stages(ctx, mask), ctx)
 
 
 def pic_timing_read(ctx) -> dict:
@@ -304,6 +314,9 @@ class Sim:
 
     def timing(self, enable: bool):
         pic_timing_enable(self.ctx, enable)
+
+    def timing_stages(self, stages):
+        pic_timing_stages(self.ctx, stages)
 
     def timing_read(self) -> dict:
         return pic_timing_read(self.ctx)
