@@ -24,33 +24,42 @@ HBM_PEAK_GBS = 8000.0
 
 def stage_bytes(stage, prob, disc, precision, cg_iters):
     """Algorithmic bytes one launch of a stage must move (reads + writes of the
-    arrays the method needs; mesh arrays counted once)."""
+    arrays the method needs; mesh arrays counted once).  Per particle: position
+    px (three FP64 coordinates, or three FP32 in-cell offsets with the cell
+    index), velocity sv, the manufactured-velocity shape sa (v^M = vbar a, one
+    vector per particle), id and cell key 4 bytes each."""
     np_, nn = disc["np"], disc["nc"][0] * disc["nc"][1] * disc["nc"][2]
     coll = bool(prob["collisions"])
     if precision == "fp64":
-        sx, sv = 24, 24          # FP64 position / velocity per particle
+        px, sv, sa = 24, 24, 24
+        sx = px                  # absolute position
     else:
-        sx, sv = 16, 12          # cell index + 3 FP32 offsets / 3 FP32 velocities
+        px, sv, sa = 12, 12, 12
+        sx = px + 4              # cell index + in-cell offsets
     if stage == "collide":       # velocities in, averaged velocity change out
         return (sv + sv) * np_ + 4 * nn
     if stage == "kick":          # x, v, <dv> and cell key in; v out; E and cell starts
         return (sx + sv + (sv + 4 if coll else 0) + sv) * np_ + 28 * nn
-    if stage == "drift":         # x, v, id in; x, key, slot out
-        return (sx + sv + 4 + sx + 4 + 4) * np_ + 4 * nn
-    if stage == "sort":          # key/slot -> index; gather + scatter of the state
-        return (16 + 8 + 2 * (sx + sv + 4) + 4) * np_ + 12 * nn
+    if stage == "drift":         # x, v, a in; x, key, slot out
+        return (sx + sv + sa + sx + 4 + 4) * np_ + 4 * nn
+    if stage == "sort":          # scatter slots (key, slot -> index, key); the
+        # ordered move reads the indices and gathers/scatters x, v, a, id; key out
+        return (16 + 8 + 2 * (px + sv + sa + 4) + 4) * np_ + 12 * nn
     if stage == "deposit":       # positions in; node charge and right-hand side
         return sx * np_ + 4 * nn + 2 * 64 * nn + 32 * nn
     if stage == "cg":            # per iteration: stencil on p and r, update x, r
         return max(cg_iters, 1) * 80 * nn
     if stage == "gradient":
         return 32 * nn
-    if stage == "particle":      # fused mixed kernel: state in and out, key
-        return (2 * (sx + sv) + 4) * np_ + 28 * nn
+    if stage == "particle":      # fused pass: x, v, a, key in; x, v, key, slot out
+        return (2 * (px + sv) + sa + 4 + 4 + 4) * np_ + 28 * nn
     return 0
 
 
-DEVICE_SOURCES = ("pic_device.hpp", "pic_kernels.hpp", "pic_particle.hpp", "pic_mixed.hpp")
+# Every source that goes into the library: a change to any of them voids the
+# committed counter record.
+DEVICE_SOURCES = ("pic.hip", "pic_device.hpp", "pic_kernels.hpp", "pic_particle.hpp", "pic_mixed.hpp",
+                  "pic_cg_brick.hpp", "pic_lowmode.hpp", "pic_angles.hpp", "pic_collide_heavy.hpp")
 
 
 def measured_traffic(stage, workload):
