@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--levels", default="1,2,3", help="Table 1 levels for --workload table1")
+    ap.add_argument("--cases", default="isolated,coupled,collisionless",
+                    help="Table 1 cases for --workload table1")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes five times (reference for "
                          "hardware byte counters) and exit")
@@ -160,7 +162,7 @@ def main():
         print(json.dumps(run_ensemble_bench()), flush=True)
         return
     if args.workload == "table1":
-        print(json.dumps(run_table1(args.levels)), flush=True)
+        print(json.dumps(run_table1(args.levels, args.cases)), flush=True)
         return
     out = run_workload(pic, W, torch, args.workload, args.steps, args.warmup)
     if args.beside and args.beside != "none":
@@ -194,7 +196,7 @@ def run_ensemble_bench():
             "orders_l2_mean": out["orders_l2_mean"]}
 
 
-def run_table1(levels):
+def run_table1(levels, cases_arg="isolated,coupled,collisionless"):
     """The paper's Table 1 ladder, FP64 form: isolated collisions, fully coupled
     collisional and fully coupled collisionless; l2 / linf norms per level and
     observed orders (progress to stderr, one line per step)."""
@@ -208,7 +210,10 @@ def run_table1(levels):
                               isolate=True),
              "coupled": dict(collisions=True), "collisionless": dict(collisions=False)}
     out = {"workload": "table1", "levels": levels, "cases": {}}
+    wanted = cases_arg.split(",")
     for name, kw in cases.items():
+        if name not in wanted:
+            continue
         prob = W.paper_problem(**kw)
         rows = []
         for lv in levels:

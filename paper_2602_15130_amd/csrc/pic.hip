@@ -537,12 +537,27 @@ int field_solve(pic_ctx* c, double t) {
 int collide(pic_ctx* c, int call, int64_t step, double* D, long long* pairlog, int64_t cap) {
   const SimConst& K = c->K;
   StageTimer tm(c, PIC_STAGE_COLLIDE);
-  if (c->heavy)
+  if (c->heavy) {
+    // workgroup per cell; the few cells beyond its capacity run one thread each
     k_collide_heavy<<<K.nn, 64 * kHeavyWaves, kHeavyLdsBytes, c->stream>>>(
         K, call, step, c->v[c->cur], c->cstart, D, c->heavy_bits, pairlog, cap, c->cnt, c->flags);
-  else
+    LAUNCH_CHECK(c, "collide (heavy)");
+    // (the sort's index arrays are idle here: marks and touched lists)
+    const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
+    const double* vc = c->v[c->cur];
+    if (sig == kSigHS)
+      k_collide_big<kSigHS><<<grid_for(K.nn), kBlock, 0, c->stream>>>(
+          K, call, step, vc, c->cstart, D, c->U, c->tidx, c->tkey, pairlog, cap, c->cnt, c->flags);
+    else if (sig == kSigMaxwell)
+      k_collide_big<kSigMaxwell><<<grid_for(K.nn), kBlock, 0, c->stream>>>(
+          K, call, step, vc, c->cstart, D, c->U, c->tidx, c->tkey, pairlog, cap, c->cnt, c->flags);
+    else
+      k_collide_big<kSigPoly><<<grid_for(K.nn), kBlock, 0, c->stream>>>(
+          K, call, step, vc, c->cstart, D, c->U, c->tidx, c->tkey, pairlog, cap, c->cnt, c->flags);
+  } else {
     k_collide_f64<<<grid_for(K.nn), kBlock, 0, c->stream>>>(K, call, step, c->v[c->cur], c->cstart,
                                                             D, c->U, pairlog, cap, c->cnt, c->flags);
+  }
   LAUNCH_CHECK(c, "collide");
   return PIC_OK;
 }

@@ -21,8 +21,8 @@
 namespace pic {
 
 constexpr int kHeavyWaves = 4;
-constexpr int kHeavyMaxN = 2048;      // particles per cell
-constexpr int kHeavyMaxPairs = 192;   // candidate pairs per outcome
+// kHeavyMaxN particles per cell, kHeavyMaxPairs candidate pairs per outcome;
+// cells that could exceed them (heavy_big_cell) are left to k_collide_f64.
 
 struct HeavyWaveLds {
   unsigned mark[kHeavyMaxN];          // (outcome tag << 9) | list entry
@@ -48,8 +48,8 @@ __global__ void __launch_bounds__(64 * kHeavyWaves) k_collide_heavy(SimConst K, 
   const int64_t NP = K.np;
   const int c = blockIdx.x;
   const int s = cstart[c], n = cstart[c + 1] - s;
-  if (n < 2 || n > kHeavyMaxN) {
-    if (n > kHeavyMaxN && threadIdx.x == 0) atomicOr(&flags[kFlagCapacity], 1);
+  if (heavy_big_cell(K, n)) return;  // run by k_collide_f64 (big_only)
+  if (n < 2) {
     for (int j = threadIdx.x; j < n; j += 64 * kHeavyWaves)
       for (int d = 0; d < 3; ++d) D[d * NP + s + j] = 0.0;
     return;

@@ -673,6 +673,17 @@ __device__ inline int pick_partner(const SimConst& K, int cell, int64_t step, in
   return q;
 }
 
+// Capacity of the workgroup-per-cell collision kernel (k_collide_heavy):
+// particles per cell and candidate pairs per outcome.  A cell that could
+// exceed either (N_pairs = floor(n (n - 1) P_max / 2 + U) < n (n - 1) P_max / 2 + 1)
+// is a "big" cell; in the collision-heavy mode it runs in k_collide_big instead.
+constexpr int kHeavyMaxN = 2048;
+constexpr int kHeavyMaxPairs = 192;
+__device__ inline bool heavy_big_cell(const SimConst& K, int n) {
+  return n > kHeavyMaxN ||
+         (double)n * (double)(n - 1) * K.pmax / 2.0 + 1.0 >= (double)(kHeavyMaxPairs + 1);
+}
+
 __global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, int64_t step,
                                                         const double* v, const int* cstart,
                                                         double* D, double* u,

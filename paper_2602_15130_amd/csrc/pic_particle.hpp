@@ -313,6 +313,48 @@ __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int c
   }
 }
 
+// The big cells of the collision-heavy mode (heavy_big_cell), one thread per
+// cell: the N_avg outcomes of Algorithm 1 in increasing order, each with
+// copy-on-write private velocities (u, mark, touched list tl; the mark tag of
+// outcome k is k + 1), its velocity changes added to D in outcome order and D
+// divided by N_avg at the end, so D equals k_collide_f64's bit for bit.
+// Other cells are left to k_collide_heavy.
+template <int SIG>
+__global__ void __launch_bounds__(kBlock) k_collide_big(SimConst K, int call, int64_t step,
+                                                        const double* v, const int* cstart,
+                                                        double* D, double* u, int* mark, int* tl,
+                                                        long long* pairlog, int64_t cap,
+                                                        unsigned long long* counters, int* flags) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= K.nn) return;
+  const int64_t NP = K.np;
+  const int s = cstart[c], n = cstart[c + 1] - s;
+  if (!heavy_big_cell(K, n)) return;
+  for (int j = 0; j < n; ++j) {
+    mark[s + j] = 0;
+    for (int d = 0; d < 3; ++d) D[d * NP + s + j] = 0.0;
+  }
+  unsigned long long acc = 0, gmx = 0;
+  bool touched = false;
+  for (int k = 0; k < K.navg; ++k) {
+    const int64_t npairs = npairs_of(K, c, step, call, k, n, flags);
+    if (npairs <= 0) continue;
+    int ntl = 0;
+    ntc_outcome<SIG, double>(K, c, step, call, k, npairs, n, v + s, u + s, mark + s, k + 1,
+                             tl + s, ntl, (int)NP, (int)NP, pairlog, cap, counters, acc, gmx);
+    for (int t = 0; t < ntl; ++t) {
+      const int j = s + tl[s + t];
+      for (int d = 0; d < 3; ++d) D[d * NP + j] += u[d * NP + j] - v[d * NP + j];
+    }
+    touched = true;
+  }
+  if (touched)
+    for (int j = 0; j < n; ++j)
+      for (int d = 0; d < 3; ++d) D[d * NP + s + j] /= (double)K.navg;
+  if (acc) atomicAdd(&counters[kCntAccepted], acc);
+  if (gmx) atomicAdd(&counters[kCntGmax], gmx);
+}
+
 // Collision call over the tile: v0 (pre-collision velocities, tile slots,
 // stride st) -> D = N_avg <dv> per slot.  u (stride stu), mark and tl are
 // scratch of the tile's slots for the outcomes a cell thread runs itself; a

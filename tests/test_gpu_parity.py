@@ -412,6 +412,55 @@ def test_heavy_collision_kernel_matches_serial_and_oracle():
     assert _rel(g.get(P.STATE_V), h.get(P.STATE_V), scale) < 1e-11
 
 
+def test_heavy_mode_big_cells_run_by_the_per_cell_kernel():
+    """With a 15x time step at Table 1 level 2 (32 outcomes) the mean outcome has ~90
+    candidate pairs: the paper's non-uniform density puts the dense cells past
+    the workgroup kernel's capacity (192 pairs per outcome), so they run in
+    k_collide_big while the rest stay in k_collide_heavy.  The combined pair
+    list equals the serial kernel's, <dv> agrees (big cells bit for bit), the
+    capacity flag stays down, and the densest cell and a sparse one agree with
+    the oracle's Algorithm 1."""
+    prob = W.paper_problem(collisions=True)
+    disc = dict(W.paper_level(2))
+    disc["dt"] = disc["dt"] * 15.0
+    disc["navg"] = 32  # keeps the pair logs at ~5M records
+    P = _pic()
+    g = P.Sim(prob, disc, 1, 0)
+    h = _with_env("PIC_HEAVY", "0", lambda: P.Sim(prob, disc, 1, 0))
+    cap = 8_000_000
+    dg, sg, lg, ng = g.collide(0, 0.0, pairlog_cap=cap)
+    dh, sh, lh, nh = h.collide(0, 0.0, pairlog_cap=cap)
+    assert ng == nh and 0 < ng <= cap
+
+    def srt(a):
+        a = np.asarray(a, dtype=np.int64).reshape(-1, 7)
+        return a[np.lexsort((a[:, 3], a[:, 2], a[:, 1], a[:, 0]))]
+
+    np.testing.assert_array_equal(srt(lg), srt(lh))
+    cs = g.get(P.STATE_CELL_START)
+    counts = np.diff(cs)
+    L = W.L_PAPER
+    # Algorithm 1: P_max = (sigma g)_max w dt / V_cell, w = N / N_p physical particles each
+    pmax = (33.2464 * W.SIGBAR * W.VBAR) * (W.N_PAPER / disc["np"]) * disc["dt"] / (L**3 / 12**3)
+    # pair bound per cell; 30 % margins keep the check off the threshold
+    bound = counts * (counts - 1.0) * pmax / 2.0 + 1.0
+    big, small = bound >= 1.3 * 193.0, bound <= 193.0 / 1.3
+    assert big.any() and small.any()
+    scale = np.abs(g.get(P.STATE_V)).max()
+    assert _rel(dg, dh, scale) < 1e-13
+    for cell in np.flatnonzero(big)[:3]:
+        s, e = cs[cell], cs[cell + 1]
+        np.testing.assert_array_equal(dg[:, s:e], dh[:, s:e])
+    v = g.get(P.STATE_V)
+    for cell in (int(np.argmax(counts)), int(np.argmin(np.where(counts > 1, counts, 10**9)))):
+        s, e = cs[cell], cs[cell + 1]
+        do, _, _, _ = O.collide_cell(prob, disc, 1, 0, 0, 0, cell, v[:, s:e])
+        assert _rel(dg[:, s:e], do, scale) < 1e-12
+    g.step(1)
+    h.step(1)
+    assert _rel(g.get(P.STATE_V), h.get(P.STATE_V), scale) < 1e-11
+
+
 # ----------------------------------------------------------------------------- checkpoint
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_checkpoint_resume_is_bitwise(precision):
