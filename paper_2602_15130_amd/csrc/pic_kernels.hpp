@@ -18,7 +18,10 @@ constexpr int kWaves = kBlock / 64;
 #endif
 constexpr int kTileB = PIC_TILE_B;               // particle slots that start cells in one tile
 constexpr int kTileThreads = PIC_TILE_THREADS;   // threads of the tile kernels
-constexpr int kLdsSlots = kTileB + kTileB / 2;   // LDS-resident slots per tile
+#ifndef PIC_LDS_SLOTS
+#define PIC_LDS_SLOTS (PIC_TILE_B + PIC_TILE_B / 2)
+#endif
+constexpr int kLdsSlots = PIC_LDS_SLOTS;          // LDS-resident slots per tile
 // Minimum resident waves per SIMD requested for the fused particle kernels
 // (their register budget is 512 / waves per lane).
 #ifndef PIC_MIXED_WAVES
