@@ -59,7 +59,8 @@ def stage_bytes(stage, prob, disc, precision, cg_iters):
 # Every source that goes into the library: a change to any of them voids the
 # committed counter record.
 DEVICE_SOURCES = ("pic.hip", "pic_device.hpp", "pic_kernels.hpp", "pic_particle.hpp", "pic_mixed.hpp",
-                  "pic_cg_brick.hpp", "pic_lowmode.hpp", "pic_angles.hpp", "pic_collide_heavy.hpp")
+                  "pic_cg_brick.hpp", "pic_lowmode.hpp", "pic_angles.hpp", "pic_collide_heavy.hpp",
+                  "pic_order.hpp")
 
 
 def measured_traffic(stage, workload):

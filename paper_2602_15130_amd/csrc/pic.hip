@@ -19,6 +19,7 @@
 #include "pic_lowmode.hpp"
 #include "pic_angles.hpp"
 #include "pic_collide_heavy.hpp"
+#include "pic_order.hpp"
 
 using namespace pic;
 
@@ -278,6 +279,7 @@ struct pic_ctx {
   int low_k = 0;                // Fourier modes per axis solved exactly before the CG
   size_t low_lds[3] = {0, 0, 0};  // dynamic LDS of the three pre-solve passes
   bool count_zero = false;        // cell counts known to be zero (left so by the scan)
+  bool mom_ready = false;         // cell moments of the current positions deposited by the sort
   bool heavy = false;           // collision calls by k_collide_heavy (many pairs per outcome)
   int heavy_bits = 0;           // its fixed-point scale
   double* angbuf = nullptr;     // scattering-angle records and their sort scratch
@@ -446,14 +448,23 @@ int sort_particles(pic_ctx* c) {
               c->stream>>>(c->key, c->slot, c->cstart, c->tidx, c->tkey, np);
   int s = c->cur, d = 1 - c->cur;
   const int ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
-  if (c->precision == PIC_FP64)
-    k_order_tiles<double><<<ntiles, kTileThreads, 0, c->stream>>>(
-        c->tile_c0, c->tile_s0, c->tidx, c->tkey, c->cstart, c->x[s], c->v[s], c->sh[s], c->id[s],
-        c->x[d], c->v[d], c->sh[d], c->id[d], c->key, np, c->flags);
-  else
-    k_order_tiles<float><<<ntiles, kTileThreads, 0, c->stream>>>(
-        c->tile_c0, c->tile_s0, c->tidx, c->tkey, c->cstart, c->off[s], c->vf[s], c->asf[s],
-        c->id[s], c->off[d], c->vf[d], c->asf[d], c->id[d], c->key, np, c->flags);
+  // the fused step deposits each tile as it is moved (cell moments for the
+  // field solve that follows)
+  const bool dep = c->fused;
+  if (c->precision == PIC_FP64) {
+    auto kfn = dep ? k_order_tiles<double, true> : k_order_tiles<double, false>;
+    kfn<<<ntiles, kTileThreads, 0, c->stream>>>(c->K, c->tile_c0, c->tile_s0, c->tidx, c->tkey,
+                                                 c->cstart, c->x[s], c->v[s], c->sh[s], c->id[s],
+                                                 c->x[d], c->v[d], c->sh[d], c->id[d], c->key,
+                                                 (double*)c->mom, np, c->flags);
+  } else {
+    auto kfn = dep ? k_order_tiles<float, true> : k_order_tiles<float, false>;
+    kfn<<<ntiles, kTileThreads, 0, c->stream>>>(c->K, c->tile_c0, c->tile_s0, c->tidx, c->tkey,
+                                                 c->cstart, c->off[s], c->vf[s], c->asf[s],
+                                                 c->id[s], c->off[d], c->vf[d], c->asf[d],
+                                                 c->id[d], c->key, (float*)c->mom, np, c->flags);
+  }
+  c->mom_ready = dep;
   LAUNCH_CHECK(c, "sort");
   c->cur = d;
   return PIC_OK;
@@ -466,20 +477,22 @@ int field_solve(pic_ctx* c, double t) {
   {
     StageTimer tm(c, PIC_STAGE_DEPOSIT);
     const int ntiles = (int)((K.np + kTileB - 1) / kTileB);
+    const bool have_mom = c->mom_ready;  // deposited by the sort's move
+    c->mom_ready = false;
     if (c->precision == PIC_FP64) {
-      if (c->fused)
+      if (!have_mom && c->fused)
         k_deposit_tiles_f64<<<ntiles, kTileThreads, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
                                                               c->tile_c0, (double*)c->mom);
-      else
+      else if (!have_mom)
         k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
                                                              (double*)c->mom);
       k_node_rhs<double><<<nbn, kBlock, 0, c->stream>>>(K, (const double*)c->mom, t, c->rho, c->b,
                                                         c->partA);
     } else {
-      if (c->fused)
+      if (!have_mom && c->fused)
         k_deposit_tiles_mixed<<<ntiles, kTileThreads, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
                                                                 c->tile_c0, (float*)c->mom);
-      else
+      else if (!have_mom)
         k_deposit_moments_mixed<<<nbn, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
                                                                (float*)c->mom);
       k_node_rhs_mixed<<<nbn, kBlock, 0, c->stream>>>(K, (const float*)c->mom, t, c->rho, c->b,
@@ -1193,6 +1206,7 @@ int pic_checkpoint_load(pic_ctx* c, const void* host_src, int64_t bytes) {
   }
   c->step = h.step;
   c->count_zero = false;
+  c->mom_ready = false;
   return PIC_OK;
 }
 

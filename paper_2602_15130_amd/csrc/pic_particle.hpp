@@ -443,86 +443,6 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
   __syncthreads();
 }
 
-// Stable in-cell order by cell-aligned tiles: a tile's slots (the sort's
-// scatter slots of its cells) load their source indices into LDS; each
-// slot's rank among the source indices of its own cell, which is its place in
-// the stable order, is counted in LDS, and the particle's state moves from its
-// source to (cell start) + rank.  Same destinations as order_dst; tiles larger
-// than the LDS slots use order_dst itself.  Every global load a slot needs
-// (source index, cell, cell bounds, the state itself) is issued before the
-// block waits for the LDS copy, so a tile costs two dependent load rounds.
-template <class T>
-__global__ void __launch_bounds__(kTileThreads) k_order_tiles(const int* tile_c0, const int* tile_s0,
-                                                        const int* tidx, const int* tkey,
-                                                        const int* cstart, const T* xs,
-                                                        const T* vs, const T* as, const int* ids,
-                                                        T* xd, T* vd, T* ad, int* idd, int* keyd,
-                                                        int n, int* flags) {
-  constexpr int kPer = (kLdsSlots + kTileThreads - 1) / kTileThreads;
-  __shared__ int lidx[kLdsSlots];
-  const int s0 = tile_s0[blockIdx.x], ns = tile_s0[blockIdx.x + 1] - s0;
-  if (ns <= 0) return;
-  if (ns > kLdsSlots) {
-    for (int j = threadIdx.x; j < ns; j += kTileThreads) {
-      const int slot = s0 + j, my = tidx[slot];
-      const int dst = order_dst(tidx, tkey, cstart, slot, flags);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xd[(int64_t)d * n + dst] = xs[(int64_t)d * n + my];
-        vd[(int64_t)d * n + dst] = vs[(int64_t)d * n + my];
-        ad[(int64_t)d * n + dst] = as[(int64_t)d * n + my];
-      }
-      idd[dst] = ids[my];
-      keyd[dst] = tkey[slot];
-    }
-    return;
-  }
-  int my[kPer], cc[kPer], cs[kPer], ce[kPer], idv[kPer];
-  T sv[kPer][9];
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int j = threadIdx.x + q * kTileThreads;
-    if (j < ns) {
-      my[q] = tidx[s0 + j];
-      cc[q] = tkey[s0 + j];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int j = threadIdx.x + q * kTileThreads;
-    if (j < ns) {
-      lidx[j] = my[q];
-      cs[q] = cstart[cc[q]] - s0;
-      ce[q] = cstart[cc[q] + 1] - s0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        sv[q][d] = xs[(int64_t)d * n + my[q]];
-        sv[q][3 + d] = vs[(int64_t)d * n + my[q]];
-        sv[q][6 + d] = as[(int64_t)d * n + my[q]];
-      }
-      idv[q] = ids[my[q]];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int j = threadIdx.x + q * kTileThreads;
-    if (j < ns) {
-      int r = 0;
-      for (int k = cs[q]; k < ce[q]; ++k) r += lidx[k] < my[q];
-      const int dst = s0 + cs[q] + r;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xd[(int64_t)d * n + dst] = sv[q][d];
-        vd[(int64_t)d * n + dst] = sv[q][3 + d];
-        ad[(int64_t)d * n + dst] = sv[q][6 + d];
-      }
-      idd[dst] = idv[q];
-      keyd[dst] = cc[q];
-    }
-  }
-}
-
 // Tile bounds of block b: first cell, cell count, first particle, particle count.
 __device__ inline void tile_range(const SimConst& K, const int* tile_c0, const int* cstart, int b,
                                   int* sh_i) {
