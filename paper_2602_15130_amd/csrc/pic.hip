@@ -651,23 +651,40 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
     const double tA = (double)a.na * K.dt, tB = ((double)a.nb + 1.0) * K.dt;
     MixConst M = mix_const(K, tA, tB);
     const int s = c->cur;
-    if (sig == kSigHS)
-      k_particles_mixed<kSigHS><<<tiles, kTileThreads, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+    // collision-angle recording is compiled only into the instances launched
+    // while an angle log is attached
+    const bool ang = K.anglog != nullptr;
+    const dim3 grid(tiles), blk(kTileThreads);
+    float *o = c->off[s], *vv = c->vf[s];
+    const float *sh = c->asf[s], *e = c->E32;
+    if (sig == kSigHS && ang)
+      k_particles_mixed<kSigHS, true><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
+    else if (sig == kSigHS)
+      k_particles_mixed<kSigHS, false><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
+    else if (sig == kSigMaxwell && ang)
+      k_particles_mixed<kSigMaxwell, true><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
     else if (sig == kSigMaxwell)
-      k_particles_mixed<kSigMaxwell><<<tiles, kTileThreads, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+      k_particles_mixed<kSigMaxwell, false><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
+    else if (ang)
+      k_particles_mixed<kSigPoly, true><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
     else
-      k_particles_mixed<kSigPoly><<<tiles, kTileThreads, 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s], c->E32);
+      k_particles_mixed<kSigPoly, false><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
     LAUNCH_CHECK(c, "particles (mixed)");
     return PIC_OK;
   }
+  const bool ang = K.anglog != nullptr;
+  void (*fn)(SimConst, PartArgs) = nullptr;
   if (K.family == 1) {
-    if (sig == kSigHS) k_particles_f64<1, kSigHS><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
-    else if (sig == kSigMaxwell) k_particles_f64<1, kSigMaxwell><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
-    else k_particles_f64<1, kSigPoly><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
+    if (sig == kSigHS) fn = ang ? k_particles_f64<1, kSigHS, true> : k_particles_f64<1, kSigHS, false>;
+    else if (sig == kSigMaxwell)
+      fn = ang ? k_particles_f64<1, kSigMaxwell, true> : k_particles_f64<1, kSigMaxwell, false>;
+    else fn = ang ? k_particles_f64<1, kSigPoly, true> : k_particles_f64<1, kSigPoly, false>;
   } else {
-    if (sig == kSigMaxwell) k_particles_f64<0, kSigMaxwell><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
-    else k_particles_f64<0, kSigPoly><<<tiles, kTileThreads, 0, c->stream>>>(K, a);
+    if (sig == kSigMaxwell)
+      fn = ang ? k_particles_f64<0, kSigMaxwell, true> : k_particles_f64<0, kSigMaxwell, false>;
+    else fn = ang ? k_particles_f64<0, kSigPoly, true> : k_particles_f64<0, kSigPoly, false>;
   }
+  fn<<<tiles, kTileThreads, 0, c->stream>>>(K, a);
   LAUNCH_CHECK(c, "particles");
   return PIC_OK;
 }
