@@ -651,9 +651,9 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
     const double tA = (double)a.na * K.dt, tB = ((double)a.nb + 1.0) * K.dt;
     MixConst M = mix_const(K, tA, tB);
     const int s = c->cur;
-    // collision-angle recording is compiled only into the instances launched
-    // while an angle log is attached
-    const bool ang = K.anglog != nullptr;
+    // the collision-angle and pair-log recording is compiled only into the
+    // instances launched while a log is attached
+    const bool ang = K.anglog != nullptr || a.pairlog != nullptr;
     const dim3 grid(tiles), blk(kTileThreads);
     float *o = c->off[s], *vv = c->vf[s];
     const float *sh = c->asf[s], *e = c->E32;
@@ -672,7 +672,7 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
     LAUNCH_CHECK(c, "particles (mixed)");
     return PIC_OK;
   }
-  const bool ang = K.anglog != nullptr;
+  const bool ang = K.anglog != nullptr || a.pairlog != nullptr;
   void (*fn)(SimConst, PartArgs) = nullptr;
   if (K.family == 1) {
     if (sig == kSigHS) fn = ang ? k_particles_f64<1, kSigHS, true> : k_particles_f64<1, kSigHS, false>;
