@@ -203,7 +203,8 @@ __device__ inline void source_integral_f(const SimConst& K, const MixConst& M, c
     }
     float s = M.vbar;
     float kk = hs_kernel_f(sp / s);
-    for (int i = 0; i < 3; ++i) out[i] = -M.sigma_ref * s * s * kk * u[i] / sp;
+    const float f = -M.sigma_ref * s * s * kk / sp;  // one division for the three components
+    for (int i = 0; i < 3; ++i) out[i] = f * u[i];
   } else {
     // polynomial cross section with Gaussian moments m2 = s^2, m4 = 3 s^4
     float m2 = M.vbar * M.vbar, m4 = 3.0f * m2 * m2;
@@ -255,8 +256,7 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     float arg = 2.0f * (((float)cc[d] + o[d]) * M.inv_n[d] - shift[d]);
-    s[d] = sinpif(arg);
-    c[d] = cospif(arg);
+    sincospif(arg, &s[d], &c[d]);
   }
   em[0] = -amp[0] * c[0] * s[1] * s[2];
   em[1] = -amp[1] * s[0] * c[1] * s[2];
@@ -299,6 +299,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
   int* mark = a.gmark + s0;
   int* tl = a.gtl + s0;
   const float navg_f = (float)K.navg;
+  const float inv_navg = 1.0f / navg_f;  // exact for a power-of-two N_avg
 
   for (int j = tid; j < ns; j += kTileThreads) {
     const int p = s0 + j;
@@ -334,7 +335,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       float I[3] = {0.0f, 0.0f, 0.0f};
       float coef = M.src_w * (float)(n - 1);
       if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
-      for (int d = 0; d < 3; ++d) coll[d] = D[d * st + j] / navg_f - ((n >= 2) ? coef * I[d] : 0.0f);
+      for (int d = 0; d < 3; ++d) coll[d] = D[d * st + j] * inv_navg - ((n >= 2) ? coef * I[d] : 0.0f);
     }
     for (int d = 0; d < 3; ++d) {
       float acc = M.dtqm * (ep[d] - em[d]);
@@ -352,7 +353,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       float coef = M.src_w * (float)(n - 1);
       if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
       for (int d = 0; d < 3; ++d) {
-        a.Dout[(int64_t)d * NP + s0 + j] = (double)(D[d * st + j] / navg_f);
+        a.Dout[(int64_t)d * NP + s0 + j] = (double)(D[d * st + j] * inv_navg);
         a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? (double)(coef * I[d]) : 0.0;
       }
     }
