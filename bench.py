@@ -43,10 +43,12 @@ def stage_bytes(stage, prob, disc, precision, cg_iters):
     if stage == "drift":         # x, v, a in; x, key, slot out
         return (sx + sv + sa + sx + 4 + 4) * np_ + 4 * nn
     if stage == "sort":          # scatter slots (key, slot -> index, key); the
-        # ordered move reads the indices and gathers/scatters x, v, a, id; key out
-        return (16 + 8 + 2 * (px + sv + sa + 4) + 4) * np_ + 12 * nn
-    if stage == "deposit":       # positions in; node charge and right-hand side
-        return sx * np_ + 4 * nn + 2 * 64 * nn + 32 * nn
+        # ordered move reads the indices and gathers/scatters x, v, a, id; key
+        # out; in the fused step it also writes the cell moments (64 B a cell)
+        return (16 + 8 + 2 * (px + sv + sa + 4) + 4) * np_ + 12 * nn + 64 * nn
+    if stage == "deposit":       # cell moments in; node charge and right-hand
+        # side out, the right-hand side's mean removed
+        return 64 * nn + 16 * nn + 16 * nn
     if stage == "cg":            # per iteration: stencil on p and r, update x, r
         return max(cg_iters, 1) * 80 * nn
     if stage == "gradient":
