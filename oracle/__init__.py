@@ -28,7 +28,7 @@ class OrcProblem(C.Structure):
         ("sigma_ref", C.c_double), ("g_ref", C.c_double), ("omega", C.c_double),
         ("g_max", C.c_double), ("chi_model", C.c_int), ("field_to_particles", C.c_int),
         ("particles_to_field", C.c_int), ("collisions", C.c_int), ("isolate", C.c_int),
-        ("coding_error", C.c_int),
+        ("coding_error", C.c_int), ("chi_alpha", C.c_double),
     ]
 
 
@@ -78,7 +78,11 @@ def lib():
         L.orc_angle_record_start.argtypes = [P(d), C.c_int64]
         L.orc_angle_record_stop.argtypes = []
         L.orc_angle_record_stop.restype = C.c_int64
-        L.orc_angle_errors.argtypes = [P(d), C.c_int64, P(d)]
+        L.orc_angle_errors.argtypes = [P(d), C.c_int64, C.c_int, d, P(d)]
+        L.orc_cos_chi.argtypes = [C.c_int, d, d]
+        L.orc_cos_chi.restype = d
+        L.orc_chi_cdf.argtypes = [C.c_int, d, d]
+        L.orc_chi_cdf.restype = d
         L.orc_laplacian.argtypes = [P(OrcDisc), P(OrcProblem), P(d), P(d)]
         L.orc_gradient.argtypes = [P(OrcProblem), P(OrcDisc), P(d), P(d)]
         L.orc_gather.argtypes = [P(OrcProblem), P(OrcDisc), P(d), i64, P(d), P(d)]
@@ -121,7 +125,8 @@ def make_problem(p: dict) -> OrcProblem:
     sn = list(p["sigma_n"]) + [0.0] * (3 - len(p["sigma_n"]))
     s.n_sigma = len(p["sigma_n"])
     s.sigma_n = (C.c_double * 3)(*sn)
-    s.chi_model = 0
+    s.chi_model = int(p.get("chi_model", 0))
+    s.chi_alpha = float(p.get("chi_alpha", 1.0))
     for k in ("field_to_particles", "particles_to_field", "collisions", "isolate"):
         setattr(s, k, int(p[k]))
     s.coding_error = int(p.get("coding_error", 0))
@@ -415,10 +420,21 @@ class AngleRecorder:
         return False
 
 
-def angle_errors(records):
-    """Empirical-CDF errors of (chi, eps) records against the isotropic analytic
-    CDFs: (eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps)."""
+def angle_errors(records, chi_model=0, chi_alpha=1.0):
+    """Empirical-CDF errors of (chi, eps) records against the analytic CDFs of
+    the polar-angle model (isotropic by default) and of the uniform azimuth:
+    (eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps)."""
     rec = np.ascontiguousarray(records, dtype=np.float64).reshape(-1)
     out = np.zeros(4)
-    lib().orc_angle_errors(_dp(rec), len(rec) // 2, _dp(out))
+    lib().orc_angle_errors(_dp(rec), len(rec) // 2, int(chi_model), float(chi_alpha), _dp(out))
     return out
+
+
+def cos_chi(chi_model, chi_alpha, xi):
+    """cos F_pchi^{-1}(xi) of the polar-angle model (eq. chi_iso, eq. fpiv_ms, eq. vss)."""
+    return lib().orc_cos_chi(int(chi_model), float(chi_alpha), float(xi))
+
+
+def chi_cdf(chi_model, chi_alpha, chi):
+    """F_pchi(chi) of the polar-angle model."""
+    return lib().orc_chi_cdf(int(chi_model), float(chi_alpha), float(chi))

@@ -794,11 +794,45 @@ static int cmp_double(const void* a, const void* b) {
   return (x > y) - (x < y);
 }
 
+/* Polar angle from the uniform xi, returned as cos chi.
+ *   isotropic (eq. chi_iso): cos chi = 1 - 2 xi.
+ *   manufactured anisotropy (Sec. 5.2, eq. fpiv_ms): with u = sin^2(chi/2)
+ *     the CDF is F(u) = (13 u + 96 u^2 - 160 u^3 + 80 u^4) / 29, inverted in
+ *     closed form through a(xi) and b(xi); cos chi = 1 - 2 u.
+ *   variable soft sphere (eq. vss): F(chi) = 1 - cos^(2 alpha)(chi/2), whose
+ *     exact inverse is cos(chi/2) = (1 - xi)^(1/(2 alpha)) (the printed
+ *     xi^(1/(2 alpha)) is the same law with xi -> 1 - xi); cos chi =
+ *     2 cos^2(chi/2) - 1. */
+double orc_cos_chi(int chi_model, double chi_alpha, double xi) {
+  if (chi_model == ORC_CHI_MMS) {
+    double inner = 298924665.0 + 55680.0 * xi * (376377.0 + 2320.0 * xi * (-429.0 + 290.0 * xi));
+    double a = cbrt(81909.0 - 83520.0 * xi + sqrt(inner)) / (40.0 * pow(3.0, 2.0 / 3.0));
+    double b = 0.2 + a + (161.0 - 290.0 * xi) / (600.0 * a);
+    double sb = sqrt(b);
+    double u = 0.5 * (1.0 - sb + sqrt(0.6 - b + 29.0 / (40.0 * sb)));
+    return 1.0 - 2.0 * u;
+  }
+  if (chi_model == ORC_CHI_VSS) return 2.0 * pow(1.0 - xi, 1.0 / chi_alpha) - 1.0;
+  return 1.0 - 2.0 * xi;
+}
+
+/* F_pchi(chi) of the polar-angle model: (1 - cos chi)/2; sin^2(chi/2) -
+ * (3 + 5 cos 2 chi) sin^2(chi) / 58 (Sec. 5.2); 1 - cos^(2 alpha)(chi/2). */
+double orc_chi_cdf(int chi_model, double chi_alpha, double chi) {
+  if (chi_model == ORC_CHI_MMS) {
+    double s2 = sin(0.5 * chi), sc = sin(chi);
+    return s2 * s2 - (3.0 + 5.0 * cos(2.0 * chi)) * sc * sc / 58.0;
+  }
+  if (chi_model == ORC_CHI_VSS) return 1.0 - pow(cos(0.5 * chi), 2.0 * chi_alpha);
+  return 0.5 * (1.0 - cos(chi));
+}
+
 /* e_r = F(alpha_r) - F^M(alpha_r) with the empirical CDF F(alpha) =
- * (1/N) sum_r theta(alpha - alpha_r), theta(0) = 1, and the isotropic
- * analytic CDFs F^M_chi = (1 - cos chi)/2, F^M_eps = eps / (2 pi):
+ * (1/N) sum_r theta(alpha - alpha_r), theta(0) = 1, and the analytic CDFs
+ * F^M_chi of the polar-angle model and F^M_eps = eps / (2 pi):
  * out = {eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps}. */
-void orc_angle_errors(const double* rec, int64_t n, double out[4]) {
+void orc_angle_errors(const double* rec, int64_t n, int chi_model, double chi_alpha,
+                      double out[4]) {
   double* a = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
   for (int which = 0; which < 2; ++which) {
     for (int64_t r = 0; r < n; ++r) a[r] = rec[2 * r + which];
@@ -807,7 +841,7 @@ void orc_angle_errors(const double* rec, int64_t n, double out[4]) {
     for (int64_t i = 0; i < n; ++i) {
       int64_t j = i;  /* theta(0) = 1: equal values share the largest rank */
       while (j + 1 < n && a[j + 1] == a[i]) ++j;
-      double fm = which == 0 ? 0.5 * (1.0 - cos(a[i])) : a[i] / TWO_PI_D;
+      double fm = which == 0 ? orc_chi_cdf(chi_model, chi_alpha, a[i]) : a[i] / TWO_PI_D;
       double e = (double)(j + 1) / (double)n - fm;
       s2 += e * e;
       if (fabs(e) > mx) mx = fabs(e);
@@ -864,7 +898,7 @@ int orc_collide_cell(const orc_problem* P, const orc_disc* D, uint64_t seed, uin
       if (accepted) {
         ++*n_accepted;
         double eps = TWO_PI_D * orc_u01(wa[3]);
-        double cchi = 1.0 - 2.0 * orc_u01(wb[0]); /* eq. chi_iso */
+        double cchi = orc_cos_chi(P->chi_model, P->chi_alpha, orc_u01(wb[0]));
         double schi = sqrt(fmax(0.0, (1.0 - cchi) * (1.0 + cchi)));
         double nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi}; /* eq. n */
         if (P->coding_error == 2) {

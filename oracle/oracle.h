@@ -40,7 +40,10 @@ extern "C" {
 
 enum { ORC_FAM_PAPER = 0, ORC_FAM_CFG = 1 };
 enum { ORC_SIGMA_POLY = 0, ORC_SIGMA_VHS = 1 };
-enum { ORC_CHI_ISO = 0 };
+/* Polar scattering angle: isotropic (eq. chi_iso), the manufactured
+ * anisotropy fitted to VSS alpha = 2 (eq. pchi_ms with C_0 = 1/2, C_1 = 12/29,
+ * inverse eq. fpiv_ms), variable soft sphere with exponent alpha (eq. vss). */
+enum { ORC_CHI_ISO = 0, ORC_CHI_MMS = 1, ORC_CHI_VSS = 2 };
 
 typedef struct {
   int family;              /* ORC_FAM_PAPER (Sec. 5.2 functions) or ORC_FAM_CFG */
@@ -56,12 +59,13 @@ typedef struct {
   double sigma_n[3];       /* sigma(g) = sum_n sigma_n g^(2n-1) */
   double sigma_ref, g_ref, omega; /* VHS: sigma = sigma_ref (g/g_ref)^(1-2 omega) */
   double g_max;            /* (sigma g)_max is taken over [0, g_max] */
-  int chi_model;           /* ORC_CHI_ISO (eq. chi_iso) */
+  int chi_model;           /* ORC_CHI_ISO, ORC_CHI_MMS or ORC_CHI_VSS */
   int field_to_particles;  /* 0 => q/m = 0 in the push */
   int particles_to_field;  /* 0 => q = 0 in the Poisson source */
   int collisions;          /* 0 => no DSMC */
   int isolate;             /* 1 => exact-difference substitution of Sec. 5.4.1 */
   int coding_error;        /* 0 none; 1 = v_cm sign error; 2 = swap w.p. 1/2 */
+  double chi_alpha;        /* VSS exponent alpha in [1, 2] (ORC_CHI_VSS) */
 } orc_problem;
 
 typedef struct {
@@ -129,7 +133,12 @@ void orc_angle_record_start(double* buf, int64_t cap);
 int64_t orc_angle_record_stop(void);
 /* Empirical-CDF errors of n records against the isotropic analytic CDFs:
  * {eps_2 chi, eps_inf chi, eps_2 eps, eps_inf eps}. */
-void orc_angle_errors(const double* rec, int64_t n, double out[4]);
+/* cos chi = cos F_pchi^{-1}(xi) of the polar-angle model (eq. chi_iso,
+ * eq. fpiv_ms, eq. vss) and the model's CDF F_pchi(chi). */
+double orc_cos_chi(int chi_model, double chi_alpha, double xi);
+double orc_chi_cdf(int chi_model, double chi_alpha, double chi);
+void orc_angle_errors(const double* rec, int64_t n, int chi_model, double chi_alpha,
+                      double out[4]);
 
 /* ---- whole simulation ---- */
 orc_sim* orc_create(const orc_problem* P, const orc_disc* D, uint64_t seed, uint32_t rep);

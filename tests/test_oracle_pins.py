@@ -811,3 +811,95 @@ def test_fixed_navg_collisional_error_does_not_converge():
     orders = np.array(W.observed_orders(norms)[0])
     assert np.all(orders[3:6] < 1.0), orders      # velocities
     assert 1.8 < orders[6] < 2.2, orders          # phi
+
+
+# ----------------------------------------------------------------------------- anisotropic scattering
+def _mms_pchi(chi):
+    # Sec. 5.2: p_chi of eq. pchi_ms with C_0 = 1/2, C_1 = 12/29
+    c = np.cos(chi)
+    return (29.0 / 2.0 + 12.0 * c - 20.0 * c ** 3) * np.sin(chi) / 29.0
+
+
+def test_manufactured_anisotropy_inverse_cdf_closed_form():
+    """eq. fpiv_ms: the closed-form u(xi) = sin^2(chi/2) inverts the printed
+    quartic F(u) = (13 u + 96 u^2 - 160 u^3 + 80 u^4)/29, and chi = 2 asin
+    sqrt(u) inverts the printed trigonometric F_pchi(chi) as well (two forms
+    of the CDF, neither used by the sampler)."""
+    for xi in np.concatenate([np.linspace(1e-6, 1 - 1e-6, 401), [0.5, 0.25, 0.75]]):
+        c = O.cos_chi(1, 0.0, xi)
+        u = (1.0 - c) / 2.0
+        fu = (13 * u + 96 * u ** 2 - 160 * u ** 3 + 80 * u ** 4) / 29.0
+        assert abs(fu - xi) < 1e-12
+        chi = math.acos(max(-1.0, min(1.0, c)))
+        s2, sc = math.sin(chi / 2), math.sin(chi)
+        assert abs(s2 * s2 - (3 + 5 * math.cos(2 * chi)) * sc * sc / 58.0 - xi) < 1e-12
+        assert abs(O.chi_cdf(1, 0.0, chi) - xi) < 1e-12
+
+
+def test_manufactured_anisotropy_meets_both_constraints_and_the_fit():
+    """eq. pchi_ms with C_0 = 1/2, C_1 = 12/29: p_chi integrates to one
+    (eq. constraint_2), has zero mean cosine (eq. constraint_1, so the
+    manufactured collision source is unchanged), is the derivative of the
+    model CDF, and (C_0, C_1) minimise the L2 distance to the VSS alpha = 2
+    density of eq. pbar (eq. anisotropy_opt, a linear least-squares problem in
+    the two coefficients)."""
+    from scipy.integrate import quad
+    assert quad(_mms_pchi, 0, math.pi)[0] == pytest.approx(1.0, abs=1e-12)
+    assert abs(quad(lambda x: _mms_pchi(x) * math.cos(x), 0, math.pi)[0]) < 1e-12
+    for chi in (0.3, 1.1, 2.0, 2.9):
+        h = 1e-5
+        d = (O.chi_cdf(1, 0.0, chi + h) - O.chi_cdf(1, 0.0, chi - h)) / (2 * h)
+        assert d == pytest.approx(_mms_pchi(chi), rel=1e-8)
+    # p = C0 (1 - 3 cos^2) sin + C1 (cos - 5/3 cos^3) sin + 3/2 cos^2 sin
+    b0 = lambda x: (1 - 3 * math.cos(x) ** 2) * math.sin(x)
+    b1 = lambda x: (math.cos(x) - 5.0 / 3.0 * math.cos(x) ** 3) * math.sin(x)
+    r = lambda x: 2 * math.cos(x / 2) ** 3 * math.sin(x / 2) - 1.5 * math.cos(x) ** 2 * math.sin(x)
+    G = np.array([[quad(lambda x: bi(x) * bj(x), 0, math.pi)[0] for bj in (b0, b1)] for bi in (b0, b1)])
+    h = np.array([quad(lambda x: bi(x) * r(x), 0, math.pi)[0] for bi in (b0, b1)])
+    c0, c1 = np.linalg.solve(G, h)
+    assert c0 == pytest.approx(0.5, abs=1e-10) and c1 == pytest.approx(12.0 / 29.0, abs=1e-10)
+
+
+def test_manufactured_anisotropy_sampler_follows_its_density():
+    """Midpoint quadrature of xi -> cos chi(xi) gives the moments of p_chi:
+    E[cos chi] = 0 (eq. constraint_1) and E[cos^2 chi] = int p cos^2."""
+    from scipy.integrate import quad
+    c = np.array([O.cos_chi(1, 0.0, x) for x in (np.arange(4000) + 0.5) / 4000])
+    assert abs(c.mean()) < 1e-6
+    m2 = quad(lambda x: _mms_pchi(x) * math.cos(x) ** 2, 0, math.pi)[0]
+    assert c.dot(c) / len(c) == pytest.approx(m2, abs=1e-6)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.5, 2.0])
+def test_vss_inverse_cdf(alpha):
+    """eq. vss: chi = F^{-1}(xi) with F(chi) = 1 - cos^(2 alpha)(chi/2) (the
+    exact inverse of the printed CDF); alpha = 1 is the isotropic law of
+    eq. chi_iso."""
+    for xi in np.linspace(1e-6, 1 - 1e-6, 201):
+        c = O.cos_chi(2, alpha, xi)
+        chi = math.acos(max(-1.0, min(1.0, c)))
+        assert abs((1.0 - math.cos(chi / 2) ** (2 * alpha)) - xi) < 1e-11
+        assert abs(O.chi_cdf(2, alpha, chi) - xi) < 1e-11
+        if alpha == 1.0:
+            assert abs(c - (1.0 - 2.0 * xi)) < 1e-15
+            assert abs(O.chi_cdf(2, 1.0, chi) - O.chi_cdf(0, 0.0, chi)) < 1e-15
+
+
+def test_anisotropic_collisions_follow_their_own_law():
+    """With the manufactured anisotropy the recovered polar angles follow
+    F_pchi of eq. pchi_ms (sqrt(N) eps_inf O(1)) and not the isotropic law;
+    the azimuth stays uniform."""
+    prob = W.cfg_problem(two_way=False, collisionality=30.0)
+    prob["chi_model"] = 1
+    disc = W.cfg_disc(8, 16384, 1e-3, 1, 8)
+    o = O.Sim(prob, disc, 1, 0)
+    assert o.init() == 0
+    with O.AngleRecorder() as rec:
+        o.step(3)
+    r = rec.records
+    n = len(r)
+    assert n > 20000
+    own = O.angle_errors(r, 1, 0.0) * math.sqrt(n)
+    iso = O.angle_errors(r, 0, 0.0) * math.sqrt(n)
+    assert own[1] < 2.0 and own[3] < 2.0, own
+    assert iso[1] > 4.0, iso
