@@ -72,6 +72,21 @@ enum pic_sigma {
   PIC_SIGMA_VHS = 1     /* sigma_ref (g / g_ref)^(1 - 2 omega); omega in {0.5, 1} */
 };
 
+/* Polar scattering angle chi = F_pchi^{-1}(xi) (eq. chi).  PIC_CHI_MMS is the
+ * manufactured anisotropy of Sec. 5.2 (eq. pchi_ms with C_0 = 1/2,
+ * C_1 = 12/29, closed-form inverse eq. fpiv_ms); it satisfies eq. constraint_1,
+ * so the manufactured collision source is the isotropic one.  PIC_CHI_VSS is
+ * the variable soft sphere of eq. vss with exponent chi_alpha (inverse
+ * cos(chi/2) = (1 - xi)^(1/(2 alpha)), the exact inverse of its CDF); for
+ * alpha != 1 it violates eq. constraint_1, so the manufactured source is not
+ * the collision operator's expectation there (a realistic model for the angle
+ * metric, not a code-verification case). */
+enum pic_chi {
+  PIC_CHI_ISO = 0,      /* eq. chi_iso: cos chi = 1 - 2 xi */
+  PIC_CHI_MMS = 1,      /* eq. pchi_ms / eq. fpiv_ms */
+  PIC_CHI_VSS = 2       /* eq. vss */
+};
+
 /* The problem, in the paper's notation (Sec. 2, Sec. 3, Sec. 5.2). */
 typedef struct {
   int family;               /* enum pic_family */
@@ -87,12 +102,13 @@ typedef struct {
   double sigma_n[3];
   double sigma_ref, g_ref, omega; /* PIC_SIGMA_VHS */
   double g_max;             /* (sigma g)_max is the maximum over [0, g_max] */
-  int chi_model;            /* 0: isotropic scattering, eq. chi_iso */
+  int chi_model;            /* enum pic_chi: polar scattering-angle model */
   int field_to_particles;   /* 0 => q/m = 0 in the push (Sec. 5.4) */
   int particles_to_field;   /* 0 => q = 0 in the Poisson source (Sec. 5.4) */
   int collisions;           /* 0 => no DSMC */
   int isolate;              /* 1 => exact-difference substitution of the
                                manufactured time derivatives (Sec. 5.4.1) */
+  double chi_alpha;         /* VSS exponent alpha in [1, 2] (PIC_CHI_VSS) */
 } pic_problem;
 
 /* The discretization (Table 1 columns). */

@@ -119,7 +119,9 @@ int validate(const pic_problem* p, const pic_discretization* d, int precision, s
     return bad("nphys, eps0, T and vbar must be positive");
   if (p->field_to_particles && p->m == 0.0) return bad("m must be nonzero");
   if (p->family == PIC_MMS_CFG && !(std::fabs(p->rho_amp) < 1.0)) return bad("need |rho_amp| < 1");
-  if (p->chi_model != 0) return bad("only isotropic scattering (chi_model 0)");
+  if (p->chi_model < PIC_CHI_ISO || p->chi_model > PIC_CHI_VSS) return bad("chi_model must be 0, 1 or 2");
+  if (p->chi_model == PIC_CHI_VSS && !(p->chi_alpha >= 1.0 && p->chi_alpha <= 2.0))
+    return bad("chi_alpha must lie in [1, 2]");
   if (p->collisions) {
     if (!(p->g_max > 0.0)) return bad("g_max must be positive");
     if (p->sigma_model == PIC_SIGMA_POLY) {
@@ -155,6 +157,8 @@ SimConst derive(const pic_problem* p, const pic_discretization* d, uint64_t seed
   K.n_sigma = p->sigma_model == PIC_SIGMA_POLY ? p->n_sigma : 0;
   K.collisions = p->collisions;
   K.isolate = p->isolate;
+  K.chi_model = p->chi_model;
+  K.chi_alpha = p->chi_model == PIC_CHI_VSS ? p->chi_alpha : 1.0;
   K.navg = d->n_avg;
   K.np = d->n_particles;
   K.nn = d->ncell[0] * d->ncell[1] * d->ncell[2];
@@ -651,9 +655,10 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
     const double tA = (double)a.na * K.dt, tB = ((double)a.nb + 1.0) * K.dt;
     MixConst M = mix_const(K, tA, tB);
     const int s = c->cur;
-    // the collision-angle and pair-log recording is compiled only into the
-    // instances launched while a log is attached
-    const bool ang = K.anglog != nullptr || a.pairlog != nullptr;
+    // the collision-angle and pair-log recording and the anisotropic
+    // polar-angle samplers are compiled only into the full instances; the
+    // lean ones serve isotropic scattering with no log attached
+    const bool ang = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO;
     const dim3 grid(tiles), blk(kTileThreads);
     float *o = c->off[s], *vv = c->vf[s];
     const float *sh = c->asf[s], *e = c->E32;
@@ -672,7 +677,7 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
     LAUNCH_CHECK(c, "particles (mixed)");
     return PIC_OK;
   }
-  const bool ang = K.anglog != nullptr || a.pairlog != nullptr;
+  const bool ang = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO;
   void (*fn)(SimConst, PartArgs) = nullptr;
   if (K.family == 1) {
     if (sig == kSigHS) fn = ang ? k_particles_f64<1, kSigHS, true> : k_particles_f64<1, kSigHS, false>;
@@ -1274,7 +1279,7 @@ int pic_angle_errors(pic_ctx* c, double out[4], int64_t* n_records) {
   double* part = u + 2 * angle_pad(c->angcap);
   const int nb = (int)((P + kBlock - 1) / kBlock);
   double* res = part + 4 * ((angle_pad(c->angcap) + kBlock - 1) / kBlock);
-  k_angle_map<<<nb, kBlock, 0, c->stream>>>(c->angbuf, n, P, u);
+  k_angle_map<<<nb, kBlock, 0, c->stream>>>(c->angbuf, n, P, c->K.chi_model, c->K.chi_alpha, u);
   for (int64_t k = 2; k <= P; k <<= 1)
     for (int64_t j = k >> 1; j > 0; j >>= 1)
       k_bitonic_stage<<<(int)((2 * P + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(u, P, k, j);

@@ -1,6 +1,6 @@
 // Errors of the empirical CDFs of the recorded scattering angles against the
 // analytic ones (the metric that follows eq. angle_recovery): the records are
-// mapped through the isotropic analytic CDFs, F_chi = (1 - cos chi) / 2 and
+// mapped through the analytic CDFs, F_chi of the polar-angle model and
 // F_eps = eps / (2 pi), sorted (bitonic network over a power-of-two padded
 // copy), and e_i = (rank of the last equal value) / N - F(alpha_(i)) is
 // reduced to its root mean square and maximum with fixed-order sums.
@@ -10,13 +10,25 @@
 
 namespace pic {
 
+// F_pchi(chi) of the polar-angle model: (1 - cos chi)/2 (eq. chi_iso);
+// sin^2(chi/2) - (3 + 5 cos 2 chi) sin^2(chi) / 58 (manufactured anisotropy,
+// Sec. 5.2); 1 - cos^(2 alpha)(chi/2) (eq. vss).
+__device__ inline double chi_cdf(int model, double alpha, double chi) {
+  if (model == 1) {
+    const double s2 = sin(0.5 * chi), sc = sin(chi);
+    return s2 * s2 - (3.0 + 5.0 * cos(2.0 * chi)) * sc * sc / 58.0;
+  }
+  if (model == 2) return 1.0 - pow(cos(0.5 * chi), 2.0 * alpha);
+  return 0.5 * (1.0 - cos(chi));
+}
+
 // u[which][i] = F^M(alpha_i) for i < n, 2 (sorts last) up to the padded size P.
 __global__ void __launch_bounds__(kBlock) k_angle_map(const double* rec, int64_t n, int64_t P,
-                                                      double* u) {
+                                                      int model, double alpha, double* u) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= P) return;
   if (i < n) {
-    u[i] = 0.5 * (1.0 - cos(rec[2 * i]));
+    u[i] = chi_cdf(model, alpha, rec[2 * i]);
     u[P + i] = rec[2 * i + 1] / (2.0 * kPi);
   } else {
     u[i] = u[P + i] = 2.0;

@@ -146,7 +146,7 @@ inline size_t brick_lds_bytes(const int bd[3]) {
 template <int Q, int NT>
 __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
   extern __shared__ double R[];
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[3 * (NT / 64)];
   const int bd[3] = {a.bdim[0], a.bdim[1], Q};
   int foff[7];
   brick_face_offsets(bd, foff);
@@ -184,6 +184,10 @@ __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
   };
   double xr[Q], rr[Q], wr[Q], sr[Q], pr[Q];
   unsigned gen = 0;
+  // sum of the iterate, carried by each iteration's reduction (for the
+  // zero-mean projection; summed in the same order as a reduction of its own)
+  double xsum = 0.0;
+  bool xsum_ok = false;
 
   // r_0 = -b - A x_0 from the stored iterate (own nodes and halo straight from x)
 #pragma unroll
@@ -271,6 +275,7 @@ __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
         wr[q] = wv;
         gd[0] += rr[q] * rr[q];
         gd[1] += wv * rr[q];
+        gd[2] += xr[q];
         if (face(q)) {
           publish(dst, q, rr[q]);
           publish(dst + nh, q, wv);
@@ -279,7 +284,9 @@ __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
       }
       // (grid_sum's block barrier also orders these stencil reads of R before
       // the next sweep overwrites it)
-      if (!grid_sum_t<NT>(a, gd, 2, ++gen, sh)) return;
+      if (!grid_sum_t<NT>(a, gd, 3, ++gen, sh)) return;
+      xsum = gd[2];
+      xsum_ok = true;
       cur ^= 1;
       ++it;
       beta = gd[0] / gamma;
@@ -288,12 +295,16 @@ __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
       if (sqrt(gamma) <= a.tol * bnorm) break;
     }
   }
-  // zero-mean projection (Sec. 2)
-  double s_x[kMaxRed] = {0.0, 0.0, 0.0};
+  // zero-mean projection (Sec. 2); the last iteration's reduction carried
+  // the sum of the final iterate, else one more reduction
+  if (!xsum_ok) {
+    double s_x[kMaxRed] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int q = 0; q < Q; ++q) s_x[0] += xr[q];
-  if (!grid_sum_t<NT>(a, s_x, 1, ++gen, sh)) return;
-  const double mean = s_x[0] / (double)K.nn;
+    for (int q = 0; q < Q; ++q) s_x[0] += xr[q];
+    if (!grid_sum_t<NT>(a, s_x, 1, ++gen, sh)) return;
+    xsum = s_x[0];
+  }
+  const double mean = xsum / (double)K.nn;
 #pragma unroll
   for (int q = 0; q < Q; ++q) a.x[gn(q)] = xr[q] - mean;
   if (blockIdx.x == 0 && tid == 0) {

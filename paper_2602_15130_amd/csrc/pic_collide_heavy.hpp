@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(64 * kHeavyWaves) k_collide_heavy(SimConst K, 
           if (ok) {
             ++nacc;
             const double eps = 2.0 * kPi * W.peps[j];
-            const double cchi = 1.0 - 2.0 * W.pchi[j];  // eq. chi_iso
+            const double cchi = cos_chi<double>(K, W.pchi[j]);  // eq. chi
             const double schi = sqrt(fmax(0.0, (1.0 - cchi) * (1.0 + cchi)));
             const double nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
             if (ip < 0) {

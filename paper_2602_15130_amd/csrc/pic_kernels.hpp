@@ -70,6 +70,31 @@ __device__ inline double block_sum_t(double v, double* sh) {
   return r;
 }
 __device__ inline double block_sum(double v, double* sh) { return block_sum_t<kBlock>(v, sh); }
+// block_sum_t of nv <= 3 values at once (one barrier pair for all of them;
+// each value summed in the same order as block_sum_t).  sh: 3 * NT / 64 doubles.
+template <int NT>
+__device__ inline void block_sum3_t(double* v, int nv, double* sh) {
+  constexpr int W = NT / 64;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  double w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] = i < nv ? wave_sum(v[i]) : 0.0;
+  __syncthreads();
+  if (ln == 0) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (i < nv) sh[i * W + wv] = w[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i >= nv) break;
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) r += sh[i * W + k];
+    v[i] = r;
+  }
+}
 __device__ inline double block_max(double v, double* sh) {
   v = wave_max(v);
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
@@ -417,6 +442,7 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(SimConst K, double* b, cons
 // ---------------------------------------------------------------------------
 constexpr int kFlagStride = 32;  // 128 bytes between per-block flags
 constexpr int kMaxRed = 3;       // values per reduction
+static_assert(kMaxRed == 3, "block_sum3_t reduces up to three values");
 
 struct CgArgs {
   const double* b;
@@ -467,7 +493,8 @@ __device__ inline bool grid_sum_t(const CgArgs& a, double* vals, int nv, unsigne
   // and so publishes the whole block's stores with its flag.  (A workgroup
   // barrier alone does not wait for outstanding vector-memory stores.)
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  for (int i = 0; i < nv; ++i) tot[i] = block_sum_t<NT>(vals[i], sh);
+  for (int i = 0; i < nv; ++i) tot[i] = vals[i];
+  block_sum3_t<NT>(tot, nv, sh);
   if (threadIdx.x == 0) {
     for (int i = 0; i < nv; ++i) a.part[blockIdx.x * kMaxRed + i] = tot[i];
     __hip_atomic_store(&a.arrive[blockIdx.x * kFlagStride], gen, __ATOMIC_RELEASE,
@@ -482,12 +509,12 @@ __device__ inline bool grid_sum_t(const CgArgs& a, double* vals, int nv, unsigne
     if (!good) ok = 0;
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (int i = 0; i < nv; ++i) {
-      double acc = 0.0;
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += NT) acc += a.part[b * kMaxRed + i];
-      double s = block_sum_t<NT>(acc, sh);
-      if (threadIdx.x == 0) a.result[i] = s;
-    }
+    double acc[kMaxRed] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < nv; ++i)
+      for (int b = threadIdx.x; b < (int)gridDim.x; b += NT) acc[i] += a.part[b * kMaxRed + i];
+    block_sum3_t<NT>(acc, nv, sh);
+    if (threadIdx.x == 0)
+      for (int i = 0; i < nv; ++i) a.result[i] = acc[i];
     if (threadIdx.x == 0)
       __hip_atomic_store(a.release, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -515,7 +542,7 @@ __device__ inline double neg_lap(const SimConst& K, int i, int j, int k, const F
 }
 
 __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
-  __shared__ double sh[kWaves];
+  __shared__ double sh[3 * kWaves];
   const int gsize = gridDim.x * kBlock;
   const int g0 = blockIdx.x * kBlock + threadIdx.x;
   unsigned gen = 0;
@@ -676,6 +703,31 @@ __device__ inline int pick_partner(const SimConst& K, int cell, int64_t step, in
   return q;
 }
 
+// cos chi = cos F_pchi^{-1}(xi) of the polar-angle model, in the working
+// precision R:
+//   isotropic, eq. chi_iso: 1 - 2 xi;
+//   manufactured anisotropy (Sec. 5.2), eq. fpiv_ms: u = sin^2(chi/2) from the
+//     closed-form a(xi), b(xi); cos chi = 1 - 2 u;
+//   variable soft sphere, eq. vss: cos(chi/2) = (1 - xi)^(1/(2 alpha)), the
+//     exact inverse of F = 1 - cos^(2 alpha)(chi/2); cos chi = 2 (1 - xi)^(1/alpha) - 1.
+// ANY = false compiles the isotropic law alone (the fused kernels' lean
+// instances, launched only for isotropic scattering).
+template <class R, bool ANY = true>
+__device__ inline R cos_chi(const SimConst& K, R xi) {
+  if constexpr (!ANY) return (R)1.0 - (R)2.0 * xi;
+  if (K.chi_model == 1) {
+    const R inner = (R)298924665.0 +
+                    (R)55680.0 * xi * ((R)376377.0 + (R)2320.0 * xi * ((R)-429.0 + (R)290.0 * xi));
+    const R a = cbrt((R)81909.0 - (R)83520.0 * xi + sqrt(inner)) / ((R)40.0 * cbrt((R)9.0));
+    const R b = (R)0.2 + a + ((R)161.0 - (R)290.0 * xi) / ((R)600.0 * a);
+    const R sb = sqrt(b);
+    const R u = (R)0.5 * ((R)1.0 - sb + sqrt((R)0.6 - b + (R)29.0 / ((R)40.0 * sb)));
+    return (R)1.0 - (R)2.0 * u;
+  }
+  if (K.chi_model == 2) return (R)2.0 * pow((R)1.0 - xi, (R)1.0 / (R)K.chi_alpha) - (R)1.0;
+  return (R)1.0 - (R)2.0 * xi;
+}
+
 // Capacity of the workgroup-per-cell collision kernel (k_collide_heavy):
 // particles per cell and candidate pairs per outcome.  A cell that could
 // exceed either (N_pairs = floor(n (n - 1) P_max / 2 + U) < n (n - 1) P_max / 2 + 1)
@@ -731,7 +783,7 @@ __global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, in
       if (ok) {
         ++acc;
         double eps = 2.0 * kPi * unif(wa.w[3]);
-        double cchi = 1.0 - 2.0 * unif(wb.w[0]);  // eq. chi_iso
+        double cchi = cos_chi<double>(K, unif(wb.w[0]));  // eq. chi
         double schi = sqrt(fmax(0.0, (1.0 - cchi) * (1.0 + cchi)));
         double nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
         for (int d = 0; d < 3; ++d) {

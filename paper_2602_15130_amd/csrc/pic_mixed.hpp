@@ -266,7 +266,7 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 // The mixed-form fused pass (configuration family), same phases as the FP64 one.
 // Registers are capped for six waves per SIMD (measured best at 64^3: the pass
 // is latency bound, and the extra resident waves outweigh the spills).
-template <int SIG, bool TRACE>
+template <int SIG, bool FULL>
 __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
   };
 
   if (a.mode & kCollideOnly) {
-    tile_collide<SIG, float, TRACE>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+    tile_collide<SIG, float, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                              NP, cl);
     for (int j = tid; j < ns; j += kTileThreads) {
       int n = cell_count(j);
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
 
   if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
     if (K.collisions)
-      tile_collide<SIG, float, TRACE>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+      tile_collide<SIG, float, FULL>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                NP, cl);
     for (int j = tid; j < ns; j += kTileThreads) kick(j, M.emB, K.collisions != 0);
     __syncthreads();
@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
 
   // call A at t^{na}, first half kick, drift to t^{na+1}
   if (K.collisions)
-    tile_collide<SIG, float, TRACE>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+    tile_collide<SIG, float, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
                              st, NP, cl);
   for (int base = 0; base < ns; base += kTileThreads) {
     int j = base + tid;

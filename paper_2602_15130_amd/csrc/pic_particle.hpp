@@ -105,7 +105,7 @@ __device__ inline R sigma_g_r(const SimConst& K, R g) {
 // with stride st).  The outcome's private velocities are copy-on-write: slot j
 // holds a private value in u when mark[j] == tag, else its value is v0[j]; the
 // slots written are appended to the touched list tl.
-template <int SIG, class R, bool TRACE>
+template <int SIG, class R, bool FULL>
 __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, int call, int k,
                                    int64_t npairs, int n, const R* v0, R* u, int* mark, int tag,
                                    int* tl, int& ntl, int st, int stu, long long* pairlog,
@@ -132,7 +132,7 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
     if (ok) {
       ++acc;
       R eps = (R)2.0 * (R)kPi * unif_r<R>(wa.w[3]);
-      R cchi = (R)1.0 - (R)2.0 * unif_r<R>(wb.w[0]);  // eq. chi_iso
+      R cchi = cos_chi<R, FULL>(K, unif_r<R>(wb.w[0]));  // eq. chi
       R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
       R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
       R pn[3], qn[3];
@@ -143,7 +143,7 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
         u[d * stu + p] = pn[d];
         u[d * stu + q] = qn[d];
       }
-      if constexpr (TRACE) record_angles<R>(pn, qn, g, K.anglog, K.angcap, counters);
+      if constexpr (FULL) record_angles<R>(pn, qn, g, K.anglog, K.angcap, counters);
       if (mark[p] != tag) {
         mark[p] = tag;
         tl[ntl++] = p;
@@ -153,7 +153,7 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
         tl[ntl++] = q;
       }
     }
-    if (TRACE && pairlog) {
+    if (FULL && pairlog) {
       unsigned long long s = atomicAdd(&counters[kCntPairLog], 1ull);
       if ((int64_t)s < cap) {
         long long* r = pairlog + 7 * s;
@@ -192,7 +192,7 @@ __device__ inline int64_t npairs_of(const SimConst& K, int cell, int64_t step, i
 // records of the pool (slot in pslot, current value in pdv), everything else
 // is read from v0; at the end the records are turned into velocity changes.
 // Same arithmetic as ntc_outcome.  Returns the number of records.
-template <int SIG, class R, bool TRACE>
+template <int SIG, class R, bool FULL>
 __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t step, int call, int k,
                                         int npairs, int n, const R* v0, int st, int* pslot, R* pdv,
                                         long long* pairlog, int64_t cap,
@@ -224,7 +224,7 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
     if (ok) {
       ++acc;
       R eps = (R)2.0 * (R)kPi * unif_r<R>(wa.w[3]);
-      R cchi = (R)1.0 - (R)2.0 * unif_r<R>(wb.w[0]);  // eq. chi_iso
+      R cchi = cos_chi<R, FULL>(K, unif_r<R>(wb.w[0]));  // eq. chi
       R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
       R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
       if (ip < 0) {
@@ -243,9 +243,9 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
         pdv[d * kPool + ip] = pn[d];
         pdv[d * kPool + iq] = qn[d];
       }
-      if constexpr (TRACE) record_angles<R>(pn, qn, g, K.anglog, K.angcap, counters);
+      if constexpr (FULL) record_angles<R>(pn, qn, g, K.anglog, K.angcap, counters);
     }
-    if (TRACE && pairlog) {
+    if (FULL && pairlog) {
       unsigned long long s = atomicAdd(&counters[kCntPairLog], 1ull);
       if ((int64_t)s < cap) {
         long long* r = pairlog + 7 * s;
@@ -263,7 +263,7 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
 // is read).  Outcomes already run by a lane contribute their stored changes;
 // the others run here.  Only the particles an outcome changed contribute to
 // the sum; the others would add exact zeros.
-template <int SIG, class R, bool TRACE>
+template <int SIG, class R, bool FULL>
 __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
                                      int c, int ci, int cs, int n, const R* v0, R* u, R* D,
                                      int* mark, int* tl, int tagbase, int st, int stu,
@@ -304,7 +304,7 @@ __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int c
       marks_clear = true;
     }
     int ntl = 0;
-    ntc_outcome<SIG, R, TRACE>(K, c, step, call, k, np_, n, v0 + cs, u + cs, mark + cs, tagbase + k + 1,
+    ntc_outcome<SIG, R, FULL>(K, c, step, call, k, np_, n, v0 + cs, u + cs, mark + cs, tagbase + k + 1,
                         tl + cs, ntl, st, stu, a.pairlog, a.cap, a.counters, acc, gmx);
     for (int t = 0; t < ntl; ++t) {
       int j = cs + tl[cs + t];
@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_collide_big(SimConst K, int call, in
 // stride st) -> D = N_avg <dv> per slot.  u (stride stu), mark and tl are
 // scratch of the tile's slots for the outcomes a cell thread runs itself; a
 // cell's marks are cleared before its first such outcome in a call.
-template <int SIG, class R, bool TRACE>
+template <int SIG, class R, bool FULL>
 __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
                                     int64_t step, int c0, int ncells, int s0, int ns,
                                     const R* v0, R* u, R* D, int* mark, int* tl, int tagbase,
@@ -418,7 +418,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
       int ci = l / navg, k = l - ci * navg;
       int c = c0 + ci;
       int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
-      int cnt = ntc_outcome_small<SIG, R, TRACE>(K, c, step, call, k, np_, n, v0 + cs, st,
+      int cnt = ntc_outcome_small<SIG, R, FULL>(K, c, step, call, k, np_, n, v0 + cs, st,
                                           L.pslot + start, L.pdv + start, a.pairlog, a.cap,
                                           a.counters, acc, gmx);
       L.evp[e] = start | (cnt << 16);
@@ -435,7 +435,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
       for (int e = 0; e < ne; ++e) any |= (L.evt[e] / navg) == ci;
       if (!any) continue;
     }
-    cell_outcomes<SIG, R, TRACE>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, stu, L,
+    cell_outcomes<SIG, R, FULL>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, stu, L,
                           ne, all, acc, gmx);
   }
   if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
@@ -564,7 +564,7 @@ __device__ inline void half_kick_f64(const SimConst& K, const double xp[3], cons
 // LDS (three tile arrays) allows four workgroups per CU; registers are capped
 // to match (four waves per SIMD), accepting a few spills: the pass is latency
 // bound and gains more from resident waves than it loses to spill traffic.
-template <int FAM, int SIG, bool TRACE>
+template <int FAM, int SIG, bool FULL>
 __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(SimConst K, PartArgs a) {
   // the copy-on-write scratch of outcomes run by a cell thread is global
   __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots];
@@ -596,7 +596,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
   __syncthreads();
 
   if (a.mode & kCollideOnly) {
-    tile_collide<SIG, double, TRACE>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+    tile_collide<SIG, double, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                               NP, cl);
     for (int j = tid; j < ns; j += kTileThreads) {
       int c = a.key[s0 + j];
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
     // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
     const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
     if (K.collisions)
-      tile_collide<SIG, double, TRACE>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+      tile_collide<SIG, double, FULL>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                 NP, cl);
     for (int j = tid; j < ns; j += kTileThreads) {
       int p = s0 + j;
@@ -644,7 +644,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
   // collision call A at t^{na} on v^{na}, first half kick, drift to t^{na+1}
   const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
   if (K.collisions)
-    tile_collide<SIG, double, TRACE>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+    tile_collide<SIG, double, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
                               st, NP, cl);
   for (int base = 0; base < ns; base += kTileThreads) {
     int j = base + tid;
