@@ -34,7 +34,7 @@ class OrcProblem(C.Structure):
 
 class OrcDisc(C.Structure):
     _fields_ = [("nc", C.c_int * 3), ("np", C.c_int64), ("dt", C.c_double), ("navg", C.c_int),
-                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int)]
+                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int), ("poisson_op", C.c_int)]
 
 
 class OrcPair(C.Structure):
@@ -141,6 +141,7 @@ def make_disc(d: dict) -> OrcDisc:
     s.navg = int(d["navg"])
     s.cg_tol = float(d["cg_tol"])
     s.cg_max_iter = int(d["cg_max_iter"])
+    s.poisson_op = int(d.get("poisson_op", 0))
     return s
 
 

@@ -546,28 +546,78 @@ static void node_position(const orc_problem* P, const orc_disc* D, int64_t n, do
   x[2] = k * (P->L[2] / D->nc[2]);
 }
 
-/* Eq. poisson_mms at the nodes, spatial mean removed (Sec. 2). */
+/* Eq. poisson_mms at the nodes, spatial mean removed (Sec. 2).
+ * 7-point form: b_i = lap phi^M(x_i) - (rho_i - q f_x(x_i)) / eps0, pointwise.
+ * Q1 form (Galerkin, divided by the cell volume): the particle charge enters as
+ * rho_i = (q w / dV) sum_p N_i(x_p), which is exactly (1/dV) int rho N_i for
+ * point charges; the manufactured terms m = lap phi^M + q f_x / eps0 enter as
+ * (1/dV) (M m)_i with the consistent Q1 mass matrix M applied to their nodal
+ * values: the tensor product of (1, 4, 1) / 6 along each axis. */
 void orc_rhs(const orc_problem* P, const orc_disc* D, const double* rho, double t, double* b) {
   int64_t nn = nnodes(D);
-  double sum = 0.0;
+  double* m = (double*)malloc(sizeof(double) * (size_t)nn);
   for (int64_t n = 0; n < nn; ++n) {
     double xn[3];
     node_position(P, D, n, xn);
     double v = orc_lapphiM(P, xn, t);
-    if (P->particles_to_field) v += -(rho[n] - P->q * orc_fx(P, xn, t)) / P->eps0;
-    b[n] = v;
-    sum += v;
+    if (P->particles_to_field) v += P->q * orc_fx(P, xn, t) / P->eps0;
+    m[n] = v;
   }
+  double sum = 0.0;
+  for (int k = 0; k < D->nc[2]; ++k)
+    for (int j = 0; j < D->nc[1]; ++j)
+      for (int i = 0; i < D->nc[0]; ++i) {
+        int64_t n = node_index(D, i, j, k);
+        double v;
+        if (D->poisson_op == ORC_OP_Q1) {
+          static const double w1[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+          v = 0.0;
+          for (int c = -1; c <= 1; ++c)
+            for (int bb = -1; bb <= 1; ++bb)
+              for (int a = -1; a <= 1; ++a)
+                v += w1[a + 1] * w1[bb + 1] * w1[c + 1] * m[node_index(D, i + a, j + bb, k + c)];
+        } else {
+          v = m[n];
+        }
+        if (P->particles_to_field) v -= rho[n] / P->eps0;
+        b[n] = v;
+        sum += v;
+      }
+  free(m);
   double mean = sum / (double)nn;
   for (int64_t n = 0; n < nn; ++n) b[n] -= mean;
 }
 
-/* Periodic 7-point Laplacian. */
+/* Periodic Laplacian L of the field discretization.  7-point: the second
+ * differences (phi_{i-1} - 2 phi_i + phi_{i+1}) / h^2 summed over the axes.
+ * Q1 (minus the trilinear stiffness divided by the cell volume, Sec. 4.2):
+ * along each axis d the second difference in d times the 1-D mass weights
+ * (1, 4, 1) / 6 in the two other axes, summed over d (27 points). */
 void orc_laplacian(const orc_disc* D, const orc_problem* P, const double* phi, double* out) {
   double ih2[3];
   for (int d = 0; d < 3; ++d) {
     double h = P->L[d] / D->nc[d];
     ih2[d] = 1.0 / (h * h);
+  }
+  if (D->poisson_op == ORC_OP_Q1) {
+    static const double w1[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    static const double d2[3] = {1.0, -2.0, 1.0};
+    for (int k = 0; k < D->nc[2]; ++k)
+      for (int j = 0; j < D->nc[1]; ++j)
+        for (int i = 0; i < D->nc[0]; ++i) {
+          double v = 0.0;
+          for (int c = -1; c <= 1; ++c)
+            for (int bb = -1; bb <= 1; ++bb)
+              for (int a = -1; a <= 1; ++a) {
+                double f = phi[node_index(D, i + a, j + bb, k + c)];
+                double wx = d2[a + 1] * ih2[0] * w1[bb + 1] * w1[c + 1];
+                double wy = w1[a + 1] * d2[bb + 1] * ih2[1] * w1[c + 1];
+                double wz = w1[a + 1] * w1[bb + 1] * d2[c + 1] * ih2[2];
+                v += (wx + wy + wz) * f;
+              }
+          out[node_index(D, i, j, k)] = v;
+        }
+    return;
   }
   for (int k = 0; k < D->nc[2]; ++k)
     for (int j = 0; j < D->nc[1]; ++j)

@@ -75,7 +75,14 @@ typedef struct {
   int navg;                /* averaged independent collision outcomes */
   double cg_tol;           /* relative residual tolerance */
   int cg_max_iter;
+  int poisson_op;          /* ORC_OP_FD7 or ORC_OP_Q1 */
 } orc_disc;
+
+/* Field discretization: the periodic 7-point finite-difference Laplacian with
+ * a pointwise right-hand side, or the trilinear (Q1) finite elements of
+ * Sec. 4.2 (27-point stiffness, Galerkin right-hand side), both divided by the
+ * cell volume so that the system reads L phi = b in either case. */
+enum { ORC_OP_FD7 = 0, ORC_OP_Q1 = 1 };
 
 typedef struct orc_sim orc_sim;
 

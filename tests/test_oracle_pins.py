@@ -903,3 +903,88 @@ def test_anisotropic_collisions_follow_their_own_law():
     iso = O.angle_errors(r, 0, 0.0) * math.sqrt(n)
     assert own[1] < 2.0 and own[3] < 2.0, own
     assert iso[1] > 4.0, iso
+
+
+# ----------------------------------------------------------------------------- trilinear finite elements
+def _q1_assemble(nc, L):
+    """Periodic Q1 stiffness K and mass M assembled element by element from
+    2-point Gauss quadrature (exact for the trilinear products)."""
+    nx, ny, nz = nc
+    h = [L[d] / nc[d] for d in range(3)]
+    nn = nx * ny * nz
+    K = np.zeros((nn, nn))
+    M = np.zeros((nn, nn))
+    g = np.array([0.5 - 0.5 / math.sqrt(3), 0.5 + 0.5 / math.sqrt(3)])
+    corners = [(a, b, c) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+
+    def shape(a, s):  # 1-D shape value and derivative (reference coordinate in [0, 1])
+        return (s if a else 1 - s), (1.0 if a else -1.0)
+
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                idx = [((k + c) % nz * ny + (j + b) % ny) * nx + (i + a) % nx for a, b, c in corners]
+                for sx in g:
+                    for sy in g:
+                        for sz in g:
+                            wq = 0.125 * h[0] * h[1] * h[2]
+                            vals, grads = [], []
+                            for a, b, c in corners:
+                                (nxv, dx), (nyv, dy), (nzv, dz) = shape(a, sx), shape(b, sy), shape(c, sz)
+                                vals.append(nxv * nyv * nzv)
+                                grads.append(np.array([dx * nyv * nzv / h[0], nxv * dy * nzv / h[1],
+                                                       nxv * nyv * dz / h[2]]))
+                            for p in range(8):
+                                for q in range(8):
+                                    K[idx[p], idx[q]] += wq * grads[p].dot(grads[q])
+                                    M[idx[p], idx[q]] += wq * vals[p] * vals[q]
+    return K, M
+
+
+def test_q1_operator_is_the_assembled_trilinear_stiffness():
+    """Sec. 4.2, trilinear elements: the Q1 Laplacian of the oracle equals minus
+    the element-by-element assembled stiffness divided by the cell volume, and
+    its right-hand side applies the assembled mass matrix (over the cell
+    volume) to the nodal manufactured terms, on a ragged periodic mesh."""
+    nc, L = (4, 3, 5), (1.0, 0.8, 1.3)
+    K, M = _q1_assemble(nc, L)
+    dV = np.prod([L[d] / nc[d] for d in range(3)])
+    prob = W.cfg_problem(two_way=False, collisions=False)
+    prob["L"] = L
+    disc = W.cfg_disc(4, 64, 1e-3, 1, 1)
+    disc["nc"] = nc
+    disc["poisson_op"] = 1
+    rng = np.random.default_rng(7)
+    phi = rng.standard_normal(np.prod(nc))
+    np.testing.assert_allclose(O.laplacian(prob, disc, phi), -(K @ phi) / dV, rtol=0, atol=1e-10 * np.abs(K @ phi / dV).max())
+    # right-hand side without the particles: (1/dV) M m, mean removed
+    t = 0.013
+    xs = [np.arange(nc[d]) * L[d] / nc[d] for d in range(3)]
+    m = np.array([O.scalar("orc_lapphiM", prob, (xs[0][i], xs[1][j], xs[2][k]), t)
+                  for k in range(nc[2]) for j in range(nc[1]) for i in range(nc[0])])
+    b = O.rhs(prob, disc, np.zeros(np.prod(nc)), t)
+    ref = M @ m / dV
+    np.testing.assert_allclose(b, ref - ref.mean(), rtol=0, atol=1e-12 * np.abs(ref).max())
+    # the 7-point operator is untouched by the switch
+    disc["poisson_op"] = 0
+    lap7 = O.laplacian(prob, disc, phi)
+    assert not np.allclose(lap7, -(K @ phi) / dV)
+
+
+def test_q1_poisson_solve_is_second_order():
+    """The Q1 discrete solution of lap phi = lap phi^M (Galerkin right-hand
+    side) converges to phi^M at second order in h (Sec. 4.2: the basis-function
+    error is O(h^2))."""
+    prob = W.cfg_problem(two_way=False, collisions=False)
+    errs = []
+    for n in (8, 16, 32):
+        disc = W.cfg_disc(n, 64, 1e-3, 1, 1, cg_tol=1e-13)
+        disc["poisson_op"] = 1
+        b = O.rhs(prob, disc, np.zeros(n ** 3), 0.0)
+        phi, it, rr = O.cg(prob, disc, b)[:3]
+        xs = np.arange(n) / n
+        ex = np.array([O.scalar("orc_phiM", prob, (xs[i], xs[j], xs[k]), 0.0)
+                       for k in range(n) for j in range(n) for i in range(n)])
+        errs.append(np.abs(phi - (ex - ex.mean())).max())
+    orders = [math.log2(a / c) for a, c in zip(errs, errs[1:])]
+    assert orders[0] > 1.75 and orders[1] == pytest.approx(2.0, abs=0.05), errs
