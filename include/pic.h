@@ -119,7 +119,20 @@ typedef struct {
   int n_avg;                /* N_avg >= 1 (eq. avg_outcome) */
   double cg_tol;            /* stop when ||r||_2 <= cg_tol ||rhs||_2 */
   int cg_max_iter;          /* >= 1 */
+  int poisson_op;           /* enum pic_poisson_op */
 } pic_discretization;
+
+/* Field discretization (Sec. 4.2), both written as L phi = b over the cell
+ * volume: the periodic 7-point finite-difference Laplacian with a pointwise
+ * right-hand side, or trilinear (Q1) finite elements: minus the 27-point
+ * stiffness, the particle charge through the cloud-in-cell weights (exact for
+ * point charges) and the manufactured terms through the consistent mass
+ * matrix applied to their nodal values.  The Q1 form uses the global-memory
+ * solver. */
+enum pic_poisson_op {
+  PIC_OP_FD7 = 0,
+  PIC_OP_Q1 = 1
+};
 
 typedef struct pic_ctx pic_ctx;
 

@@ -115,6 +115,7 @@ int validate(const pic_problem* p, const pic_discretization* d, int precision, s
   if (!(d->dt > 0.0)) return bad("dt must be positive");
   if (d->n_avg < 1) return bad("n_avg must be >= 1");
   if (!(d->cg_tol > 0.0) || d->cg_max_iter < 1) return bad("bad CG controls");
+  if (d->poisson_op != PIC_OP_FD7 && d->poisson_op != PIC_OP_Q1) return bad("poisson_op must be 0 or 1");
   if (!(p->nphys > 0.0) || !(p->eps0 > 0.0) || !(p->T > 0.0) || !(p->vbar > 0.0))
     return bad("nphys, eps0, T and vbar must be positive");
   if (p->field_to_particles && p->m == 0.0) return bad("m must be nonzero");
@@ -188,6 +189,7 @@ SimConst derive(const pic_problem* p, const pic_discretization* d, uint64_t seed
   K.sg_pow = 2.0 - 2.0 * p->omega;
   K.nphys = p->nphys;
   K.dt = d->dt;
+  K.poisson_op = d->poisson_op;
   K.w = p->nphys / (double)d->n_particles;
   K.dV = (p->L[0] / d->ncell[0]) * (p->L[1] / d->ncell[1]) * (p->L[2] / d->ncell[2]);
   K.rho_scale = p->q * K.w / K.dV;
@@ -909,7 +911,8 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   c->cg_fn = (const void*)k_cg;
   c->cg_nt = kBlock;
   const char* force_global = std::getenv("PIC_CG_GLOBAL");
-  if (!(force_global && std::atoi(force_global) == 1)) {
+  // (the brick solver's on-chip stencil is the 7-point one)
+  if (!(force_global && std::atoi(force_global) == 1) && c->K.poisson_op == PIC_OP_FD7) {
     // co-resident workgroups per CU of each instance at its largest LDS use
     int lds_max = 65536;
     (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);

@@ -35,6 +35,7 @@ struct SimConst {
   double rho_scale;    // q w / dV
   double src_half;     // w dt / (2 dV)
   double nphys;
+  int poisson_op;      // field discretization: 0 7-point differences, 1 trilinear elements
   int chi_model;       // polar-angle model: 0 isotropic, 1 manufactured anisotropy, 2 VSS
   double chi_alpha;    // VSS exponent
   double* anglog;      // scattering-angle records (chi, eps) of accepted collisions, or null

@@ -380,6 +380,28 @@ __device__ inline void node_coords(const SimConst& K, int n, int& i, int& j, int
   k = n / (K.nc[0] * K.nc[1]);
 }
 
+// Manufactured part of eq. poisson_mms at node (i, j, k): m = lap phi^M, plus
+// q f_x / eps0 when the particles feed the field; pointwise for the 7-point
+// operator, through the Q1 mass weights (1, 4, 1) / 6 per axis (the consistent
+// mass matrix over the cell volume) for trilinear elements.
+__device__ inline double rhs_manufactured(const SimConst& K, int i, int j, int k, double t) {
+  auto m_at = [&](int ii, int jj, int kk) {
+    const double xn[3] = {ii * K.h[0], jj * K.h[1], kk * K.h[2]};
+    double v = lap_phiM(K, xn, t);
+    if (K.p2f != 0.0) v += K.q * number_density(K, xn, t) / K.eps0;
+    return v;
+  };
+  if (K.poisson_op != 1) return m_at(i, j, k);
+  const double w1[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+  double v = 0.0;
+  for (int c = -1; c <= 1; ++c)
+    for (int bb = -1; bb <= 1; ++bb)
+      for (int a = -1; a <= 1; ++a)
+        v += w1[a + 1] * w1[bb + 1] * w1[c + 1] *
+             m_at(wrapi(i + a, K.nc[0]), wrapi(j + bb, K.nc[1]), wrapi(k + c, K.nc[2]));
+  return v;
+}
+
 // Node charge and the right-hand side of eq. poisson_mms; block partial sums
 // of b for the mean removal.
 template <class MomT>
@@ -401,9 +423,8 @@ __global__ void __launch_bounds__(kBlock) k_node_rhs(SimConst K, const MomT* mom
           s += (double)mom[(int64_t)(cz * 4 + cy * 2 + cx) * K.nn + lin(K, i - cx, j - cy, k - cz)];
     double r = K.rho_scale * s;
     rho[n] = r;
-    double xn[3] = {i * K.h[0], j * K.h[1], k * K.h[2]};
-    bv = lap_phiM(K, xn, t);
-    if (K.p2f != 0.0) bv += -(r - K.q * number_density(K, xn, t)) / K.eps0;
+    bv = rhs_manufactured(K, i, j, k, t);
+    if (K.p2f != 0.0) bv -= r / K.eps0;
     b[n] = bv;
   }
   double tot = block_sum(bv, sh);
@@ -531,9 +552,29 @@ __device__ inline bool grid_sum(const CgArgs& a, double* vals, int nv, unsigned 
   return grid_sum_t<kBlock>(a, vals, nv, gen, sh);
 }
 
-// (-L f)(n) for f given by a callable.
+// (-L f)(n) for f given by a callable.  7-point: minus the summed second
+// differences.  Trilinear elements (Sec. 4.2): the stiffness over the cell
+// volume, 27 points: along each axis d the second difference in d times the
+// 1-D mass weights (1, 4, 1) / 6 in the two other axes, summed over d.
 template <class F>
 __device__ inline double neg_lap(const SimConst& K, int i, int j, int k, const F& f) {
+  if (K.poisson_op == 1) {
+    const double w1[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    const double d2[3] = {1.0, -2.0, 1.0};
+    double v = 0.0;
+#pragma unroll
+    for (int c = -1; c <= 1; ++c)
+#pragma unroll
+      for (int bb = -1; bb <= 1; ++bb)
+#pragma unroll
+        for (int a = -1; a <= 1; ++a) {
+          const double wx = d2[a + 1] * K.ih2[0] * w1[bb + 1] * w1[c + 1];
+          const double wy = w1[a + 1] * d2[bb + 1] * K.ih2[1] * w1[c + 1];
+          const double wz = w1[a + 1] * w1[bb + 1] * d2[c + 1] * K.ih2[2];
+          v += (wx + wy + wz) * f(lin(K, i + a, j + bb, k + c));
+        }
+    return -v;
+  }
   double c = f(lin(K, i, j, k));
   double lx = f(lin(K, i + 1, j, k)) - 2.0 * c + f(lin(K, i - 1, j, k));
   double ly = f(lin(K, i, j + 1, k)) - 2.0 * c + f(lin(K, i, j - 1, k));

@@ -171,7 +171,13 @@ __global__ void __launch_bounds__(kLowThreads) k_low_solve(SimConst K, LowArgs L
   for (int t = threadIdx.x; t < m0 * m2; t += kLowThreads) {
     const int a = t / m2, cc = t % m2;
     const double acc = low_dot(u + a * nz, 1, phz + cc * pz, 1, nz);
-    const double lam = L.mu[a] + L.mu[kLowMaxM + bb] + L.mu[2 * kLowMaxM + cc];
+    const double ma = L.mu[a], mb = L.mu[kLowMaxM + bb], mc = L.mu[2 * kLowMaxM + cc];
+    double lam = ma + mb + mc;
+    if (K.poisson_op == 1) {  // Q1: mu_d times the 1-D mass eigenvalues 1 - mu h^2 / 6 of the others
+      const double sa = 1.0 - ma / (6.0 * K.ih2[0]), sb = 1.0 - mb / (6.0 * K.ih2[1]),
+                   sc = 1.0 - mc / (6.0 * K.ih2[2]);
+      lam = ma * sb * sc + sa * mb * sc + sa * sb * mc;
+    }
     const double nrm = (a ? 0.5 : 1.0) * (bb ? 0.5 : 1.0) * (cc ? 0.5 : 1.0) * (double)K.nn;
     cf[t] = lam > 0.0 ? acc / (lam * nrm) : 0.0;
   }

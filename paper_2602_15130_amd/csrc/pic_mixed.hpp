@@ -161,9 +161,8 @@ __global__ void __launch_bounds__(kBlock) k_node_rhs_mixed(SimConst K, const flo
         }
     double r = K.rho_scale * s;
     rho[n] = r;
-    double xn[3] = {i * K.h[0], j * K.h[1], k * K.h[2]};
-    bv = lap_phiM(K, xn, t);
-    if (K.p2f != 0.0) bv += -(r - K.q * number_density(K, xn, t)) / K.eps0;
+    bv = rhs_manufactured(K, i, j, k, t);
+    if (K.p2f != 0.0) bv -= r / K.eps0;
     b[n] = bv;
   }
   double tot = block_sum(bv, sh);

@@ -44,7 +44,8 @@ class pic_problem(C.Structure):
 
 class pic_discretization(C.Structure):
     _fields_ = [("ncell", C.c_int * 3), ("n_particles", C.c_int64), ("dt", C.c_double),
-                ("n_avg", C.c_int), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int)]
+                ("n_avg", C.c_int), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int),
+                ("poisson_op", C.c_int)]
 
 
 class pic_error_norms(C.Structure):
@@ -124,6 +125,7 @@ def make_disc(d: dict) -> pic_discretization:
     s.n_avg = int(d["navg"])
     s.cg_tol = float(d["cg_tol"])
     s.cg_max_iter = int(d["cg_max_iter"])
+    s.poisson_op = int(d.get("poisson_op", 0))
     return s
 
 
