@@ -518,3 +518,29 @@ def test_checkpoint_resume_is_bitwise(precision):
     with pytest.raises(P.PicError) as ei:
         other.restore(data)
     assert ei.value.code == P.PIC_EINVAL
+
+
+# ----------------------------------------------------------------------------- stage timing
+def test_stage_timing_covers_the_chosen_stages_only():
+    """pic_timing_enable times every stage of the fused step; pic_timing_stages
+    times only the chosen ones (the others stay at zero launches); timing
+    never changes the result."""
+    prob, disc = _small(16, 60000, 1e-3, 4)
+    P = _pic()
+    g = P.Sim(prob, disc, 3, 0, "mixed")
+    h = P.Sim(prob, disc, 3, 0, "mixed")
+    g.timing(True)
+    g.step(3)
+    h.step(3)
+    st = g.timing_read()
+    for name in ("particle", "sort", "deposit", "cg", "gradient"):
+        ms, n = st[name]
+        assert n >= 3 and ms > 0.0, (name, st[name])
+    g.timing_stages(["particle"])
+    g.step(2)
+    h.step(2)
+    st = g.timing_read()
+    assert st["particle"][1] >= 2 and st["particle"][0] > 0.0
+    assert all(n == 0 for k, (ms, n) in st.items() if k != "particle"), st
+    g.timing(False)
+    np.testing.assert_array_equal(g.get(P.STATE_V), h.get(P.STATE_V))
