@@ -4,16 +4,19 @@
 // persistent block.  A thread owns Q nodes of its brick and keeps x, r, w, s
 // and p of those nodes in registers for the whole solve; the stencil reads
 // r_{i+1} from a padded LDS copy of the brick.  Only the brick faces travel
-// through global memory: after each sweep a block publishes r, w and s on its
-// six faces into a packed per-brick buffer (ping-pong by iteration parity),
-// and the next sweep rebuilds the neighbours' r_{i+1} on the one-node halo
-// from those published values with the expression their owner evaluates, so
-// one grid-wide reduction per iteration is still the only synchronisation.
-// Per iteration a block moves 3 x (face nodes) x 8 bytes each way, in
-// contiguous runs, instead of 80 bytes per node.
+// through global memory: after each sweep a block publishes w on its six faces
+// into a packed per-brick buffer (ping-pong by iteration parity; r_0 once at
+// the start), and the next sweep rebuilds the neighbours' r_{i+1} on the
+// one-node halo with their owner's recurrence, s_i = w_i + beta s_{i-1},
+// r_{i+1} = r_i - alpha s_i, from the published w_i and the halo's r_i and
+// s_{i-1} kept in LDS: the same operations on the same values (no contraction
+// into FMA), so the halo holds the owners' bits, and one grid-wide reduction
+// per iteration is still the only synchronisation.  Per iteration a block
+// moves (face nodes) x 8 bytes each way, in contiguous runs, instead of 80
+// bytes per node.
 //
 // Published faces: pub[((brick * 2 + parity) * 3 + array) * nh + slot], array
-// 0 = r, 1 = w, 2 = s; slots of face f start at foff[f] with faces ordered
+// 0 = r (r_0 only), 1 = w, 2 unused; slots of face f start at foff[f] with faces ordered
 // -x, +x, -y, +y, -z, +z; within an x face the slot is lj + by lk, within a y
 // face li + bx lk, within a z face li + bx lj.  The halo uses the same order,
 // so halo slot h of one brick reads slot h of the opposite face of the
@@ -136,7 +139,7 @@ __device__ inline void brick_publish(double* fb, const int bd[3], const int foff
 inline size_t brick_lds_bytes(const int bd[3]) {
   size_t pad = (size_t)(bd[0] + 2) * (bd[1] + 2) * (bd[2] + 2);
   size_t nh = 2 * ((size_t)bd[1] * bd[2] + (size_t)bd[0] * bd[2] + (size_t)bd[0] * bd[1]);
-  return pad * sizeof(double) + 2 * nh * sizeof(int);
+  return pad * sizeof(double) + 2 * nh * sizeof(int) + 2 * nh * sizeof(double);
 }
 
 // Bricks are NT columns (bdim[0] x bdim[1] = NT) of Q nodes along z: thread t
@@ -161,6 +164,9 @@ __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
   // halo table, built once per solve: padded index and published source
   int* hp = (int*)(R + pxy * (Q + 2));
   int* hs = hp + nh;
+  // the halo's own r and s, carried by the owners' recurrence
+  double* hrv = (double*)(hs + nh);
+  double* hsv = hrv + nh;
   for (int h = tid; h < nh; h += NT) brick_halo_src(bd, a.nbr, foff, bi, bj, bk, h, hp[h], hs[h]);
 
   const int li = tid % bd[0], lj = tid / bd[0];
@@ -223,7 +229,12 @@ __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
     // w_0 = A r_0
 #pragma unroll
     for (int q = 0; q < Q; ++q) R[pl(q)] = rr[q];
-    for (int h = tid; h < nh; h += NT) R[hp[h]] = face_load(pub + hs[h]);
+    for (int h = tid; h < nh; h += NT) {
+      const double rv = face_load(pub + hs[h]);
+      R[hp[h]] = rv;
+      hrv[h] = rv;
+      hsv[h] = 0.0;
+    }
     __syncthreads();
     double v1[kMaxRed] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -253,15 +264,19 @@ __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
         rr[q] = rr[q] - alpha * sv;
         R[pl(q)] = rr[q];
       }
-      // halo: the neighbours' r_{i+1} from their published r_i, w_i, s_{i-1}
+      // halo: the neighbours' r_{i+1} by their own recurrence, from their
+      // published w_i and the halo's r_i, s_{i-1} kept here (the same
+      // operations on the same values as the owners', so the same bits)
       {
-        const double* src = pub + (int64_t)cur * 3 * nh;
+        const double* src = pub + (int64_t)cur * 3 * nh + nh;
 #pragma unroll 4
         for (int h = tid; h < nh; h += NT) {
-          const double* f = src + hs[h];
-          double f0 = face_load(f), f1 = face_load(f + nh);
-          double sv = first ? f1 : f1 + beta * face_load(f + 2 * nh);
-          R[hp[h]] = f0 - alpha * sv;
+          const double wv = face_load(src + hs[h]);
+          const double sv = first ? wv : wv + beta * hsv[h];
+          const double rv = hrv[h] - alpha * sv;
+          hsv[h] = sv;
+          hrv[h] = rv;
+          R[hp[h]] = rv;
         }
       }
       __syncthreads();
@@ -276,11 +291,7 @@ __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
         gd[0] += rr[q] * rr[q];
         gd[1] += wv * rr[q];
         gd[2] += xr[q];
-        if (face(q)) {
-          publish(dst, q, rr[q]);
-          publish(dst + nh, q, wv);
-          publish(dst + 2 * nh, q, sr[q]);
-        }
+        if (face(q)) publish(dst + nh, q, wv);
       }
       // (grid_sum's block barrier also orders these stencil reads of R before
       // the next sweep overwrites it)
