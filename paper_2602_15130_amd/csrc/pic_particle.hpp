@@ -36,7 +36,8 @@ constexpr int kPool = 64;         // velocity-change records of those outcomes p
 // outcome is left to its cell's thread).
 template <class R>
 struct CollideLds {
-  int evt[kMaxEvents];
+  int evc[kMaxEvents];   // tile-local cell of the event
+  int evk[kMaxEvents];   // its outcome
   int evn[kMaxEvents];
   int evp[kMaxEvents];
   int n_evt, overflow, pool_n;
@@ -279,8 +280,7 @@ __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int c
     } else {  // next event of this cell in increasing outcome order
       k = navg;
       for (int e = 0; e < ne; ++e) {
-        int l = L.evt[e];
-        int eci = l / navg, ek = l - eci * navg;
+        const int eci = L.evc[e], ek = L.evk[e];
         if (eci == ci && ek > last && ek < k) {
           k = ek;
           ev = e;
@@ -389,7 +389,8 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
       if (np_ > 0) {
         int e = atomicAdd(&L.n_evt, 1);
         if (e < kMaxEvents) {
-          L.evt[e] = ci * navg + k;
+          L.evc[e] = ci;
+          L.evk[e] = k;
           L.evn[e] = (int)np_;
         } else {
           L.overflow = 1;
@@ -414,8 +415,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
         L.evp[e] = -1;
         continue;
       }
-      int l = L.evt[e];
-      int ci = l / navg, k = l - ci * navg;
+      int ci = L.evc[e], k = L.evk[e];
       int c = c0 + ci;
       int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
       int cnt = ntc_outcome_small<SIG, R, FULL>(K, c, step, call, k, np_, n, v0 + cs, st,
@@ -432,7 +432,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
     if (n < 2) continue;
     if (!all) {  // skip cells without events quickly
       bool any = false;
-      for (int e = 0; e < ne; ++e) any |= (L.evt[e] / navg) == ci;
+      for (int e = 0; e < ne; ++e) any |= L.evc[e] == ci;
       if (!any) continue;
     }
     cell_outcomes<SIG, R, FULL>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, stu, L,
