@@ -163,6 +163,8 @@ SimConst derive(const pic_problem* p, const pic_discretization* d, uint64_t seed
   K.navg = d->n_avg;
   K.np = d->n_particles;
   K.nn = d->ncell[0] * d->ncell[1] * d->ncell[2];
+  K.div_x = div_magic((uint32_t)d->ncell[0]);
+  K.div_xy = div_magic((uint32_t)(d->ncell[0] * d->ncell[1]));
   K.seed = seed;
   K.rep = rep;
   for (int k = 0; k < 3; ++k) {

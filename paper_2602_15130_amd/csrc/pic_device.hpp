@@ -12,6 +12,27 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr float kPiF = 3.14159265358979323846f;
 
 // Everything a kernel needs to know about the problem, derived once on the host.
+// Unsigned division by a divisor d >= 1 fixed for the whole run, as one
+// multiply-high and a shift (Granlund and Montgomery, PLDI 1994, the
+// round-up multiplier): with s = ceil(log2 d) and
+// m = floor(2^32 (2^s - d) / d) + 1, n / d = (mulhi(n, m) + n) >> s for
+// every 32-bit n when the sum is formed in 64 bits.
+struct DivMagic {
+  uint32_t m, s;
+};
+
+__host__ __device__ inline DivMagic div_magic(uint32_t d) {
+  uint32_t s = 0;
+  while ((uint64_t(1) << s) < d) ++s;
+  const uint64_t m = (((uint64_t(1) << s) - d) << 32) / d + 1;
+  return {(uint32_t)m, s};
+}
+
+__host__ __device__ inline uint32_t div_by(DivMagic q, uint32_t n) {
+  const uint64_t hi = ((uint64_t)n * q.m) >> 32;
+  return (uint32_t)((hi + n) >> q.s);
+}
+
 struct SimConst {
   int family;          // 0 paper (Sec. 5.2), 1 configuration family
   int sigma_model;     // 0 polynomial (eq. sigma_ms), 1 variable hard sphere
@@ -19,6 +40,7 @@ struct SimConst {
   int collisions, isolate, navg;
   int nc[3];
   int nn;              // nodes = cells
+  DivMagic div_x, div_xy;  // division by nc[0] and by nc[0] nc[1]
   int64_t np;
   uint64_t seed;
   uint32_t rep;

@@ -374,10 +374,13 @@ __global__ void __launch_bounds__(kBlock) k_deposit_moments_f64(SimConst K, cons
   for (int k = 0; k < 8; ++k) mom[(int64_t)k * K.nn + c] = m[k];
 }
 
+// Node (= cell) index n = i + nc0 (j + nc1 k) split into its coordinates.
 __device__ inline void node_coords(const SimConst& K, int n, int& i, int& j, int& k) {
-  i = n % K.nc[0];
-  j = (n / K.nc[0]) % K.nc[1];
-  k = n / (K.nc[0] * K.nc[1]);
+  const int a = (int)div_by(K.div_x, (uint32_t)n);   // j + nc1 k
+  const int b = (int)div_by(K.div_xy, (uint32_t)n);  // k
+  i = n - a * K.nc[0];
+  j = a - b * K.nc[1];
+  k = b;
 }
 
 // Manufactured part of eq. poisson_mms at node (i, j, k): m = lap phi^M, plus

@@ -322,7 +322,8 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
 
   auto kick = [&](int j, const float amp[3], bool coll_on) {
     int c = tk[j];
-    int ci = c % K.nc[0], cj = (c / K.nc[0]) % K.nc[1], ck = c / (K.nc[0] * K.nc[1]);
+    int ci, cj, ck;
+    node_coords(K, c, ci, cj, ck);
     float o[3] = {to[j], to[st + j], to[2 * st + j]};
     float ep[3], em[3];
     gather_mixed(K, E32, ci, cj, ck, o, ep);
@@ -384,7 +385,8 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       int p = s0 + j;
       kick(j, M.emA, K.collisions != 0);
       int c = tk[j];
-      int cc[3] = {c % K.nc[0], (c / K.nc[0]) % K.nc[1], c / (K.nc[0] * K.nc[1])};
+      int cc[3];
+      node_coords(K, c, cc[0], cc[1], cc[2]);
       float on[3];
       for (int d = 0; d < 3; ++d) {
         // x += dt (v - v^M) in cell units; v^M = vbar a (time independent)
@@ -428,7 +430,8 @@ __global__ void __launch_bounds__(kBlock) k_export_mixed(SimConst K, const int* 
   int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (p >= K.np) return;
   int c = key[p];
-  int cc[3] = {c % K.nc[0], (c / K.nc[0]) % K.nc[1], c / (K.nc[0] * K.nc[1])};
+  int cc[3];
+  node_coords(K, c, cc[0], cc[1], cc[2]);
   for (int d = 0; d < 3; ++d) {
     if (x) x[d * K.np + p] = ((double)cc[d] + (double)off[d * K.np + p]) * K.h[d];
     if (v) v[d * K.np + p] = (double)vf[d * K.np + p];
@@ -448,7 +451,8 @@ __global__ void __launch_bounds__(kBlock) k_err_particles_mixed(SimConst K, doub
     double xi[6], xm[3], a[3];
     init_uniforms(K, id[i], xi);
     int c = key[i];
-    int cc[3] = {c % K.nc[0], (c / K.nc[0]) % K.nc[1], c / (K.nc[0] * K.nc[1])};
+    int cc[3];
+    node_coords(K, c, cc[0], cc[1], cc[2]);
     double xp[3];
     for (int d = 0; d < 3; ++d) xp[d] = ((double)cc[d] + (double)off[d * K.np + i]) * K.h[d];
     manufactured_position(K, xi, t, xp, xm);
