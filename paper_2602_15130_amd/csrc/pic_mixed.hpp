@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
   __shared__ float lv0[3 * kLdsSlots], lD[3 * kLdsSlots], loff[3 * kLdsSlots],
       lash[3 * kLdsSlots];
   __shared__ int lkey[kLdsSlots], lcn[kLdsSlots];
-  __shared__ CollideLds<float> cl;
+  __shared__ CollideLds<float, 2, 128> cl;  // both calls of the pass drawn up front
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;
@@ -300,6 +300,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
   const float navg_f = (float)K.navg;
   const float inv_navg = 1.0f / navg_f;  // exact for a power-of-two N_avg
 
+  if (K.collisions && !(a.mode & kCollideOnly)) tile_clear(ns, st, D, cl);
   for (int j = tid; j < ns; j += kTileThreads) {
     const int p = s0 + j;
     for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + p];
@@ -335,7 +336,10 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       float I[3] = {0.0f, 0.0f, 0.0f};
       float coef = M.src_w * (float)(n - 1);
       if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
-      for (int d = 0; d < 3; ++d) coll[d] = D[d * st + j] * inv_navg - ((n >= 2) ? coef * I[d] : 0.0f);
+      for (int d = 0; d < 3; ++d) {
+        coll[d] = D[d * st + j] * inv_navg - ((n >= 2) ? coef * I[d] : 0.0f);
+        D[d * st + j] = 0.0f;  // cleared for the next call (a barrier follows every kick)
+      }
     }
     for (int d = 0; d < 3; ++d) {
       float acc = M.dtqm * (ep[d] - em[d]);
@@ -360,11 +364,13 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     return;
   }
 
+  if (K.collisions) tile_draw_pass(K, a, c0, ncells, cl);
   if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
     if (K.collisions)
-      tile_collide<SIG, float, FULL>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+      tile_run<SIG, float, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                NP, cl);
     for (int j = tid; j < ns; j += kTileThreads) kick(j, M.emB, K.collisions != 0);
+    if (tid == 0) cl.pool_n = 0;
     __syncthreads();
     if (!(a.mode & kDoA)) {
       for (int j = tid; j < ns; j += kTileThreads)
@@ -375,7 +381,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
 
   // call A at t^{na}, first half kick, drift to t^{na+1}
   if (K.collisions)
-    tile_collide<SIG, float, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+    tile_run<SIG, float, FULL>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
                              st, NP, cl);
   for (int base = 0; base < ns; base += kTileThreads) {
     int j = base + tid;
@@ -404,8 +410,9 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
           o = 0.0f;
           shift = 0;
         }
-        int nd = K.nc[d];
-        int ni = cc[d] + (shift % nd);
+        const int nd = K.nc[d];
+        if (shift >= nd || shift <= -nd) shift %= nd;  // more than a box length: rare
+        int ni = cc[d] + shift;
         ni = ni < 0 ? ni + nd : (ni >= nd ? ni - nd : ni);
         cc[d] = ni;
         on[d] = o;

@@ -26,7 +26,6 @@
 
 namespace pic {
 
-constexpr int kMaxEvents = 192;   // (cell, outcome) lanes with pairs per tile
 constexpr int kSmallPairs = 4;    // outcomes with at most this many pairs run one per lane
 constexpr int kPool = 64;         // velocity-change records of those outcomes per tile
 
@@ -34,13 +33,17 @@ constexpr int kPool = 64;         // velocity-change records of those outcomes p
 // with candidate pairs), their pair counts, and the velocity changes of the
 // outcomes run one per lane (record start | count << 16, or -1 when the
 // outcome is left to its cell's thread).
-template <class R>
+// NL event lists of CAP (cell, outcome) lanes with pairs each: one list when
+// every call draws just before it runs, two when both calls of a pass draw at
+// the start of the tile (list 0 call B, list 1 call A).
+template <class R, int NL, int CAP>
 struct CollideLds {
-  int evc[kMaxEvents];   // tile-local cell of the event
-  int evk[kMaxEvents];   // its outcome
-  int evn[kMaxEvents];
-  int evp[kMaxEvents];
-  int n_evt, overflow, pool_n;
+  static constexpr int kLists = NL, kCap = CAP;
+  int evc[NL][CAP];  // tile-local cell of the event
+  int evk[NL][CAP];  // its outcome
+  int evn[NL][CAP];  // its N_pairs
+  int evp[CAP];      // records of the list being run
+  int n_evt[NL], overflow[NL], pool_n;
   int pslot[kPool];
   R pdv[3 * kPool];
 };
@@ -264,11 +267,11 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
 // is read).  Outcomes already run by a lane contribute their stored changes;
 // the others run here.  Only the particles an outcome changed contribute to
 // the sum; the others would add exact zeros.
-template <int SIG, class R, bool FULL>
+template <int SIG, class R, bool FULL, class Lds>
 __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
                                      int c, int ci, int cs, int n, const R* v0, R* u, R* D,
                                      int* mark, int* tl, int tagbase, int st, int stu,
-                                     const CollideLds<R>& L, int ne, bool all,
+                                     const Lds& L, int li, int ne, bool all,
                                      unsigned long long& acc, unsigned long long& gmx) {
   const int navg = K.navg;
   int last = -1;
@@ -280,7 +283,7 @@ __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int c
     } else {  // next event of this cell in increasing outcome order
       k = navg;
       for (int e = 0; e < ne; ++e) {
-        const int eci = L.evc[e], ek = L.evk[e];
+        const int eci = L.evc[li][e], ek = L.evk[li][e];
         if (eci == ci && ek > last && ek < k) {
           k = ek;
           ev = e;
@@ -297,7 +300,7 @@ __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int c
       }
       continue;
     }
-    int64_t np_ = ev >= 0 ? (int64_t)L.evn[ev] : npairs_of(K, c, step, call, k, n, a.flags);
+    int64_t np_ = ev >= 0 ? (int64_t)L.evn[li][ev] : npairs_of(K, c, step, call, k, n, a.flags);
     if (np_ <= 0) continue;
     if (!marks_clear) {
       for (int t = 0; t < n; ++t) mark[cs + t] = 0;
@@ -355,57 +358,65 @@ __global__ void __launch_bounds__(kBlock) k_collide_big(SimConst K, int call, in
   if (gmx) atomicAdd(&counters[kCntGmax], gmx);
 }
 
-// Collision call over the tile: v0 (pre-collision velocities, tile slots,
-// stride st) -> D = N_avg <dv> per slot.  u (stride stu), mark and tl are
-// scratch of the tile's slots for the outcomes a cell thread runs itself; a
-// cell's marks are cleared before its first such outcome in a call.
-template <int SIG, class R, bool FULL>
-__device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
-                                    int64_t step, int c0, int ncells, int s0, int ns,
-                                    const R* v0, R* u, R* D, int* mark, int* tl, int tagbase,
-                                    int st, int stu, CollideLds<R>& L) {
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    L.n_evt = 0;
-    L.overflow = 0;
-    L.pool_n = 0;
-  }
-  for (int j = tid; j < ns; j += kTileThreads) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
-  __syncthreads();
+// Collision calls over a tile, in two steps.  tile_draw finds the events
+// ((cell, outcome) with candidate pairs) of up to two calls at once: lists
+// [lo, hi) of calls[] / steps[] (list 0 call B, list 1 call A of a pass), one
+// random block per four outcomes; N_pairs depends only on the cell counts, so
+// both calls of a pass draw before either runs.  The caller clears n_evt and
+// overflow of those lists before a barrier, and synchronises after.
+template <class Lds>
+__device__ inline void tile_draw(const SimConst& K, const PartArgs& a, int lo, int hi,
+                                 const int calls[2], const int64_t steps[2], int c0, int ncells,
+                                 Lds& L) {
   const int navg = K.navg;
   const int ngroups = (navg + 3) >> 2;
   const int64_t lanes = (int64_t)ncells * ngroups;
-  // (1) N_pairs of every (cell, outcome), one random block per four outcomes
-  for (int64_t l = tid; l < lanes; l += kTileThreads) {
-    int ci = (int)(l / ngroups), g = (int)(l - (int64_t)ci * ngroups);
+  for (int64_t l = threadIdx.x; l < (hi - lo) * lanes; l += kTileThreads) {
+    const int li = lo + (l >= lanes ? 1 : 0);
+    const int64_t r = l - (li - lo) * lanes;
+    int ci = (int)(r / ngroups), g = (int)(r - (int64_t)ci * ngroups);
     int c = c0 + ci;
     int n = a.cstart[c + 1] - a.cstart[c];
     if (n < 2) continue;
-    U64x4 w = npairs_block(K, c, step, call, g);
+    U64x4 w = npairs_block(K, c, steps[li], calls[li], g);
     for (int kk = 0; kk < 4; ++kk) {
       int k = 4 * g + kk;
       if (k >= navg) break;
       int64_t np_ = npairs_from(K, n, w.w[kk], a.flags);
       if (np_ > 0) {
-        int e = atomicAdd(&L.n_evt, 1);
-        if (e < kMaxEvents) {
-          L.evc[e] = ci;
-          L.evk[e] = k;
-          L.evn[e] = (int)np_;
+        int e = atomicAdd(&L.n_evt[li], 1);
+        if (e < Lds::kCap) {
+          L.evc[li][e] = ci;
+          L.evk[li][e] = k;
+          L.evn[li][e] = (int)np_;
         } else {
-          L.overflow = 1;
+          L.overflow[li] = 1;
         }
       }
     }
   }
-  __syncthreads();
-  const int ne = min(L.n_evt, kMaxEvents);
-  const bool all = L.overflow != 0;
+}
+
+// tile_run: the drawn call of list li: v0 (pre-collision velocities, tile
+// slots, stride st) -> D = N_avg <dv> per slot.  u (stride stu), mark and tl
+// are scratch of the tile's slots for the outcomes a cell thread runs itself;
+// a cell's marks are cleared before its first such outcome in a call.  The
+// caller has zeroed D[0, ns) and the record pool count before a barrier (each
+// block-wide barrier costs the whole tile its slowest wave, so none is spent
+// on that here).
+template <int SIG, class R, bool FULL, class Lds>
+__device__ inline void tile_run(const SimConst& K, const PartArgs& a, int li, int call,
+                                int64_t step, int c0, int ncells, int s0, int ns, const R* v0,
+                                R* u, R* D, int* mark, int* tl, int tagbase, int st, int stu,
+                                Lds& L) {
+  const int tid = threadIdx.x;
+  const int ne = min(L.n_evt[li], Lds::kCap);
+  const bool all = L.overflow[li] != 0;
   unsigned long long acc = 0, gmx = 0;
-  // (2) small outcomes, one per lane, into the record pool
+  // small outcomes, one per lane, into the record pool
   if (!all) {
     for (int e = tid; e < ne; e += kTileThreads) {
-      int np_ = L.evn[e];
+      int np_ = L.evn[li][e];
       int start = -1;
       if (np_ <= kSmallPairs) {
         start = atomicAdd(&L.pool_n, 2 * np_);
@@ -415,7 +426,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
         L.evp[e] = -1;
         continue;
       }
-      int ci = L.evc[e], k = L.evk[e];
+      int ci = L.evc[li][e], k = L.evk[li][e];
       int c = c0 + ci;
       int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
       int cnt = ntc_outcome_small<SIG, R, FULL>(K, c, step, call, k, np_, n, v0 + cs, st,
@@ -425,21 +436,67 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
     }
     __syncthreads();
   }
-  // (3) per cell, in increasing outcome order
+  // per cell, in increasing outcome order
   for (int ci = tid; ci < ncells; ci += kTileThreads) {
     int c = c0 + ci;
     int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
     if (n < 2) continue;
     if (!all) {  // skip cells without events quickly
       bool any = false;
-      for (int e = 0; e < ne; ++e) any |= L.evc[e] == ci;
+      for (int e = 0; e < ne; ++e) any |= L.evc[li][e] == ci;
       if (!any) continue;
     }
     cell_outcomes<SIG, R, FULL>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, stu, L,
-                          ne, all, acc, gmx);
+                          li, ne, all, acc, gmx);
   }
   if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
   if (gmx) atomicAdd(&a.counters[kCntGmax], gmx);
+  __syncthreads();
+}
+
+// Start-of-tile state of a pass's collisions: both lists empty, no records,
+// D = 0 (before the barrier that ends the tile's loads).
+template <class R, class Lds>
+__device__ inline void tile_clear(int ns, int st, R* D, Lds& L) {
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < Lds::kLists; ++i) L.n_evt[i] = L.overflow[i] = 0;
+    L.pool_n = 0;
+  }
+  for (int j = threadIdx.x; j < ns; j += kTileThreads) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
+}
+
+// One collision call over the tile (draw, then run; list 0).
+template <int SIG, class R, bool FULL, class Lds>
+__device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
+                                    int64_t step, int c0, int ncells, int s0, int ns,
+                                    const R* v0, R* u, R* D, int* mark, int* tl, int tagbase,
+                                    int st, int stu, Lds& L) {
+  if (threadIdx.x == 0) {
+    L.n_evt[0] = 0;
+    L.overflow[0] = 0;
+    L.pool_n = 0;
+  }
+  for (int j = threadIdx.x; j < ns; j += kTileThreads) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
+  __syncthreads();
+  const int calls[2] = {call, call};
+  const int64_t steps[2] = {step, step};
+  tile_draw(K, a, 0, 1, calls, steps, c0, ncells, L);
+  __syncthreads();
+  tile_run<SIG, R, FULL>(K, a, 0, call, step, c0, ncells, s0, ns, v0, u, D, mark, tl, tagbase, st,
+                         stu, L);
+}
+
+// The events of the pass's calls (B: list 0, A: list 1), drawn together at
+// the start of a tile; the caller has cleared the counters, the record pool
+// count and D before a barrier (tile_clear).
+template <class Lds>
+__device__ inline void tile_draw_pass(const SimConst& K, const PartArgs& a, int c0, int ncells,
+                                      Lds& L) {
+  static_assert(Lds::kLists == 2, "a pass draws into two lists");
+  const int calls[2] = {a.callB, a.callA};
+  const int64_t steps[2] = {a.nb, a.na};
+  const int lo = (a.mode & kDoB) ? 0 : 1, hi = (a.mode & kDoA) ? 2 : 1;
+  tile_draw(K, a, lo, hi, calls, steps, c0, ncells, L);
   __syncthreads();
 }
 
@@ -568,7 +625,7 @@ template <int FAM, int SIG, bool FULL>
 __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(SimConst K, PartArgs a) {
   // the copy-on-write scratch of outcomes run by a cell thread is global
   __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots];
-  __shared__ CollideLds<double> cl;
+  __shared__ CollideLds<double, 2, 128> cl;  // both calls of the pass drawn up front
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;
@@ -591,6 +648,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
   const double dt = K.dt;
   const double inv_navg_den = (double)K.navg;
 
+  if (K.collisions && !(a.mode & kCollideOnly)) tile_clear(ns, st, D, cl);
   for (int j = tid; j < ns; j += kTileThreads)
     for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
   __syncthreads();
@@ -612,11 +670,12 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
     return;
   }
 
+  if (K.collisions) tile_draw_pass(K, a, c0, ncells, cl);
   if (a.mode & kDoB) {
     // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
     const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
     if (K.collisions)
-      tile_collide<SIG, double, FULL>(K, a, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+      tile_run<SIG, double, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                 NP, cl);
     for (int j = tid; j < ns; j += kTileThreads) {
       int p = s0 + j;
@@ -629,10 +688,14 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
       double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
       double Dj[3] = {0.0, 0.0, 0.0};
       if (K.collisions)
-        for (int d = 0; d < 3; ++d) Dj[d] = D[d * st + j] / inv_navg_den;
+        for (int d = 0; d < 3; ++d) {
+          Dj[d] = D[d * st + j] / inv_navg_den;
+          D[d * st + j] = 0.0;  // cleared for call A (the barrier below orders it)
+        }
       half_kick_f64<FAM, SIG>(K, xp, ep, t1, th, t1, th, aa, n, Dj, vp);
       for (int d = 0; d < 3; ++d) v0[d * st + j] = vp[d];
     }
+    if (tid == 0) cl.pool_n = 0;
     __syncthreads();
     if (!(a.mode & kDoA)) {
       for (int j = tid; j < ns; j += kTileThreads)
@@ -644,7 +707,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
   // collision call A at t^{na} on v^{na}, first half kick, drift to t^{na+1}
   const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
   if (K.collisions)
-    tile_collide<SIG, double, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+    tile_run<SIG, double, FULL>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
                               st, NP, cl);
   for (int base = 0; base < ns; base += kTileThreads) {
     int j = base + tid;
