@@ -283,6 +283,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     sh_i[1] = min(a.tile_c0[blockIdx.x + 1], K.nn);
     sh_i[2] = a.tile_s0[blockIdx.x];
     sh_i[3] = a.tile_s0[blockIdx.x + 1];
+    tile_lists_clear(cl);
   }
   __syncthreads();
   const int c0 = sh_i[0], ncells = max(sh_i[1] - sh_i[0], 0), s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
@@ -300,7 +301,8 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
   const float navg_f = (float)K.navg;
   const float inv_navg = 1.0f / navg_f;  // exact for a power-of-two N_avg
 
-  if (K.collisions && !(a.mode & kCollideOnly)) tile_clear(ns, st, D, cl);
+  const bool pass_coll = K.collisions && !(a.mode & kCollideOnly);
+  if (pass_coll) tile_zero_D(ns, st, D);
   for (int j = tid; j < ns; j += kTileThreads) {
     const int p = s0 + j;
     for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + p];
@@ -314,6 +316,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       lcn[j] = a.cstart[c + 1] - a.cstart[c];
     }
   }
+  if (pass_coll) tile_draw_pass(K, a, c0, ncells, cl);
   __syncthreads();
   auto cell_count = [&](int j) {
     if (lds) return lcn[j];
@@ -364,7 +367,6 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     return;
   }
 
-  if (K.collisions) tile_draw_pass(K, a, c0, ncells, cl);
   if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
     if (K.collisions)
       tile_run<SIG, float, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,

@@ -454,14 +454,17 @@ __device__ inline void tile_run(const SimConst& K, const PartArgs& a, int li, in
   __syncthreads();
 }
 
-// Start-of-tile state of a pass's collisions: both lists empty, no records,
-// D = 0 (before the barrier that ends the tile's loads).
-template <class R, class Lds>
-__device__ inline void tile_clear(int ns, int st, R* D, Lds& L) {
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < Lds::kLists; ++i) L.n_evt[i] = L.overflow[i] = 0;
-    L.pool_n = 0;
-  }
+// Start-of-tile state of a pass's collisions: both event lists empty and no
+// records (one thread, before the kernel's first barrier), D = 0 (before the
+// barrier that ends the tile's loads).
+template <class Lds>
+__device__ inline void tile_lists_clear(Lds& L) {
+  for (int i = 0; i < Lds::kLists; ++i) L.n_evt[i] = L.overflow[i] = 0;
+  L.pool_n = 0;
+}
+
+template <class R>
+__device__ inline void tile_zero_D(int ns, int st, R* D) {
   for (int j = threadIdx.x; j < ns; j += kTileThreads) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
 }
 
@@ -487,8 +490,10 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
 }
 
 // The events of the pass's calls (B: list 0, A: list 1), drawn together at
-// the start of a tile; the caller has cleared the counters, the record pool
-// count and D before a barrier (tile_clear).
+// the start of a tile, beside the loads of the tile's state (the draw reads
+// only the cell starts, so its random blocks overlap the loads' latency); the
+// lists were cleared before the kernel's first barrier, and the barrier that
+// ends the loads publishes them.
 template <class Lds>
 __device__ inline void tile_draw_pass(const SimConst& K, const PartArgs& a, int c0, int ncells,
                                       Lds& L) {
@@ -497,7 +502,6 @@ __device__ inline void tile_draw_pass(const SimConst& K, const PartArgs& a, int 
   const int64_t steps[2] = {a.nb, a.na};
   const int lo = (a.mode & kDoB) ? 0 : 1, hi = (a.mode & kDoA) ? 2 : 1;
   tile_draw(K, a, lo, hi, calls, steps, c0, ncells, L);
-  __syncthreads();
 }
 
 // Tile bounds of block b: first cell, cell count, first particle, particle count.
@@ -618,9 +622,9 @@ __device__ inline void half_kick_f64(const SimConst& K, const double xp[3], cons
   }
 }
 
-// LDS (three tile arrays) allows four workgroups per CU; registers are capped
-// to match (four waves per SIMD), accepting a few spills: the pass is latency
-// bound and gains more from resident waves than it loses to spill traffic.
+// Registers are capped for three resident waves per SIMD (168 VGPRs), accepting
+// a few spills: the pass is latency bound and gains more from resident waves
+// than it loses to spill traffic.
 template <int FAM, int SIG, bool FULL>
 __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(SimConst K, PartArgs a) {
   // the copy-on-write scratch of outcomes run by a cell thread is global
@@ -634,6 +638,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
     sh_i[1] = min(a.tile_c0[blockIdx.x + 1], K.nn);
     sh_i[2] = a.tile_s0[blockIdx.x];
     sh_i[3] = a.tile_s0[blockIdx.x + 1];
+    tile_lists_clear(cl);
   }
   __syncthreads();
   const int c0 = sh_i[0], ncells = max(sh_i[1] - sh_i[0], 0), s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
@@ -648,9 +653,11 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
   const double dt = K.dt;
   const double inv_navg_den = (double)K.navg;
 
-  if (K.collisions && !(a.mode & kCollideOnly)) tile_clear(ns, st, D, cl);
+  const bool pass_coll = K.collisions && !(a.mode & kCollideOnly);
+  if (pass_coll) tile_zero_D(ns, st, D);
   for (int j = tid; j < ns; j += kTileThreads)
     for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
+  if (pass_coll) tile_draw_pass(K, a, c0, ncells, cl);
   __syncthreads();
 
   if (a.mode & kCollideOnly) {
@@ -670,7 +677,6 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
     return;
   }
 
-  if (K.collisions) tile_draw_pass(K, a, c0, ncells, cl);
   if (a.mode & kDoB) {
     // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
     const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
