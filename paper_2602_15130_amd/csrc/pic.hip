@@ -517,7 +517,9 @@ int field_solve(pic_ctx* c, double t) {
     const LowArgs& L = c->low;
     const int planes = L.slabs * K.nc[2];
     k_low_project<<<planes, kLowThreads, c->low_lds[0], c->stream>>>(K, L, c->b, c->phi);
-    k_low_solve<<<L.m[1], kLowThreads, c->low_lds[1], c->stream>>>(K, L);
+    // four x chunks per y mode (the LDS sized for all nx columns bounds a chunk's)
+    const dim3 gsolve((unsigned)L.m[1], (unsigned)std::min(4, K.nc[0]));
+    k_low_solve<<<gsolve, kLowThreads, c->low_lds[1], c->stream>>>(K, L);
     k_low_correct<<<planes, kLowThreads, c->low_lds[2], c->stream>>>(K, L, c->phi);
     LAUNCH_CHECK(c, "low-mode solve");
   }

@@ -144,16 +144,21 @@ __global__ void __launch_bounds__(kLowThreads) k_low_project(SimConst K, LowArgs
 // scaled by 1 / (eigenvalue * squared norm) (the constant mode is left alone),
 // then the back-transforms along x and z:
 //   d1[c][i] = sum_a c'[a][b][c] phi_a(i),  e[k][b][i] = sum_c phi_c(k) d1[c][i].
+// Workgroup (bb, q): y mode bb, x columns [i0, i0 + ni) of chunk q of
+// gridDim.y: the chunks of one mode repeat its small coefficient step, and the
+// back-transforms (most of the LDS operand traffic) spread over more CUs.
 __global__ void __launch_bounds__(kLowThreads) k_low_solve(SimConst K, LowArgs L) {
   extern __shared__ double lds[];
   const int nx = K.nc[0], nz = K.nc[2];
   const int m0 = L.m[0], m1 = L.m[1], m2 = L.m[2];
   const int bb = blockIdx.x;
+  const int i0 = (int)(((int64_t)nx * blockIdx.y) / gridDim.y);
+  const int ni = (int)(((int64_t)nx * (blockIdx.y + 1)) / gridDim.y) - i0;
   const int pz = nz + 1;
   double* u = lds;                 // [m0][nz], then d1 [m2][nx]
   double* phz = u + max(m0 * nz, m2 * nx);  // [m2][nz + 1]
   double* cf = phz + m2 * pz;      // [m0][m2]
-  double* phx = cf + m0 * m2;      // [m0][nx]
+  double* phx = cf + m0 * m2;      // [m0][ni]: columns i0 .. i0 + ni - 1
 #pragma unroll 4
   for (int t = threadIdx.x; t < m0 * nz; t += kLowThreads) {
     const int a = t / nz, k = t % nz;
@@ -165,8 +170,8 @@ __global__ void __launch_bounds__(kLowThreads) k_low_solve(SimConst K, LowArgs L
   for (int t = threadIdx.x; t < m2 * nz; t += kLowThreads)
     phz[(t / nz) * pz + t % nz] = L.tab[(2 * kLowMaxM + t / nz) * L.nmax + t % nz];
 #pragma unroll 4
-  for (int t = threadIdx.x; t < m0 * nx; t += kLowThreads)
-    phx[t] = L.tab[(t / nx) * L.nmax + t % nx];
+  for (int t = threadIdx.x; t < m0 * ni; t += kLowThreads)
+    phx[t] = L.tab[(t / ni) * L.nmax + i0 + t % ni];
   __syncthreads();
   for (int t = threadIdx.x; t < m0 * m2; t += kLowThreads) {
     const int a = t / m2, cc = t % m2;
@@ -182,15 +187,15 @@ __global__ void __launch_bounds__(kLowThreads) k_low_solve(SimConst K, LowArgs L
     cf[t] = lam > 0.0 ? acc / (lam * nrm) : 0.0;
   }
   __syncthreads();
-  double* d1 = u;  // the projections are consumed
-  for (int t = threadIdx.x; t < m2 * nx; t += kLowThreads) {
-    const int cc = t / nx, i = t % nx;
-    d1[t] = low_dot(cf + cc, m2, phx + i, nx, m0);
+  double* d1 = u;  // the projections are consumed; [m2][ni]
+  for (int t = threadIdx.x; t < m2 * ni; t += kLowThreads) {
+    const int cc = t / ni, i = t % ni;
+    d1[t] = low_dot(cf + cc, m2, phx + i, ni, m0);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < nz * nx; t += kLowThreads) {
-    const int k = t / nx, i = t % nx;
-    L.e[((int64_t)k * m1 + bb) * nx + i] = low_dot(phz + k, pz, d1 + i, nx, m2);
+  for (int t = threadIdx.x; t < nz * ni; t += kLowThreads) {
+    const int k = t / ni, i = t % ni;
+    L.e[((int64_t)k * m1 + bb) * nx + i0 + i] = low_dot(phz + k, pz, d1 + i, ni, m2);
   }
 }
 
