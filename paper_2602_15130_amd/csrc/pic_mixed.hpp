@@ -324,7 +324,8 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     return a.cstart[c + 1] - a.cstart[c];
   };
 
-  auto kick = [&](int j, const float amp[3], bool coll_on) {
+  // Field part of a half kick: dt q/m (E - E^M) at the particle.
+  auto field_acc = [&](int j, const float amp[3], float acc[3]) {
     int c = tk[j];
     int ci, cj, ck;
     node_coords(K, c, ci, cj, ck);
@@ -332,6 +333,9 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     float ep[3], em[3];
     gather_mixed(K, E32, ci, cj, ck, o, ep);
     EM_mixed(M, ci, cj, ck, o, amp, em);
+    for (int d = 0; d < 3; ++d) acc[d] = M.dtqm * (ep[d] - em[d]);
+  };
+  auto kick_with = [&](int j, const float acc[3], bool coll_on) {
     float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
     float coll[3] = {0.0f, 0.0f, 0.0f};
     if (coll_on) {
@@ -345,11 +349,18 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       }
     }
     for (int d = 0; d < 3; ++d) {
-      float acc = M.dtqm * (ep[d] - em[d]);
-      vp[d] = vp[d] + 0.5f * (acc + coll[d]);
+      vp[d] = vp[d] + 0.5f * (acc[d] + coll[d]);
       v0[d * st + j] = vp[d];
     }
   };
+  // With both halves in one pass, kick B (end of step n) and kick A (start of
+  // step n + 1) are at the same time t^{n+1} and position (no drift between
+  // them, one field solve before the pass), so the field part is computed once
+  // and kept per slot: bitwise what kick A would compute again.
+  constexpr int kPer = (kLdsSlots + kTileThreads - 1) / kTileThreads;
+  const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 &&
+                     ns <= kPer * kTileThreads;
+  float accs[kPer][3];
 
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, float, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
@@ -371,7 +382,22 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     if (K.collisions)
       tile_run<SIG, float, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                NP, cl);
-    for (int j = tid; j < ns; j += kTileThreads) kick(j, M.emB, K.collisions != 0);
+    if (reuse) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int j = tid + q * kTileThreads;
+        if (j < ns) {
+          field_acc(j, M.emB, accs[q]);
+          kick_with(j, accs[q], K.collisions != 0);
+        }
+      }
+    } else {
+      for (int j = tid; j < ns; j += kTileThreads) {
+        float acc[3];
+        field_acc(j, M.emB, acc);
+        kick_with(j, acc, K.collisions != 0);
+      }
+    }
     if (tid == 0) cl.pool_n = 0;
     __syncthreads();
     if (!(a.mode & kDoA)) {
@@ -391,7 +417,16 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     int kk = 0;
     if (valid) {
       int p = s0 + j;
-      kick(j, M.emA, K.collisions != 0);
+      float acc[3];
+      if (reuse) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+          if (base == q * kTileThreads)
+            for (int d = 0; d < 3; ++d) acc[d] = accs[q][d];
+      } else {
+        field_acc(j, M.emA, acc);
+      }
+      kick_with(j, acc, K.collisions != 0);
       int c = tk[j];
       int cc[3];
       node_coords(K, c, cc[0], cc[1], cc[2]);
