@@ -592,11 +592,9 @@ __device__ inline void gather_f64(const SimConst& K, const double* E, const doub
 // Half kick of one particle (eq. velocity_verlet): v += (acc + D - S)/2 + h.
 // FAM: 0 paper family (time-dependent velocity shape), 1 configuration family.
 template <int FAM, int SIG>
-__device__ inline void half_kick_f64(const SimConst& K, const double xp[3], const double ep[3],
-                                     double t, double t_from, double t_to, double t_src,
+__device__ inline void half_kick_f64(const SimConst& K, const double acc[3], double t,
+                                     double t_from, double t_to, double t_src,
                                      const double aa[3], int n, const double D[3], double v[3]) {
-  double em[3];
-  EM(K, xp, t, em);
   double h[3] = {0.0, 0.0, 0.0};
   if (FAM == 0) {
     double va[3], vb[3], da[3], db[3];
@@ -616,10 +614,15 @@ __device__ inline void half_kick_f64(const SimConst& K, const double xp[3], cons
     if (n >= 2) source_integral_t<SIG>(K, v, t_src, I);
     for (int d = 0; d < 3; ++d) coll[d] = D[d] - ((n >= 2) ? coef * I[d] : 0.0);
   }
-  for (int d = 0; d < 3; ++d) {
-    double acc = K.dt * K.qm * (ep[d] - em[d]);
-    v[d] = v[d] + 0.5 * (acc + coll[d]) + h[d];
-  }
+  for (int d = 0; d < 3; ++d) v[d] = v[d] + 0.5 * (acc[d] + coll[d]) + h[d];
+}
+
+// Field part of a half kick at time t: dt q/m (E - E^M) at the particle.
+__device__ inline void field_acc_f64(const SimConst& K, const double xp[3], const double ep[3],
+                                     double t, double acc[3]) {
+  double em[3];
+  EM(K, xp, t, em);
+  for (int d = 0; d < 3; ++d) acc[d] = K.dt * K.qm * (ep[d] - em[d]);
 }
 
 // Registers are capped for three resident waves per SIMD (168 VGPRs), accepting
@@ -677,17 +680,31 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
     return;
   }
 
+  // With both halves in one pass, kick B (end of step n) and kick A (start of
+  // step n + 1) are at the same time t^{n+1} and position, so the field part
+  // of the acceleration is computed once and kept per slot (bitwise the same).
+  constexpr int kPer = (kLdsSlots + kTileThreads - 1) / kTileThreads;
+  const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 &&
+                     ns <= kPer * kTileThreads;
+  double accs[kPer][3];
   if (a.mode & kDoB) {
     // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
     const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
     if (K.collisions)
       tile_run<SIG, double, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                 NP, cl);
-    for (int j = tid; j < ns; j += kTileThreads) {
+#pragma unroll
+    for (int j = tid, q = 0; j < ns; j += kTileThreads, ++q) {
       int p = s0 + j;
-      double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
+      double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3], acc[3];
       int cc[3];
       gather_f64(K, a.E, xp, ep, cc);
+      field_acc_f64(K, xp, ep, t1, acc);
+      if (reuse)
+#pragma unroll
+        for (int r = 0; r < kPer; ++r)
+          if (r == q)
+            for (int d = 0; d < 3; ++d) accs[r][d] = acc[d];
       int c = a.key[p];
       int n = a.cstart[c + 1] - a.cstart[c];
       double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
@@ -698,7 +715,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
           Dj[d] = D[d * st + j] / inv_navg_den;
           D[d * st + j] = 0.0;  // cleared for call A (the barrier below orders it)
         }
-      half_kick_f64<FAM, SIG>(K, xp, ep, t1, th, t1, th, aa, n, Dj, vp);
+      half_kick_f64<FAM, SIG>(K, acc, t1, th, t1, th, aa, n, Dj, vp);
       for (int d = 0; d < 3; ++d) v0[d * st + j] = vp[d];
     }
     if (tid == 0) cl.pool_n = 0;
@@ -721,9 +738,18 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
     int kk = 0;
     if (valid) {
       int p = s0 + j;
-      double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
-      int cc[3];
-      gather_f64(K, a.E, xp, ep, cc);
+      double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, acc[3];
+      if (reuse) {
+#pragma unroll
+        for (int r = 0; r < kPer; ++r)
+          if (base == r * kTileThreads)
+            for (int d = 0; d < 3; ++d) acc[d] = accs[r][d];
+      } else {
+        double ep[3];
+        int cc[3];
+        gather_f64(K, a.E, xp, ep, cc);
+        field_acc_f64(K, xp, ep, t0, acc);
+      }
       int c = a.key[p];
       int n = a.cstart[c + 1] - a.cstart[c];
       double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
@@ -731,7 +757,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
       double Dj[3] = {0.0, 0.0, 0.0};
       if (K.collisions)
         for (int d = 0; d < 3; ++d) Dj[d] = D[d * st + j] / inv_navg_den;
-      half_kick_f64<FAM, SIG>(K, xp, ep, t0, t0, th, t0, aa, n, Dj, vp);
+      half_kick_f64<FAM, SIG>(K, acc, t0, t0, th, t0, aa, n, Dj, vp);
       // drift (eq. velocity_verlet) with the manufactured term
       double vm[3], vdm[3], h[3] = {0.0, 0.0, 0.0};
       if (FAM == 1) {
