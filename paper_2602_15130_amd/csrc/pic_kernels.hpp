@@ -28,7 +28,7 @@ constexpr int kLdsSlots = PIC_LDS_SLOTS;          // LDS-resident slots per tile
 #define PIC_MIXED_WAVES 6
 #endif
 #ifndef PIC_F64_WAVES
-#define PIC_F64_WAVES 3
+#define PIC_F64_WAVES 4  // also the LDS limit: four 33 KB tiles per CU
 #endif
 
 // Flags raised by kernels and read back at the next synchronising call.

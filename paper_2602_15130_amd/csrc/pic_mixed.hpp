@@ -269,10 +269,12 @@ template <int SIG, bool FULL>
 __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
-  // Tile-resident copies of everything the pass reads per particle; the
-  // copy-on-write scratch of outcomes run by a cell thread is global.
+  // Tile-resident copies of what the pass reads per particle more than once
+  // (the velocity shape is read once, in the drift, straight from memory), and
+  // the field acceleration kept from kick B for kick A; the copy-on-write
+  // scratch of outcomes run by a cell thread is global.
   __shared__ float lv0[3 * kLdsSlots], lD[3 * kLdsSlots], loff[3 * kLdsSlots],
-      lash[3 * kLdsSlots];
+      lacc[3 * kLdsSlots];
   __shared__ int lkey[kLdsSlots], lcn[kLdsSlots];
   __shared__ CollideLds<float, 2, 128> cl;  // both calls of the pass drawn up front
   __shared__ int sh_i[4];
@@ -293,7 +295,6 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
   float* v0 = lds ? lv0 : (float*)a.gv0 + s0;
   float* D = lds ? lD : (float*)a.gD + s0;
   const float* to = lds ? loff : off + s0;   // offsets at the start of the pass
-  const float* ta = lds ? lash : ash + s0;
   const int* tk = lds ? lkey : a.key + s0;   // cells at the start of the pass
   float* u = (float*)a.gu + s0;
   int* mark = a.gmark + s0;
@@ -310,7 +311,6 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       const int c = a.key[p];
       for (int d = 0; d < 3; ++d) {
         loff[d * kLdsSlots + j] = off[(int64_t)d * NP + p];
-        lash[d * kLdsSlots + j] = ash[(int64_t)d * NP + p];
       }
       lkey[j] = c;
       lcn[j] = a.cstart[c + 1] - a.cstart[c];
@@ -356,11 +356,8 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
   // With both halves in one pass, kick B (end of step n) and kick A (start of
   // step n + 1) are at the same time t^{n+1} and position (no drift between
   // them, one field solve before the pass), so the field part is computed once
-  // and kept per slot: bitwise what kick A would compute again.
-  constexpr int kPer = (kLdsSlots + kTileThreads - 1) / kTileThreads;
-  const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 &&
-                     ns <= kPer * kTileThreads;
-  float accs[kPer][3];
+  // and kept per slot in LDS: bitwise what kick A would compute again.
+  const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 && lds;
 
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, float, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
@@ -382,21 +379,12 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     if (K.collisions)
       tile_run<SIG, float, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                NP, cl);
-    if (reuse) {
-#pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const int j = tid + q * kTileThreads;
-        if (j < ns) {
-          field_acc(j, M.emB, accs[q]);
-          kick_with(j, accs[q], K.collisions != 0);
-        }
-      }
-    } else {
-      for (int j = tid; j < ns; j += kTileThreads) {
-        float acc[3];
-        field_acc(j, M.emB, acc);
-        kick_with(j, acc, K.collisions != 0);
-      }
+    for (int j = tid; j < ns; j += kTileThreads) {
+      float acc[3];
+      field_acc(j, M.emB, acc);
+      if (reuse)
+        for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
+      kick_with(j, acc, K.collisions != 0);
     }
     if (tid == 0) cl.pool_n = 0;
     __syncthreads();
@@ -419,10 +407,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       int p = s0 + j;
       float acc[3];
       if (reuse) {
-#pragma unroll
-        for (int q = 0; q < kPer; ++q)
-          if (base == q * kTileThreads)
-            for (int d = 0; d < 3; ++d) acc[d] = accs[q][d];
+        for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
       } else {
         field_acc(j, M.emA, acc);
       }
@@ -433,7 +418,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       float on[3];
       for (int d = 0; d < 3; ++d) {
         // x += dt (v - v^M) in cell units; v^M = vbar a (time independent)
-        float vm = M.vbar * ta[d * st + j];
+        float vm = M.vbar * ash[(int64_t)d * NP + p];
         float o = to[d * st + j] + M.dt * (v0[d * st + j] - vm) * M.inv_h[d];
         float fl = floorf(o);
         o -= fl;

@@ -625,13 +625,13 @@ __device__ inline void field_acc_f64(const SimConst& K, const double xp[3], cons
   for (int d = 0; d < 3; ++d) acc[d] = K.dt * K.qm * (ep[d] - em[d]);
 }
 
-// Registers are capped for three resident waves per SIMD (168 VGPRs), accepting
+// Registers are capped for four resident waves per SIMD (128 VGPRs), accepting
 // a few spills: the pass is latency bound and gains more from resident waves
 // than it loses to spill traffic.
 template <int FAM, int SIG, bool FULL>
 __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(SimConst K, PartArgs a) {
   // the copy-on-write scratch of outcomes run by a cell thread is global
-  __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots];
+  __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots], lacc[3 * kLdsSlots];
   __shared__ CollideLds<double, 2, 128> cl;  // both calls of the pass drawn up front
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
@@ -682,29 +682,23 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
 
   // With both halves in one pass, kick B (end of step n) and kick A (start of
   // step n + 1) are at the same time t^{n+1} and position, so the field part
-  // of the acceleration is computed once and kept per slot (bitwise the same).
-  constexpr int kPer = (kLdsSlots + kTileThreads - 1) / kTileThreads;
-  const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 &&
-                     ns <= kPer * kTileThreads;
-  double accs[kPer][3];
+  // of the acceleration is computed once and kept per slot in LDS (bitwise the
+  // same).
+  const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 && lds;
   if (a.mode & kDoB) {
     // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
     const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
     if (K.collisions)
       tile_run<SIG, double, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                 NP, cl);
-#pragma unroll
-    for (int j = tid, q = 0; j < ns; j += kTileThreads, ++q) {
+    for (int j = tid; j < ns; j += kTileThreads) {
       int p = s0 + j;
       double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3], acc[3];
       int cc[3];
       gather_f64(K, a.E, xp, ep, cc);
       field_acc_f64(K, xp, ep, t1, acc);
       if (reuse)
-#pragma unroll
-        for (int r = 0; r < kPer; ++r)
-          if (r == q)
-            for (int d = 0; d < 3; ++d) accs[r][d] = acc[d];
+        for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
       int c = a.key[p];
       int n = a.cstart[c + 1] - a.cstart[c];
       double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
@@ -740,10 +734,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(S
       int p = s0 + j;
       double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, acc[3];
       if (reuse) {
-#pragma unroll
-        for (int r = 0; r < kPer; ++r)
-          if (base == r * kTileThreads)
-            for (int d = 0; d < 3; ++d) acc[d] = accs[r][d];
+        for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
       } else {
         double ep[3];
         int cc[3];
