@@ -18,7 +18,7 @@
 namespace pic {
 
 constexpr int kLowMaxK = 24;                 // modes per axis beyond the constant (at most)
-constexpr int kLowDefaultK = 20;             // default modes per axis
+constexpr int kLowDefaultK = 24;             // default modes per axis (fewest CG iterations)
 constexpr int kLowMaxM = 2 * kLowMaxK + 1;   // 1-D basis functions per axis
 constexpr int kLowChunk = 16;                // mesh rows staged in LDS at a time
 constexpr int kLowBlocks = 256;              // target workgroups of the plane passes
