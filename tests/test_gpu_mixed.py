@@ -122,6 +122,26 @@ def test_mixed_steps_two_way_collisional():
     np.testing.assert_allclose(eg["l2"], eo["l2"], rtol=1e-3)
 
 
+@pytest.mark.parametrize("nc,np_", [(8, 12000), (3, 19000)])
+def test_mixed_step_chunks_are_bitwise_equal(nc, np_):
+    """One pic_step(6) runs passes that hold call B of a step and call A of the
+    next, kick A reusing kick B's field acceleration (same time, same
+    position); six pic_step(1) calls run every half as a pass of its own and
+    compute it afresh.  The states agree bit for bit (3^3: tiles larger than
+    their LDS slots, where nothing is kept)."""
+    prob = W.cfg_problem(two_way=True, collisionality=20.0)
+    disc = W.cfg_disc(nc, np_, 2e-3, 1, 6, cg_tol=1e-13)
+    P = _pic()
+    a = P.Sim(prob, disc, 11, 0, "mixed")
+    b = P.Sim(prob, disc, 11, 0, "mixed")
+    a.step(6)
+    for _ in range(6):
+        b.step(1)
+    for item in (P.STATE_X, P.STATE_V, P.STATE_ID, P.STATE_CELL_START, P.STATE_PHI):
+        np.testing.assert_array_equal(a.get(item), b.get(item))
+    assert a.stats()["n_accepted"] == b.stats()["n_accepted"] > 0
+
+
 def test_mixed_large_cells_global_path():
     prob = W.cfg_problem(collisionality=2.0)
     disc = W.cfg_disc(3, 19000, 1e-3, 1, 3, cg_tol=1e-13)
