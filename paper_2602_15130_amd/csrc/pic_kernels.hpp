@@ -147,22 +147,31 @@ __device__ inline void locate(const SimConst& K, const double x[3], int c[3], do
 //            input order (stability) independently of atomic arrival order,
 //            and gather the particle state into the destination arrays.
 // ---------------------------------------------------------------------------
+// Arrival slot of each valid lane in its cell: the wave's lanes are grouped by
+// key with ballots and shuffles first (no memory traffic), then every group's
+// first lane adds the group's size to the cell count -- all groups' atomics in
+// one instruction, so the wave waits for one round trip, not one per cell --
+// and each lane takes its group's base plus its rank among the group's lanes.
 __device__ inline int wave_aggregated_slot(int* count, int key, bool valid) {
   const int lane = __lane_id();
   unsigned long long pending = __ballot(valid);
-  int my = 0;
+  int leader_of_mine = lane, rank = 0, total = 0;
   while (pending) {
-    int leader = __ffsll((long long)pending) - 1;
-    int lkey = __shfl(key, leader);
-    bool mine = valid && key == lkey && ((pending >> lane) & 1ull);
-    unsigned long long grp = __ballot(mine);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&count[lkey], __popcll(grp));
-    base = __shfl(base, leader);
-    if (mine) my = base + __popcll(grp & ((1ull << lane) - 1ull));
+    const int leader = __ffsll((long long)pending) - 1;
+    const int lkey = __shfl(key, leader);
+    const bool mine = valid && key == lkey && ((pending >> lane) & 1ull);
+    const unsigned long long grp = __ballot(mine);
+    if (mine) {
+      leader_of_mine = leader;
+      rank = __popcll(grp & ((1ull << lane) - 1ull));
+    }
+    if (lane == leader) total = __popcll(grp);
     pending &= ~grp;
   }
-  return my;
+  int base = 0;
+  if (valid && lane == leader_of_mine) base = atomicAdd(&count[key], total);
+  base = __shfl(base, leader_of_mine);
+  return valid ? base + rank : 0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_count(const int* key, int* slot, int* count, int n) {
