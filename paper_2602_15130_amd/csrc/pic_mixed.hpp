@@ -302,6 +302,24 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
   const float navg_f = (float)K.navg;
   const float inv_navg = 1.0f / navg_f;  // exact for a power-of-two N_avg
 
+  // Field part of a half kick: dt q/m (E - E^M) at cell c, offset o.
+  auto field_acc_at = [&](int c, const float o[3], const float amp[3], float acc[3]) {
+    int ci, cj, ck;
+    node_coords(K, c, ci, cj, ck);
+    float ep[3], em[3];
+    gather_mixed(K, E32, ci, cj, ck, o, ep);
+    EM_mixed(M, ci, cj, ck, o, amp, em);
+    for (int d = 0; d < 3; ++d) acc[d] = M.dtqm * (ep[d] - em[d]);
+  };
+  // A tile held in LDS computes the field part of its first kick while it
+  // loads (the gather's loads then overlap the tile's other loads) and keeps
+  // it in lacc; with both halves in one pass, kick B (end of step n) and kick A
+  // (start of step n + 1) are at the same time t^{n+1} and position (no drift
+  // between them, one field solve before the pass), so kick A reuses it:
+  // bitwise what it would compute again.
+  const bool pre = lds && !(a.mode & kCollideOnly);
+  const bool reuse_A = pre && (!(a.mode & kDoB) || a.na == a.nb + 1);
+  const float* amp0 = (a.mode & kDoB) ? M.emB : M.emA;
   const bool pass_coll = K.collisions && !(a.mode & kCollideOnly);
   if (pass_coll) tile_zero_D(ns, st, D);
   for (int j = tid; j < ns; j += kTileThreads) {
@@ -309,11 +327,15 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + p];
     if (lds) {
       const int c = a.key[p];
-      for (int d = 0; d < 3; ++d) {
-        loff[d * kLdsSlots + j] = off[(int64_t)d * NP + p];
-      }
+      const float o[3] = {off[p], off[(int64_t)NP + p], off[2 * (int64_t)NP + p]};
+      for (int d = 0; d < 3; ++d) loff[d * kLdsSlots + j] = o[d];
       lkey[j] = c;
       lcn[j] = a.cstart[c + 1] - a.cstart[c];
+      if (pre) {
+        float acc[3];
+        field_acc_at(c, o, amp0, acc);
+        for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
+      }
     }
   }
   if (pass_coll) tile_draw_pass(K, a, c0, ncells, cl);
@@ -324,16 +346,10 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     return a.cstart[c + 1] - a.cstart[c];
   };
 
-  // Field part of a half kick: dt q/m (E - E^M) at the particle.
+  // Field part of a half kick at slot j (tiles not held in LDS).
   auto field_acc = [&](int j, const float amp[3], float acc[3]) {
-    int c = tk[j];
-    int ci, cj, ck;
-    node_coords(K, c, ci, cj, ck);
-    float o[3] = {to[j], to[st + j], to[2 * st + j]};
-    float ep[3], em[3];
-    gather_mixed(K, E32, ci, cj, ck, o, ep);
-    EM_mixed(M, ci, cj, ck, o, amp, em);
-    for (int d = 0; d < 3; ++d) acc[d] = M.dtqm * (ep[d] - em[d]);
+    const float o[3] = {to[j], to[st + j], to[2 * st + j]};
+    field_acc_at(tk[j], o, amp, acc);
   };
   auto kick_with = [&](int j, const float acc[3], bool coll_on) {
     float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
@@ -353,11 +369,6 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       v0[d * st + j] = vp[d];
     }
   };
-  // With both halves in one pass, kick B (end of step n) and kick A (start of
-  // step n + 1) are at the same time t^{n+1} and position (no drift between
-  // them, one field solve before the pass), so the field part is computed once
-  // and kept per slot in LDS: bitwise what kick A would compute again.
-  const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 && lds;
 
   if (a.mode & kCollideOnly) {
     tile_collide<SIG, float, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
@@ -381,9 +392,11 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
                                NP, cl);
     for (int j = tid; j < ns; j += kTileThreads) {
       float acc[3];
-      field_acc(j, M.emB, acc);
-      if (reuse)
-        for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
+      if (pre) {
+        for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
+      } else {
+        field_acc(j, M.emB, acc);
+      }
       kick_with(j, acc, K.collisions != 0);
     }
     if (tid == 0) cl.pool_n = 0;
@@ -406,7 +419,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     if (valid) {
       int p = s0 + j;
       float acc[3];
-      if (reuse) {
+      if (reuse_A) {
         for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
       } else {
         field_acc(j, M.emA, acc);
