@@ -418,6 +418,8 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     int kk = 0;
     if (valid) {
       int p = s0 + j;
+      // the velocity shape for the drift, loaded before the kick hides its latency
+      const float sa[3] = {ash[p], ash[(int64_t)NP + p], ash[2 * (int64_t)NP + p]};
       float acc[3];
       if (reuse_A) {
         for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
@@ -431,7 +433,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       float on[3];
       for (int d = 0; d < 3; ++d) {
         // x += dt (v - v^M) in cell units; v^M = vbar a (time independent)
-        float vm = M.vbar * ash[(int64_t)d * NP + p];
+        float vm = M.vbar * sa[d];
         float o = to[d * st + j] + M.dt * (v0[d * st + j] - vm) * M.inv_h[d];
         float fl = floorf(o);
         o -= fl;
