@@ -74,7 +74,6 @@ def lib():
         L.orc_deposit.argtypes = [P(OrcProblem), P(OrcDisc), i64, P(d), P(d)]
         L.orc_rhs.argtypes = [P(OrcProblem), P(OrcDisc), P(d), d, P(d)]
         L.orc_cg.argtypes = [P(OrcDisc), P(OrcProblem), P(d), P(d), d, C.c_int, P(C.c_int), P(d)]
-        L.orc_cg_textbook.argtypes = L.orc_cg.argtypes
         L.orc_angle_record_start.argtypes = [P(d), C.c_int64]
         L.orc_angle_record_stop.argtypes = []
         L.orc_angle_record_stop.restype = C.c_int64
@@ -106,6 +105,9 @@ def lib():
         L.orc_cg_relres.argtypes = [vp]; L.orc_cg_relres.restype = d
         L.orc_accepted.argtypes = [vp]; L.orc_accepted.restype = i64
         L.orc_gmax_events.argtypes = [vp]; L.orc_gmax_events.restype = i64
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -152,6 +154,15 @@ def philox_block(ctr, key):
     o = (C.c_uint64 * 4)()
     lib().orc_philox4x64_10(c, k, o)
     return [int(x) for x in o]
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's independent loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
 
 
 def init_uniforms(seed, rep, pid):
@@ -242,14 +253,13 @@ def rhs(prob, disc, rho, t):
     return b
 
 
-def cg(prob, disc, b, phi0=None, tol=None, max_iter=None, textbook=False):
+def cg(prob, disc, b, phi0=None, tol=None, max_iter=None):
     P, D = make_problem(prob), make_disc(disc)
     b = np.ascontiguousarray(b, dtype=np.float64)
     phi = np.zeros_like(b) if phi0 is None else np.array(phi0, dtype=np.float64)
     it = C.c_int()
     rr = C.c_double()
-    fn = lib().orc_cg_textbook if textbook else lib().orc_cg
-    st = fn(C.byref(D), C.byref(P), _dp(b), _dp(phi),
+    st = lib().orc_cg(C.byref(D), C.byref(P), _dp(b), _dp(phi),
                       float(disc["cg_tol"] if tol is None else tol),
                       int(disc["cg_max_iter"] if max_iter is None else max_iter),
                       C.byref(it), C.byref(rr))

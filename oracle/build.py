@@ -1,6 +1,6 @@
 """Compile the CPU oracle (test infrastructure) into oracle/liboracle.so.
 
-Plain gcc, scalar FP64, no FMA contraction: ``python oracle/build.py``.
+Plain gcc, scalar FP64, no FMA contraction, OpenMP over independent loops: ``python oracle/build.py``.
 """
 import os
 import subprocess
@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
            "-Wall", "-Wextra", "-Wno-unused-parameter",
            "-o", LIB + ".tmp", os.path.join(HERE, "oracle.c"), "-lm"]
     if verbose:

@@ -3,7 +3,10 @@
  *
  * Each function follows the passage of the paper named in its comment and is
  * written for reading, not for speed: scalar loops, fixed summation order,
- * no blocking, no fusion.  Compile with -O2 -ffp-contract=off.
+ * no blocking, no fusion.  Compile with -O2 -ffp-contract=off.  Loops whose
+ * iterations are independent (per particle, per cell, per mesh plane) carry an
+ * OpenMP pragma; every sum over them stays serial, so the results do not
+ * depend on the thread count.
  *
  * Pins (tests/test_oracle_*.py) check this file against what the paper and the
  * mathematics fix: numpy's Philox, closed forms, conservation laws, quadrature of
@@ -16,6 +19,7 @@
 
 #include <float.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -492,6 +496,7 @@ static double cic_weight(const double o[3], int a, int b, int c) {
 
 void orc_cell_keys(const orc_problem* P, const orc_disc* D, int64_t np, const double* x,
                    int32_t* key) {
+#pragma omp parallel for
   for (int64_t p = 0; p < np; ++p) {
     double xp[3] = {x[p], x[np + p], x[2 * np + p]};
     int c[3];
@@ -602,6 +607,7 @@ void orc_laplacian(const orc_disc* D, const orc_problem* P, const double* phi, d
   if (D->poisson_op == ORC_OP_Q1) {
     static const double w1[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
     static const double d2[3] = {1.0, -2.0, 1.0};
+#pragma omp parallel for
     for (int k = 0; k < D->nc[2]; ++k)
       for (int j = 0; j < D->nc[1]; ++j)
         for (int i = 0; i < D->nc[0]; ++i) {
@@ -619,6 +625,7 @@ void orc_laplacian(const orc_disc* D, const orc_problem* P, const double* phi, d
         }
     return;
   }
+#pragma omp parallel for
   for (int k = 0; k < D->nc[2]; ++k)
     for (int j = 0; j < D->nc[1]; ++j)
       for (int i = 0; i < D->nc[0]; ++i) {
@@ -636,78 +643,17 @@ static double dot(int64_t n, const double* a, const double* b) {
   return s;
 }
 
-/* Conjugate gradients on A = -L_h (SPD on zero-mean fields), A phi = -b, in
- * the single-reduction recurrence of Chronopoulos and Gear (1989): the
- * operator is applied to the residual, s = A p is carried by its own
- * recurrence, and the two inner products of an iteration are formed together:
- *   r_0 = -b - A x_0, w_0 = A r_0, gamma_0 = r_0.r_0, alpha_0 = gamma_0 / (w_0.r_0);
- *   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}   (beta_0 = 0)
- *   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i,  w_{i+1} = A r_{i+1}
- *   gamma_{i+1} = r_{i+1}.r_{i+1},  delta_{i+1} = w_{i+1}.r_{i+1}
- *   beta_{i+1} = gamma_{i+1} / gamma_i
- *   alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i).
- * In exact arithmetic its iterates are those of textbook CG (orc_cg_textbook).
+/* Conjugate gradients (Hestenes and Stiefel, textbook form) on A = -L_h, which
+ * is SPD on zero-mean fields: A phi = -b.  The paper names no solver (Sec. 4.1
+ * fixes only a second-order operator), so this is the plain method:
+ *   r_0 = -b - A x_0, p_0 = r_0;
+ *   alpha_i = r_i.r_i / p_i.A p_i, x_{i+1} = x_i + alpha_i p_i,
+ *   r_{i+1} = r_i - alpha_i A p_i, beta_i = r_{i+1}.r_{i+1} / r_i.r_i,
+ *   p_{i+1} = r_{i+1} + beta_i p_i.
  * Stops when ||r||_2 <= tol ||b||_2.  phi holds the initial guess on entry;
  * the result is projected to zero mean (Sec. 2). */
 int orc_cg(const orc_disc* D, const orc_problem* P, const double* b, double* phi, double tol,
            int max_iter, int* iters, double* relres) {
-  int64_t n = nnodes(D);
-  double* r = (double*)malloc(sizeof(double) * n);
-  double* w = (double*)malloc(sizeof(double) * n);
-  double* p = (double*)malloc(sizeof(double) * n);
-  double* s = (double*)malloc(sizeof(double) * n);
-  double* rhs = (double*)malloc(sizeof(double) * n);
-  for (int64_t i = 0; i < n; ++i) rhs[i] = -b[i];
-  orc_laplacian(D, P, phi, w); /* w = L phi, so A phi = -w */
-  for (int64_t i = 0; i < n; ++i) r[i] = rhs[i] + w[i];
-  double bnorm = sqrt(dot(n, rhs, rhs));
-  double gamma = dot(n, r, r);
-  int it = 0, status = 0;
-  if (bnorm == 0.0) {
-    for (int64_t i = 0; i < n; ++i) phi[i] = 0.0;
-    gamma = 0.0;
-  } else if (sqrt(gamma) > tol * bnorm) {
-    orc_laplacian(D, P, r, w);
-    for (int64_t i = 0; i < n; ++i) w[i] = -w[i];
-    double delta = dot(n, w, r);
-    double alpha = gamma / delta, beta = 0.0;
-    while (1) {
-      if (it >= max_iter) {
-        status = -3;
-        break;
-      }
-      for (int64_t i = 0; i < n; ++i) {
-        p[i] = (it == 0) ? r[i] : r[i] + beta * p[i];
-        s[i] = (it == 0) ? w[i] : w[i] + beta * s[i];
-      }
-      for (int64_t i = 0; i < n; ++i) phi[i] += alpha * p[i];
-      for (int64_t i = 0; i < n; ++i) r[i] -= alpha * s[i];
-      orc_laplacian(D, P, r, w);
-      for (int64_t i = 0; i < n; ++i) w[i] = -w[i];
-      double gamma_new = dot(n, r, r);
-      delta = dot(n, w, r);
-      ++it;
-      beta = gamma_new / gamma;
-      alpha = gamma_new / (delta - beta * gamma_new / alpha);
-      gamma = gamma_new;
-      if (sqrt(gamma) <= tol * bnorm) break;
-    }
-  }
-  double mean = 0.0;
-  for (int64_t i = 0; i < n; ++i) mean += phi[i];
-  mean /= (double)n;
-  for (int64_t i = 0; i < n; ++i) phi[i] -= mean;
-  *iters = it;
-  *relres = (bnorm == 0.0) ? 0.0 : sqrt(gamma) / bnorm;
-  free(r); free(w); free(p); free(s); free(rhs);
-  return status;
-}
-
-/* Textbook conjugate gradients (Hestenes and Stiefel) on the same system, with
- * the same stopping rule and projection; kept as an independent check of the
- * recurrence above. */
-int orc_cg_textbook(const orc_disc* D, const orc_problem* P, const double* b, double* phi,
-                    double tol, int max_iter, int* iters, double* relres) {
   int64_t n = nnodes(D);
   double* r = (double*)malloc(sizeof(double) * n);
   double* p = (double*)malloc(sizeof(double) * n);
@@ -730,12 +676,17 @@ int orc_cg_textbook(const orc_disc* D, const orc_problem* P, const double* b, do
         break;
       }
       orc_laplacian(D, P, p, Ap);
+#pragma omp parallel for
       for (int64_t i = 0; i < n; ++i) Ap[i] = -Ap[i];
       double alpha = rr / dot(n, p, Ap);
-      for (int64_t i = 0; i < n; ++i) phi[i] += alpha * p[i];
-      for (int64_t i = 0; i < n; ++i) r[i] -= alpha * Ap[i];
+#pragma omp parallel for
+      for (int64_t i = 0; i < n; ++i) {
+        phi[i] += alpha * p[i];
+        r[i] -= alpha * Ap[i];
+      }
       double rr_new = dot(n, r, r);
       double beta = rr_new / rr;
+#pragma omp parallel for
       for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
       rr = rr_new;
       ++it;
@@ -756,6 +707,7 @@ void orc_gradient(const orc_problem* P, const orc_disc* D, const double* phi, do
   int64_t nn = nnodes(D);
   double h[3];
   for (int d = 0; d < 3; ++d) h[d] = P->L[d] / D->nc[d];
+#pragma omp parallel for
   for (int k = 0; k < D->nc[2]; ++k)
     for (int j = 0; j < D->nc[1]; ++j)
       for (int i = 0; i < D->nc[0]; ++i) {
@@ -771,6 +723,7 @@ void orc_gradient(const orc_problem* P, const orc_disc* D, const double* phi, do
 void orc_gather(const orc_problem* P, const orc_disc* D, const double* E, int64_t np,
                 const double* x, double* Ep) {
   int64_t nn = nnodes(D);
+#pragma omp parallel for
   for (int64_t p = 0; p < np; ++p) {
     double xp[3] = {x[p], x[np + p], x[2 * np + p]};
     int c[3];
@@ -1046,8 +999,9 @@ static void sim_sort(orc_sim* s) {
   orc_stable_sort(np, (int32_t)s->nn, s->key, s->perm, s->cell_start);
   double* arrs[2] = {s->x, s->v};
   for (int a = 0; a < 2; ++a) {
-    for (int d = 0; d < 3; ++d)
-      for (int64_t i = 0; i < np; ++i) s->tmp[d * np + i] = arrs[a][d * np + s->perm[i]];
+#pragma omp parallel for
+    for (int64_t i = 0; i < np; ++i)
+      for (int d = 0; d < 3; ++d) s->tmp[d * np + i] = arrs[a][d * np + s->perm[i]];
     memcpy(arrs[a], s->tmp, sizeof(double) * 3 * (size_t)np);
   }
   for (int64_t i = 0; i < np; ++i) s->id_tmp[i] = s->id[s->perm[i]];
@@ -1065,6 +1019,7 @@ static int sim_field(orc_sim* s, double t) {
 }
 
 int orc_init(orc_sim* s) {
+#pragma omp parallel for
   for (int64_t p = 0; p < s->np; ++p) {
     double xi[6], xm[3], vm[3];
     orc_init_uniforms(s->seed, s->rep, p, xi);
@@ -1095,28 +1050,38 @@ static int sim_collide(orc_sim* s, int call, double t, double* dv_avg, double* d
     int64_t n = s->cell_start[c + 1] - s->cell_start[c];
     if (n > maxn) maxn = n;
   }
-  double* vc = (double*)malloc(sizeof(double) * 3 * (size_t)(maxn + 1));
-  double* dc = (double*)malloc(sizeof(double) * 3 * (size_t)(maxn + 1));
-  int st = 0;
-  for (int64_t c = 0; c < s->nn; ++c) {
-    int64_t b = s->cell_start[c], n = s->cell_start[c + 1] - b;
-    for (int d = 0; d < 3; ++d)
-      for (int64_t j = 0; j < n; ++j) vc[d * n + j] = s->v[d * np + b + j];
-    orc_collide_cell(&s->P, &s->D, s->seed, s->rep, s->step, call, c, n, vc, dc, log, log_cap,
-                     log_n, &s->n_acc, &s->n_gmax);
-    double coef = (w * s->D.dt * (double)(n - 1)) / (2.0 * dV);
-    for (int64_t j = 0; j < n; ++j) {
-      double vp[3] = {vc[j], vc[n + j], vc[2 * n + j]}, I[3];
-      if (orc_source_integral(&s->P, vp, t, I) != 0) st = -1;
-      for (int d = 0; d < 3; ++d) {
-        dv_avg[d * np + b + j] = dc[d * n + j];
-        dv_src[d * np + b + j] = (n >= 2) ? coef * I[d] : 0.0;
+  /* cells are independent; the pair log and the angle records keep the serial
+   * cell order, so they run on one thread */
+  const int serial = log != NULL || angle_rec.buf != NULL;
+  int64_t acc = 0, gmx = 0;
+  int bad = 0;
+#pragma omp parallel if (!serial) reduction(+ : acc, gmx) reduction(| : bad)
+  {
+    double* vc = (double*)malloc(sizeof(double) * 3 * (size_t)(maxn + 1));
+    double* dc = (double*)malloc(sizeof(double) * 3 * (size_t)(maxn + 1));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t c = 0; c < s->nn; ++c) {
+      int64_t b = s->cell_start[c], n = s->cell_start[c + 1] - b;
+      for (int d = 0; d < 3; ++d)
+        for (int64_t j = 0; j < n; ++j) vc[d * n + j] = s->v[d * np + b + j];
+      orc_collide_cell(&s->P, &s->D, s->seed, s->rep, s->step, call, c, n, vc, dc, log, log_cap,
+                       log_n, &acc, &gmx);
+      double coef = (w * s->D.dt * (double)(n - 1)) / (2.0 * dV);
+      for (int64_t j = 0; j < n; ++j) {
+        double vp[3] = {vc[j], vc[n + j], vc[2 * n + j]}, I[3];
+        if (orc_source_integral(&s->P, vp, t, I) != 0) bad = 1;
+        for (int d = 0; d < 3; ++d) {
+          dv_avg[d * np + b + j] = dc[d * n + j];
+          dv_src[d * np + b + j] = (n >= 2) ? coef * I[d] : 0.0;
+        }
       }
     }
+    free(vc);
+    free(dc);
   }
-  free(vc);
-  free(dc);
-  return st;
+  s->n_acc += acc;
+  s->n_gmax += gmx;
+  return bad ? -1 : 0;
 }
 
 int orc_collide(orc_sim* s, int call, double t, double* dv_avg, double* dv_src, orc_pair* log,
@@ -1141,6 +1106,7 @@ static int sim_kick(orc_sim* s, double t, double t_iso_from, double t_iso_to, co
   orc_gather(&s->P, &s->D, s->E, np, s->x, s->Ep);
   double qm = s->P.field_to_particles ? s->P.q / s->P.m : 0.0;
   double dt = s->D.dt;
+#pragma omp parallel for
   for (int64_t p = 0; p < np; ++p) {
     double xi[6], xp[3], EM[3], h[3];
     orc_init_uniforms(s->seed, s->rep, s->id[p], xi);
@@ -1170,6 +1136,7 @@ static int sim_kick(orc_sim* s, double t, double t_iso_from, double t_iso_to, co
 static void sim_drift(orc_sim* s, double t0, double th, double t1) {
   int64_t np = s->np;
   double dt = s->D.dt;
+#pragma omp parallel for
   for (int64_t p = 0; p < np; ++p) {
     double xi[6], vm[3], h[3];
     orc_init_uniforms(s->seed, s->rep, s->id[p], xi);
@@ -1284,3 +1251,7 @@ int orc_cg_iters(orc_sim* s) { return s->cg_iters; }
 double orc_cg_relres(orc_sim* s) { return s->cg_relres; }
 int64_t orc_accepted(orc_sim* s) { return s->n_acc; }
 int64_t orc_gmax_events(orc_sim* s) { return s->n_gmax; }
+
+/* Threads of the independent loops (results do not depend on it). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -10,8 +10,10 @@
  * definition of Philox4x64-10 and the stream layout stated below, which each
  * side implements on its own.
  *
- * Everything is scalar FP64, single threaded, compiled with
- * -ffp-contract=off, and written to be checked against the paper by eye.
+ * Everything is scalar FP64, compiled with -ffp-contract=off, and written to be
+ * checked against the paper by eye.  Independent per-particle and per-cell
+ * loops run on OpenMP threads; sums stay serial, so results are bitwise the
+ * same for any thread count.
  *
  * Random stream layout (the paper's Algorithm 1 only says "rand_num()"):
  *   generator  Philox4x64-10, key = (seed, replicate)
@@ -21,9 +23,12 @@
  *              c3 = block index
  *   tag 1 INIT   particle id, n = 0: block 0 -> (xi_x, xi_y, xi_z, -),
  *                block 1 -> (xi_u, xi_v, xi_w, -); uniforms on (0,1)
- *   tag 2 COLL   cell, step, call (0 = first kick, 1 = second kick), outcome:
- *                block 0 word 0 -> N_pairs uniform; pair m uses blocks
- *                1+2m -> (p, q, U_acc, U_eps) and 2+2m -> (U_chi, q-redraw 1..3)
+ *   tag 4 NPAIRS cell, step, call (0 = first kick, 1 = second kick), outcome
+ *                field k / 4, block 0: word k mod 4 -> the N_pairs uniform of
+ *                outcome k (four consecutive outcomes share one block)
+ *   tag 2 COLL   cell, step, call, outcome k: pair m uses blocks
+ *                1+2m -> (p, q, U_acc, U_eps) and 2+2m -> (U_chi, q-redraw 1..3);
+ *                block 0 is not used
  *   tag 3 REDRAW same entity/step/call/outcome, c3 = m << 16 | j: four further
  *                q-redraws per block j of pair m
  *   uniform on [0,1): (w >> 11) * 2^-53; on (0,1): ((w >> 12) + 1/2) * 2^-52;
@@ -115,8 +120,6 @@ void orc_deposit(const orc_problem* P, const orc_disc* D, int64_t np, const doub
 void orc_rhs(const orc_problem* P, const orc_disc* D, const double* rho, double t, double* b);
 int orc_cg(const orc_disc* D, const orc_problem* P, const double* b, double* phi,
            double tol, int max_iter, int* iters, double* relres);
-int orc_cg_textbook(const orc_disc* D, const orc_problem* P, const double* b, double* phi,
-                    double tol, int max_iter, int* iters, double* relres);
 void orc_laplacian(const orc_disc* D, const orc_problem* P, const double* phi, double* out);
 void orc_gradient(const orc_problem* P, const orc_disc* D, const double* phi, double* E);
 void orc_gather(const orc_problem* P, const orc_disc* D, const double* E, int64_t np,
@@ -167,6 +170,8 @@ int orc_cg_iters(orc_sim* s);
 double orc_cg_relres(orc_sim* s);
 int64_t orc_accepted(orc_sim* s);
 int64_t orc_gmax_events(orc_sim* s);
+void orc_set_threads(int n);
+int orc_max_threads(void);
 
 #ifdef __cplusplus
 }
