@@ -21,10 +21,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# Bytes the method itself must move per particle-step on push + deposit +
+# collide, with the uniforms regenerated from Philox rather than stored:
+# the particle state read and written once (mixed: cell index 4 + FP32 offsets
+# 12 + FP32 velocities 12 = 28 B; FP64: positions 24 + velocities 24 = 48 B)
+# and the 4-byte sort key.
+METHOD_BYTES = {"mixed": 28 + 28 + 4, "fp64": 48 + 48 + 4}
+
+
+def progress(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
 
 def stage_bytes(stage, prob, disc, precision, cg_iters):
-    """Algorithmic bytes one launch of a stage must move (reads + writes of the
-    arrays the method needs; mesh arrays counted once).  Per particle: position
+    """Bytes this implementation's arrays need per step of a stage (reads +
+    writes, mesh arrays counted once): the implementation's own model, larger
+    than METHOD_BYTES because it also carries the velocity shape, the sort
+    slot and the reordered copy.  Per particle: position
     px (three FP64 coordinates, or three FP32 in-cell offsets with the cell
     index), velocity sv, the manufactured-velocity shape sa (v^M = vbar a, one
     vector per particle), id and cell key 4 bytes each."""
@@ -88,19 +101,92 @@ def measured_traffic(stage, workload):
     return int((m["FETCH_SIZE"] * f["FETCH_SIZE"] + m["WRITE_SIZE"] * f["WRITE_SIZE"]) * 2**20)
 
 
-def cpu_baseline(prob, disc, seed):
-    """The oracle on the host cores: init (untimed), then one timed step of the
-    same workload; particle-steps/s."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cells_by_id(cell_start, ids):
+    """Cell of every particle, indexed by particle id, from a cell-sorted order."""
+    import numpy as np
+    cells = np.repeat(np.arange(len(cell_start) - 1), np.diff(cell_start))
+    out = np.empty_like(cells)
+    out[ids] = cells
+    return out
+
+
+def _compare_with_oracle(pic, g, o, prob, disc):
+    """Per-quantity differences of a GPU simulation from the FP64 oracle at the
+    same step, by particle identity: largest position difference (minimum
+    image) in cells and velocity difference in vbar over the particles whose
+    cell agrees, the number whose cell differs, phi and rho relative to their
+    largest value, and the relative differences of the error norms."""
+    import numpy as np
+    ig, io = g.get(pic.STATE_ID), o.get(o.ID)
+    xg, xo = np.empty((3, disc["np"])), np.empty((3, disc["np"]))
+    vg, vo = np.empty_like(xg), np.empty_like(xo)
+    xg[:, ig], xo[:, io] = g.get(pic.STATE_X), o.get(o.X)
+    vg[:, ig], vo[:, io] = g.get(pic.STATE_V), o.get(o.V)
+    same = _cells_by_id(g.get(pic.STATE_CELL_START), ig) == _cells_by_id(o.get(o.CELL_START), io)
+    L = np.array(prob["L"])[:, None]
+    h = prob["L"][0] / disc["nc"][0]
+    dx = np.abs(xg - xo)
+    dx = np.minimum(dx, L - dx).max(axis=0)
+    dv = np.abs(vg - vo).max(axis=0)
+    pg, po = g.get(pic.STATE_PHI), o.get(o.PHI)
+    rg, ro = g.get(pic.STATE_RHO), o.get(o.RHO)
+    eg, eo = g.errors(), o.errors()
+    return {"step": int(o.step_index),
+            "max_dx_over_h": float(dx[same].max() / h),
+            "max_dv_over_vbar": float(dv[same].max() / prob["vbar"]),
+            "cell_flips": int((~same).sum()),
+            "phi_rel": float(np.abs(pg - po).max() / np.abs(po).max()),
+            "rho_rel": float(np.abs(rg - ro).max() / np.abs(ro).max()),
+            "l2_rel": [float("%.3g" % v) for v in np.abs(eg["l2"] / eo["l2"] - 1)],
+            "accepted": {"gpu": int(g.stats()["n_accepted"]), "oracle": int(o.accepted)}}
+
+
+def oracle_leg(pic, prob, disc, seed, precision):
+    """The oracle on the host cores, on a bounded sample of the workload: init
+    (untimed, all threads), one time step on all threads, one on a single
+    thread (particle-steps/s each).  The same two oracle steps also give the
+    per-quantity differences of the GPU form from the FP64 oracle at full size
+    (a GPU simulation from the same initial state, compared after each step)."""
     import oracle as O
 
-    s = O.Sim(prob, disc, seed, 0)
-    s.init()
-    t0 = time.perf_counter()
-    s.step(1)
-    dt = time.perf_counter() - t0
-    return {"value": disc["np"] / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 time step of the full workload after init ({disc['np']} particles, "
-                      f"{disc['nc'][0]}^3 mesh), single-threaded FP64 C, {dt:.1f} s"}
+    nthreads = O.max_threads()
+    progress(f"oracle init ({disc['np']} particles, {nthreads} threads)")
+    o = O.Sim(prob, disc, seed, 0)
+    o.init()
+    g = pic.Sim(prob, disc, seed, 0, precision)
+    rates, parity = {}, []
+    try:
+        for threads in (nthreads, 1):
+            O.set_threads(threads)
+            progress(f"oracle step on {threads} thread(s)")
+            t0 = time.perf_counter()
+            o.step(1)
+            rates[threads] = (disc["np"] / (time.perf_counter() - t0), time.perf_counter() - t0)
+            g.step(1)
+            parity.append(_compare_with_oracle(pic, g, o, prob, disc))
+    finally:
+        O.set_threads(nthreads)
+        g.close()
+    base = {"value": rates[nthreads][0], "unit": "particle-steps/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"one time step of the full workload ({disc['np']} particles, "
+                      f"{disc['nc'][0]}^3 mesh) after init, FP64 C with OpenMP over the "
+                      f"independent per-particle and per-cell loops, {nthreads} threads, "
+                      f"{rates[nthreads][1]:.1f} s",
+            "single_core": {"value": rates[1][0], "cores": 1,
+                            "sample": f"the next time step on one thread, {rates[1][1]:.1f} s"},
+            "nproc": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model()}
+    return base, {"reference": "FP64 oracle", "form": precision, "steps": parity}
 
 
 def convergence_report(pic, W, levels=(0, 1, 2, 3)):
@@ -117,7 +203,7 @@ def convergence_report(pic, W, levels=(0, 1, 2, 3)):
             g = pic.Sim(L["problem"], L["disc"], 1, 0, precision)
             g.step(L["disc"]["steps"])
             norms.append(list(g.errors()["l2"]))
-            del g
+            g.close()
         orders[precision] = W.observed_orders(norms)
         rep[precision] = {"l2": [[float("%.6g" % v) for v in n] for n in norms],
                           "orders": [[round(v, 4) for v in o] for o in orders[precision]]}
@@ -167,16 +253,20 @@ def main():
     if args.workload == "table1":
         print(json.dumps(run_table1(args.levels, args.cases)), flush=True)
         return
+    progress(f"timing {args.workload}")
     out = run_workload(pic, W, torch, args.workload, args.steps, args.warmup)
     if args.beside and args.beside != "none":
+        progress(f"timing {args.beside}")
         b = run_workload(pic, W, torch, args.beside, args.steps, args.warmup)
         out["beside"] = {k: b[k] for k in ("value", "ms_per_step", "dtype", "config", "roofline",
                                            "roofline_particle_path", "stages", "cg_iters_last")}
     if not args.no_convergence:
+        progress("convergence ladder")
         out["convergence"] = convergence_report(pic, W)
     if not args.no_cpu_baseline:
         c = W.get(args.workload)
-        out["cpu_baseline"] = cpu_baseline(c["problem"], c["disc"], c["seed"])
+        out["cpu_baseline"], out["parity_vs_oracle"] = oracle_leg(
+            pic, c["problem"], c["disc"], c["seed"], c["precision"])
     print(json.dumps(out), flush=True)
 
 
@@ -235,7 +325,7 @@ def run_table1(levels, cases_arg="isolated,coupled,collisionless"):
                          "n_avg": disc["navg"], "steps": disc["steps"], "wall_s": round(wall, 2),
                          "accepted": g.stats()["n_accepted"], "l2": [float(x) for x in e["l2"]],
                          "linf": [float(x) for x in e["linf"]]})
-            del g
+            g.close()
         orders = []
         for a, b in zip(rows, rows[1:]):
             r = math.log(b["ncell"] / a["ncell"])
@@ -288,24 +378,35 @@ def run_workload(pic, W, torch, workload, steps, warmup):
     elapsed = t1 - t0
     value = disc["np"] * steps / elapsed
 
-    dom_bytes = stage_bytes(dom, prob, disc, precision, st["cg_iters"])
-    ach = dom_bytes / (dom_ms / steps * 1e-3) / 1e9
+    impl_bytes = stage_bytes(dom, prob, disc, precision, st["cg_iters"])
+    dom_s = dom_ms / steps * 1e-3
+    # the fused particle pass is push + collide; its roofline uses the method's
+    # minimum bytes, the implementation's own model is reported beside it
+    dom_bytes = METHOD_BYTES[precision] * disc["np"] if dom == "particle" else impl_bytes
+    ach = dom_bytes / dom_s / 1e9
     kernel_names = {"particle": "k_particles_" + ("f64" if precision == "fp64" else "mixed"),
                     "cg": "k_cg_brick / k_cg (+ low-mode pre-solve)", "sort": "k_order_tiles",
                     "deposit": "k_deposit_tiles"}
     roof = {"bound": "hbm", "kernel": kernel_names.get(dom, dom), "achieved": round(ach, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(dom, workload), "algorithmic_bytes_per_step": dom_bytes,
+            "bytes_basis": ("method minimum, %d B per particle-step" % METHOD_BYTES[precision]
+                            if dom == "particle" else "implementation model"),
+            "implementation_bytes_per_step": impl_bytes,
+            "implementation_GBs": round(impl_bytes / dom_s / 1e9, 1),
             "per": "time step", "us_per_step": round(1e3 * dom_ms / steps, 2), "launches": dom_n}
-    # the particle path (push, deposit, collide: the fused pass, sort and deposit)
+    # push + deposit + collide: the fused pass, the sort (which deposits) and
+    # the node charge, at the method's minimum bytes per particle-step
     part_names = [k for k in ("particle", "collide", "kick", "drift", "sort", "deposit") if k in per_stage]
-    pb = sum(stage_bytes(k, prob, disc, precision, st["cg_iters"]) for k in part_names)
+    pb = METHOD_BYTES[precision] * disc["np"]
     pms = sum(per_stage[k]["ms_total"] for k in part_names) / nbreak
     pach = pb / (pms * 1e-3) / 1e9
+    impl_pb = sum(stage_bytes(k, prob, disc, precision, st["cg_iters"]) for k in part_names)
     roof_part = {"bound": "hbm", "kernels": part_names, "achieved": round(pach, 1),
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
                  "ms_per_step": round(pms, 3),
-                 "algorithmic_bytes_per_particle_step": round(pb / disc["np"], 1)}
+                 "method_bytes_per_particle_step": METHOD_BYTES[precision],
+                 "implementation_bytes_per_particle_step": round(impl_pb / disc["np"], 1)}
     out = {
         "metric": "particle-steps/s", "value": value, "unit": "particle-steps/s", "n_gpus": 1,
         "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * elapsed / steps,
@@ -323,7 +424,7 @@ def run_workload(pic, W, torch, workload, steps, warmup):
         "cg_solver": {"blocks": st["cg_blocks"], "brick": st["cg_brick"]},
         "accepted_collisions": st["n_accepted"],
     }
-    del sim
+    sim.close()
     torch.cuda.synchronize()
     return out
 

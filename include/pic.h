@@ -50,7 +50,10 @@ enum pic_status {
   PIC_ENONFINITE = -4,  /* a non-finite value in the particle state or norms */
   PIC_ESTATE = -5,      /* call out of order (e.g. before initialisation) */
   PIC_ESPACE = -6,      /* workspace too small */
-  PIC_WARN_NAVG = 1     /* N_avg P_coll,max >= 0.5: eq. navg_ineq not satisfied */
+  PIC_WARN_NAVG = 1,    /* N_avg P_coll,max >= 0.5: eq. navg_ineq not satisfied */
+  PIC_WARN_GMAX = 2     /* a candidate pair had g > g_max: (sigma g)_max is taken
+                           over [0, g_max] (Sec. 5.2), so such a pair may accept
+                           with sigma g / (sigma g)_max > 1 */
 };
 
 enum pic_precision {
@@ -180,7 +183,8 @@ int pic_step(pic_ctx* ctx, int n_steps);
  * int64 (cell, call, outcome k, pair m, p, q, accepted), in no particular
  * order, or NULL; *pairlog_n (host, may be NULL) receives the number of
  * candidate pairs (which may exceed pairlog_cap; the excess is not written).
- * Synchronises the context stream.
+ * Synchronises the context stream.  Returns PIC_WARN_GMAX (outputs valid)
+ * once any candidate pair since initialisation had g > g_max.
  */
 int pic_collide(pic_ctx* ctx, int call, double t, double* dv_avg, double* dv_src,
                 int64_t* pairlog, int64_t pairlog_cap, int64_t* pairlog_n);
@@ -188,7 +192,10 @@ int pic_collide(pic_ctx* ctx, int call, double t, double* dv_avg, double* dv_src
 /* Error norms at the current time t = step * dt (Sec. 4.3): l2 and linf of
  * x, y, z (minimum image), u, v, w over all particles and of phi over the
  * nodes.  Synchronises; returns PIC_ENOCONV / PIC_EHIP for an earlier
- * asynchronous failure and PIC_ENONFINITE for a non-finite norm. */
+ * asynchronous failure, PIC_ENONFINITE for a non-finite norm or particle
+ * state, and the warning PIC_WARN_GMAX (norms valid) once any candidate pair
+ * since initialisation had g > g_max.  The partial sums live in the
+ * context's workspace; the reduction order depends only on the sizes. */
 typedef struct {
   double t;
   double l2[7];             /* x, y, z, u, v, w, phi */
@@ -249,6 +256,20 @@ enum pic_state_item {
   PIC_STATE_E = 6           /* 3 * ncells doubles */
 };
 int pic_get_state(pic_ctx* ctx, int item, void* host_dst, int64_t bytes);
+
+/* Replace the particle positions (PIC_STATE_X) or velocities (PIC_STATE_V):
+ * host_src holds 3 * n_particles doubles, component-major, in the current
+ * cell-sorted order (the order pic_get_state returns); bytes must equal that
+ * size.  New positions are wrapped into the periodic box (a non-finite
+ * coordinate becomes 0 and the next synchronising call reports
+ * PIC_ENONFINITE), the particles are stable-sorted by their new cells from the
+ * current order, and the charge is deposited and the Poisson equation
+ * (eq. poisson_mms) solved at the current time, as at initialisation.
+ * Velocities are taken as given (rounded to FP32 in the mixed form); a
+ * non-finite one makes pic_errors return PIC_ENONFINITE.  The manufactured
+ * solution and the particle identities are unchanged.  Synchronises;
+ * PIC_EINVAL for other items or a size mismatch. */
+int pic_set_state(pic_ctx* ctx, int item, const void* host_src, int64_t bytes);
 
 /* Per-stage GPU time, measured with HIP events recorded on the context stream
  * around each stage's kernels while timing is enabled. */

@@ -1234,15 +1234,29 @@ int orc_get(orc_sim* s, int what, void* dst) {
   return -1;
 }
 
-/* Replace the particle state (positions, velocities, ids), re-sort and re-solve
- * the field at the current time, as at initialisation. */
+/* Replace the particle positions or velocities (component-major, in the
+ * current cell-sorted order).  New positions are wrapped into [0, L), the
+ * particles are stable-sorted by their new cells from the current order, and
+ * the field is deposited and solved at the current time, as at
+ * initialisation; the CG starts from the current phi.  Returns the field
+ * solve's status, or -1 for an unknown item. */
 int orc_set(orc_sim* s, int what, const void* src) {
   size_t np = (size_t)s->np;
-  if (what == ORC_X) memcpy(s->x, src, 3 * np * sizeof(double));
-  else if (what == ORC_V) memcpy(s->v, src, 3 * np * sizeof(double));
-  else if (what == ORC_ID) memcpy(s->id, src, np * sizeof(int64_t));
-  else return -1;
-  return 0;
+  if (what == ORC_V) {
+    memcpy(s->v, src, 3 * np * sizeof(double));
+    return 0;
+  }
+  if (what != ORC_X) return -1;
+  memcpy(s->x, src, 3 * np * sizeof(double));
+  for (int d = 0; d < 3; ++d)
+    for (size_t p = 0; p < np; ++p) {
+      double L = s->P.L[d], x = s->x[d * np + p];
+      x -= floor(x / L) * L;
+      if (!(x >= 0.0 && x < L)) x = 0.0;  /* rounding up to L, or non-finite */
+      s->x[d * np + p] = x;
+    }
+  sim_sort(s);
+  return sim_field(s, (double)s->step * s->D.dt);
 }
 
 int64_t orc_step_index(orc_sim* s) { return s->step; }

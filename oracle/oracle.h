@@ -163,6 +163,8 @@ int orc_errors(orc_sim* s, double out[14]);
 enum { ORC_X = 0, ORC_V = 1, ORC_ID = 2, ORC_CELL_START = 3, ORC_RHO = 4, ORC_PHI = 5,
        ORC_E = 6, ORC_EP = 7 };
 int orc_get(orc_sim* s, int what, void* dst);
+/* Replace positions (then wrap, stable re-sort, deposit and field solve at the
+ * current time) or velocities; component-major, current sorted order. */
 int orc_set(orc_sim* s, int what, const void* src);
 int64_t orc_step_index(orc_sim* s);
 double orc_time(orc_sim* s);

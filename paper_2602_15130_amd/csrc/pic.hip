@@ -78,8 +78,8 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_E] = 3 * nn * 8;
   b[A_E32] = f64 ? 0 : 3 * nn * 4;
   b[A_PART_A] = b[A_PART_B] = std::max<int64_t>(nblk_n, 4096) * 8;
-  b[A_EPART] = nblk_p * 14 * 8;
-  b[A_NPART] = nblk_n * 2 * 8;
+  b[A_EPART] = std::min<int64_t>(nblk_p, kErrBlocks) * 14 * 8;
+  b[A_NPART] = std::min<int64_t>(nblk_n, kErrBlocks) * 2 * 8;
   b[A_NORMS] = 16 * 8;
   b[A_BAR] = (int64_t)(4096 + 1) * kFlagStride * 4;  // per-block arrival flags + release word
   b[A_RESULT] = kMaxRed * 8;
@@ -274,6 +274,7 @@ bool choose_bricks(const int nc[3], const int per_cu[], int ncu, size_t lds_max,
 struct pic_ctx {
   SimConst K{};
   int precision = PIC_FP64;
+  int device = 0;               // the GPU the context's memory and stream belong to
   double cg_tol = 1e-12;
   int cg_max_iter = 1000;
   hipStream_t stream = nullptr;
@@ -767,6 +768,56 @@ int check_flags(pic_ctx* c) {
   return PIC_OK;
 }
 
+// PIC_WARN_GMAX once a candidate pair with g > g_max has been seen since
+// initialisation (stream idle).
+int gmax_warning(pic_ctx* c) {
+  unsigned long long n = 0;
+  HIP_TRY(c, hipMemcpy(&n, c->cnt + kCntGmax, sizeof(n), hipMemcpyDeviceToHost));
+  if (n > 0) {
+    c->err = std::to_string(n) + " candidate pairs had a relative speed above g_max";
+    return PIC_WARN_GMAX;
+  }
+  return PIC_OK;
+}
+
+// Workgroups of the error-norm kernels: one per 256 items, at most kErrBlocks.
+int err_grid(int64_t n) { return (int)std::min<int64_t>(kErrBlocks, grid_for(n)); }
+
+// Sec. 4.3 norms with the partial sums in epart ([err_grid(np)][14]), npart
+// ([err_grid(nn)][2]) and the 14 results in norms (device).
+int errors_into(pic_ctx* c, pic_error_norms* out, double* epart, double* npart, double* norms) {
+  if (!out) {
+    c->err = "null output";
+    return PIC_EINVAL;
+  }
+  const SimConst& K = c->K;
+  double t = (double)c->step * K.dt;
+  const int nbp = err_grid(K.np), nbn = err_grid(K.nn);
+  int s = c->cur;
+  if (c->precision == PIC_FP64)
+    k_err_particles_f64<<<nbp, kBlock, 0, c->stream>>>(K, t, c->x[s], c->v[s], c->id[s], epart,
+                                                       c->flags);
+  else
+    k_err_particles_mixed<<<nbp, kBlock, 0, c->stream>>>(K, t, c->key, c->off[s], c->vf[s],
+                                                         c->id[s], epart, c->flags);
+  k_err_nodes<<<nbn, kBlock, 0, c->stream>>>(K, t, c->phi, npart);
+  k_err_final<<<1, kBlock, 0, c->stream>>>(K, epart, nbp, npart, nbn, norms);
+  LAUNCH_CHECK(c, "errors");
+  double h[14];
+  HIP_TRY(c, hipMemcpyAsync(h, norms, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  TRY(check_flags(c));
+  out->t = t;
+  for (int a = 0; a < 7; ++a) {
+    out->l2[a] = h[a];
+    out->linf[a] = h[7 + a];
+    if (!std::isfinite(h[a]) || !std::isfinite(h[7 + a])) {
+      c->err = "non-finite error norm";
+      return PIC_ENONFINITE;
+    }
+  }
+  return gmax_warning(c);
+}
+
 }  // namespace
 
 extern "C" {
@@ -895,6 +946,7 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     delete c;
     return PIC_EHIP;
   }
+  c->device = dev;
   c->cg_grid = (int)std::min<int64_t>({(int64_t)ncu, (int64_t)ncu * per_cu, (int64_t)grid_for(c->K.nn)});
   // PIC_CG_BLOCKS sets the solver grid wanted (fewer blocks make each grid-wide
   // reduction cheaper and each sweep longer); it never exceeds the co-resident
@@ -1081,41 +1133,13 @@ int pic_collide(pic_ctx* c, int call, double t, double* dv_avg, double* dv_src, 
     HIP_TRY(c, hipMemcpy(&nlog, c->cnt + kCntPairLog, sizeof(nlog), hipMemcpyDeviceToHost));
     *pairlog_n = (int64_t)nlog;
   }
-  return check_flags(c);
+  TRY(check_flags(c));
+  return gmax_warning(c);
 }
 
 int pic_errors(pic_ctx* c, pic_error_norms* out) {
   if (!c || !c->ready) return PIC_ESTATE;
-  if (!out) {
-    c->err = "null output";
-    return PIC_EINVAL;
-  }
-  const SimConst& K = c->K;
-  double t = (double)c->step * K.dt;
-  int nbp = grid_for(K.np), nbn = grid_for(K.nn);
-  int s = c->cur;
-  if (c->precision == PIC_FP64)
-    k_err_particles_f64<<<nbp, kBlock, 0, c->stream>>>(K, t, c->x[s], c->v[s], c->id[s], c->epart,
-                                                       c->flags);
-  else
-    k_err_particles_mixed<<<nbp, kBlock, 0, c->stream>>>(K, t, c->key, c->off[s], c->vf[s], c->id[s],
-                                                         c->epart, c->flags);
-  k_err_nodes<<<nbn, kBlock, 0, c->stream>>>(K, t, c->phi, c->npart);
-  k_err_final<<<1, kBlock, 0, c->stream>>>(K, c->epart, nbp, c->npart, nbn, c->norms);
-  LAUNCH_CHECK(c, "errors");
-  double h[14];
-  HIP_TRY(c, hipMemcpyAsync(h, c->norms, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-  TRY(check_flags(c));
-  out->t = t;
-  for (int a = 0; a < 7; ++a) {
-    out->l2[a] = h[a];
-    out->linf[a] = h[7 + a];
-    if (!std::isfinite(h[a]) || !std::isfinite(h[7 + a])) {
-      c->err = "non-finite error norm";
-      return PIC_ENONFINITE;
-    }
-  }
-  return PIC_OK;
+  return errors_into(c, out, c->epart, c->npart, c->norms);
 }
 
 namespace {
@@ -1365,6 +1389,48 @@ int pic_get_state(pic_ctx* c, int item, void* host_dst, int64_t bytes) {
     case PIC_STATE_PHI: HIP_TRY(c, hipMemcpy(host_dst, c->phi, need, hipMemcpyDeviceToHost)); break;
     case PIC_STATE_E: HIP_TRY(c, hipMemcpy(host_dst, c->E, need, hipMemcpyDeviceToHost)); break;
   }
+  return check_flags(c);
+}
+
+int pic_set_state(pic_ctx* c, int item, const void* host_src, int64_t bytes) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (item != PIC_STATE_X && item != PIC_STATE_V) {
+    c->err = "pic_set_state: only PIC_STATE_X and PIC_STATE_V can be set";
+    return PIC_EINVAL;
+  }
+  const SimConst& K = c->K;
+  const int64_t need = 3 * K.np * 8;
+  if (!host_src || bytes != need) {
+    c->err = "source size mismatch: need " + std::to_string(need);
+    return PIC_EINVAL;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int s = c->cur;
+  if (item == PIC_STATE_V && c->precision == PIC_FP64) {
+    HIP_TRY(c, hipMemcpy(c->v[s], host_src, need, hipMemcpyHostToDevice));
+    return check_flags(c);
+  }
+  // staged in the workspace's FP64 scratch (idle between steps)
+  HIP_TRY(c, hipMemcpy(c->U, host_src, need, hipMemcpyHostToDevice));
+  if (item == PIC_STATE_V) {
+    k_set_velocities_mixed<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->U, c->vf[s]);
+    LAUNCH_CHECK(c, "set velocities");
+  } else {
+    // new cells, stable re-sort from the current order, deposit and field solve
+    // at the current time, as at initialisation
+    TRY(zero_counts(c));
+    if (c->precision == PIC_FP64)
+      k_set_positions_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->U, c->x[s], c->key,
+                                                                    c->slot, c->count, c->flags);
+    else
+      k_set_positions_mixed<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->U, c->off[s], c->key,
+                                                                      c->slot, c->count, c->flags);
+    LAUNCH_CHECK(c, "set positions");
+    c->mom_ready = false;
+    TRY(sort_particles(c));
+    TRY(field_solve(c, (double)c->step * K.dt));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return check_flags(c);
 }
 

@@ -356,6 +356,42 @@ __global__ void __launch_bounds__(kBlock) k_init_f64(SimConst K, double* x, doub
   if (valid) slot[p] = s;
 }
 
+// Positions given by the caller (component-major FP64): wrapped into [0, L)
+// (a non-finite coordinate becomes 0 and raises the non-finite flag), with the
+// cell keys and arrival slots of the stable sort that follows.
+__device__ inline double wrap_box(double x, double L, bool& bad) {
+  double w = x - floor(x / L) * L;
+  if (!(w >= 0.0 && w < L)) {  // rounded up to L, or non-finite
+    bad |= !isfinite(x);
+    w = 0.0;
+  }
+  return w;
+}
+
+__global__ void __launch_bounds__(kBlock) k_set_positions_f64(SimConst K, const double* xin,
+                                                              double* x, int* key, int* slot,
+                                                              int* count, int* flags) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  bool valid = p < K.np;
+  int kk = 0;
+  if (valid) {
+    bool bad = false;
+    double xp[3];
+    for (int d = 0; d < 3; ++d) {
+      xp[d] = wrap_box(xin[d * K.np + p], K.L[d], bad);
+      x[d * K.np + p] = xp[d];
+    }
+    if (bad) atomicOr(&flags[kFlagNonFinite], 1);
+    int c[3];
+    double o[3];
+    locate(K, xp, c, o);
+    kk = lin(K, c[0], c[1], c[2]);
+    key[p] = kk;
+  }
+  int s = wave_aggregated_slot(count, kk, valid);
+  if (valid) slot[p] = s;
+}
+
 // ---------------------------------------------------------------------------
 // Charge deposition (Sec. 2, cloud in cell), atomic free: each cell sums the
 // eight corner weights of its own particles in cell-sorted order, then each
@@ -989,18 +1025,24 @@ __global__ void __launch_bounds__(kBlock) k_drift_f64(SimConst K, double t0, dou
 }
 
 // ---------------------------------------------------------------------------
-// Error norms (Sec. 4.3): per-block partial sums of squares and maxima, then a
-// single block combines them in a fixed order.  part layout: [blk][14].
+// Error norms (Sec. 4.3): a fixed grid of at most kErrBlocks workgroups; each
+// thread accumulates its strided particles (or nodes) in index order, each
+// workgroup combines its threads in a fixed order into one partial, and a
+// single workgroup combines the partials in block order.  The result depends
+// only on the sizes, never on scheduling.  part layout: [blk][14].
 // ---------------------------------------------------------------------------
+constexpr int kErrBlocks = 1024;
+
 __global__ void __launch_bounds__(kBlock) k_err_particles_f64(SimConst K, double t,
                                                               const double* x, const double* v,
                                                               const int* id, double* part,
                                                               int* flags) {
   __shared__ double sh[kWaves];
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  double e[6] = {0, 0, 0, 0, 0, 0};
-  if (i < K.np) {
-    double xq[3], xv[3], xm[3], a[3], vm[3], vd[3];
+  double s2[6] = {0, 0, 0, 0, 0, 0}, mx[6] = {0, 0, 0, 0, 0, 0};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < K.np;
+       i += (int64_t)gridDim.x * kBlock) {
+    double xq[3], xv[3], xm[3], a[3], vm[3], vd[3], e[6];
     position_uniforms(K, id[i], xq);
     velocity_uniforms(K, id[i], xv);
     double xp[3] = {x[i], x[K.np + i], x[2 * K.np + i]};
@@ -1014,15 +1056,19 @@ __global__ void __launch_bounds__(kBlock) k_err_particles_f64(SimConst K, double
       e[d] = ex;
       e[3 + d] = v[d * K.np + i] - vm[d];
     }
-    for (int a2 = 0; a2 < 6; ++a2)
-      if (!isfinite(e[a2])) atomicOr(&flags[kFlagNonFinite], 1);
+    for (int a2 = 0; a2 < 6; ++a2) {
+      bad |= !isfinite(e[a2]);
+      s2[a2] += e[a2] * e[a2];
+      mx[a2] = fmax(mx[a2], fabs(e[a2]));
+    }
   }
+  if (bad) atomicOr(&flags[kFlagNonFinite], 1);
   for (int a2 = 0; a2 < 6; ++a2) {
-    double s2 = block_sum(e[a2] * e[a2], sh);
-    double mx = block_max(fabs(e[a2]), sh);
+    double s = block_sum(s2[a2], sh);
+    double m = block_max(mx[a2], sh);
     if (threadIdx.x == 0) {
-      part[blockIdx.x * 14 + a2] = s2;
-      part[blockIdx.x * 14 + 7 + a2] = mx;
+      part[blockIdx.x * 14 + a2] = s;
+      part[blockIdx.x * 14 + 7 + a2] = m;
     }
   }
 }
@@ -1030,19 +1076,20 @@ __global__ void __launch_bounds__(kBlock) k_err_particles_f64(SimConst K, double
 __global__ void __launch_bounds__(kBlock) k_err_nodes(SimConst K, double t, const double* phi,
                                                       double* part) {
   __shared__ double sh[kWaves];
-  int n = blockIdx.x * kBlock + threadIdx.x;
-  double e = 0.0;
-  if (n < K.nn) {
+  double s2 = 0.0, mx = 0.0;
+  for (int n = blockIdx.x * kBlock + threadIdx.x; n < K.nn; n += gridDim.x * kBlock) {
     int i, j, k;
     node_coords(K, n, i, j, k);
     double xn[3] = {i * K.h[0], j * K.h[1], k * K.h[2]};
-    e = phi[n] - phiM(K, xn, t);
+    const double e = phi[n] - phiM(K, xn, t);
+    s2 += e * e;
+    mx = fmax(mx, fabs(e));
   }
-  double s2 = block_sum(e * e, sh);
-  double mx = block_max(fabs(e), sh);
+  double s = block_sum(s2, sh);
+  double m = block_max(mx, sh);
   if (threadIdx.x == 0) {
-    part[blockIdx.x * 2] = s2;
-    part[blockIdx.x * 2 + 1] = mx;
+    part[blockIdx.x * 2] = s;
+    part[blockIdx.x * 2 + 1] = m;
   }
 }
 

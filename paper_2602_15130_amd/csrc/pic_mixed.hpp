@@ -51,6 +51,37 @@ __global__ void __launch_bounds__(kBlock) k_init_mixed(SimConst K, float* off, f
   if (valid) slot[p] = s;
 }
 
+// Positions given by the caller (FP64) as cell + FP32 offset, wrapped as in
+// k_set_positions_f64; velocities given by the caller rounded to FP32.
+__global__ void __launch_bounds__(kBlock) k_set_positions_mixed(SimConst K, const double* xin,
+                                                                float* off, int* key, int* slot,
+                                                                int* count, int* flags) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  bool valid = p < K.np;
+  int kk = 0;
+  if (valid) {
+    bool bad = false;
+    double xp[3];
+    for (int d = 0; d < 3; ++d) xp[d] = wrap_box(xin[d * K.np + p], K.L[d], bad);
+    if (bad) atomicOr(&flags[kFlagNonFinite], 1);
+    int c[3];
+    double o[3];
+    locate(K, xp, c, o);
+    kk = lin(K, c[0], c[1], c[2]);
+    for (int d = 0; d < 3; ++d) off[d * K.np + p] = fminf((float)o[d], kOneBelow);
+    key[p] = kk;
+  }
+  int s = wave_aggregated_slot(count, kk, valid);
+  if (valid) slot[p] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_set_velocities_mixed(SimConst K, const double* vin,
+                                                                 float* vf) {
+  int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (p >= K.np) return;
+  for (int d = 0; d < 3; ++d) vf[d * K.np + p] = (float)vin[d * K.np + p];
+}
+
 // Neumaier-compensated accumulation: s + c carries the sum to about FP64 accuracy.
 __device__ inline void neumaier_add(float& s, float& c, float x) {
   float t = s + x;
@@ -483,40 +514,48 @@ __global__ void __launch_bounds__(kBlock) k_export_mixed(SimConst K, const int* 
 }
 
 // Error norms of the mixed state: positions rebuilt in FP64, manufactured
-// values from FP64 roots, FP64 reductions.
+// values from FP64 roots, FP64 reductions (same fixed grid and order as
+// k_err_particles_f64).
 __global__ void __launch_bounds__(kBlock) k_err_particles_mixed(SimConst K, double t, const int* key,
                                                                 const float* off, const float* vf,
                                                                 const int* id, double* part,
                                                                 int* flags) {
   __shared__ double sh[kWaves];
-  int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  double e[6] = {0, 0, 0, 0, 0, 0};
-  if (i < K.np) {
-    double xi[6], xm[3], a[3];
-    init_uniforms(K, id[i], xi);
+  double s2[6] = {0, 0, 0, 0, 0, 0}, mx[6] = {0, 0, 0, 0, 0, 0};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < K.np;
+       i += (int64_t)gridDim.x * kBlock) {
+    double xq[3], xv[3], xm[3], a[3], vm[3], vd[3], e[6];
+    position_uniforms(K, id[i], xq);
+    velocity_uniforms(K, id[i], xv);
     int c = key[i];
     int cc[3];
     node_coords(K, c, cc[0], cc[1], cc[2]);
     double xp[3];
     for (int d = 0; d < 3; ++d) xp[d] = ((double)cc[d] + (double)off[d * K.np + i]) * K.h[d];
-    manufactured_position(K, xi, t, xp, xm);
-    velocity_shape(K, xi + 3, a);
+    manufactured_position(K, xq, t, xp, xm);
+    velocity_shape(K, xv, a);
+    manufactured_velocity(K, a, t, vm, vd);
     for (int d = 0; d < 3; ++d) {
       double ex = xp[d] - xm[d];
       if (ex >= 0.5 * K.L[d]) ex -= K.L[d];
       if (ex < -0.5 * K.L[d]) ex += K.L[d];
       e[d] = ex;
-      e[3 + d] = (double)vf[d * K.np + i] - K.vbar * a[d];
+      e[3 + d] = (double)vf[d * K.np + i] - vm[d];
     }
-    for (int a2 = 0; a2 < 6; ++a2)
-      if (!isfinite(e[a2])) atomicOr(&flags[kFlagNonFinite], 1);
+    for (int a2 = 0; a2 < 6; ++a2) {
+      bad |= !isfinite(e[a2]);
+      s2[a2] += e[a2] * e[a2];
+      mx[a2] = fmax(mx[a2], fabs(e[a2]));
+    }
   }
+  if (bad) atomicOr(&flags[kFlagNonFinite], 1);
   for (int a2 = 0; a2 < 6; ++a2) {
-    double s2 = block_sum(e[a2] * e[a2], sh);
-    double mx = block_max(fabs(e[a2]), sh);
+    double s = block_sum(s2[a2], sh);
+    double m = block_max(mx[a2], sh);
     if (threadIdx.x == 0) {
-      part[blockIdx.x * 14 + a2] = s2;
-      part[blockIdx.x * 14 + 7 + a2] = mx;
+      part[blockIdx.x * 14 + a2] = s;
+      part[blockIdx.x * 14 + 7 + a2] = m;
     }
   }
 }

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -16,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_EHIP, PIC_ENOCONV, PIC_ENONFINITE, PIC_ESTATE, PIC_ESPACE = 0, -1, -2, -3, -4, -5, -6
-PIC_WARN_NAVG = 1
+PIC_WARN_NAVG, PIC_WARN_GMAX = 1, 2
 PIC_FP64, PIC_MIXED = 0, 1
 PRECISION = {"fp64": PIC_FP64, "mixed": PIC_MIXED}
 FAMILY = {"paper": 0, "cfg": 1}
@@ -71,6 +72,7 @@ def _load():
     L.pic_errors.argtypes = [vp, P(pic_error_norms)]
     L.pic_stats.argtypes = [vp, P(pic_stats_t)]
     L.pic_get_state.argtypes = [vp, C.c_int, vp, i64]
+    L.pic_set_state.argtypes = [vp, C.c_int, vp, i64]
     L.pic_timing_enable.argtypes = [vp, C.c_int]
     L.pic_timing_stages.argtypes = [vp, C.c_uint32]
     L.pic_timing_read.argtypes = [vp, P(C.c_double), P(i64)]
@@ -91,7 +93,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pic_workspace_size", "pic_init_manufactured", "pic_step", "pic_collide", "pic_errors",
-            "pic_stats", "pic_get_state", "pic_timing_enable", "pic_timing_stages", "pic_timing_read",
+            "pic_stats", "pic_get_state", "pic_set_state", "pic_timing_enable", "pic_timing_stages", "pic_timing_read",
             "pic_destroy",
             "pic_angle_buffer_bytes", "pic_angle_log", "pic_angle_errors",
             "pic_checkpoint_bytes", "pic_checkpoint_save", "pic_checkpoint_load",
@@ -164,16 +166,18 @@ def pic_step(ctx, n_steps: int):
 
 
 def pic_collide(ctx, call, t, dv_avg_ptr, dv_src_ptr, pairlog_ptr=0, pairlog_cap=0):
+    """Number of candidate pairs and the status (PIC_OK or a PIC_WARN_* code)."""
     n = C.c_int64()
-    _check(lib.pic_collide(ctx, int(call), float(t), C.c_void_p(dv_avg_ptr), C.c_void_p(dv_src_ptr),
-                           C.c_void_p(pairlog_ptr or None), int(pairlog_cap), C.byref(n)), ctx)
-    return n.value
+    st = _check(lib.pic_collide(ctx, int(call), float(t), C.c_void_p(dv_avg_ptr),
+                                C.c_void_p(dv_src_ptr), C.c_void_p(pairlog_ptr or None),
+                                int(pairlog_cap), C.byref(n)), ctx)
+    return n.value, st
 
 
 def pic_errors(ctx) -> dict:
     e = pic_error_norms()
-    _check(lib.pic_errors(ctx, C.byref(e)), ctx)
-    return {"t": e.t, "l2": np.array(list(e.l2)), "linf": np.array(list(e.linf))}
+    st = _check(lib.pic_errors(ctx, C.byref(e)), ctx)
+    return {"t": e.t, "l2": np.array(list(e.l2)), "linf": np.array(list(e.linf)), "status": st}
 
 
 def pic_stats(ctx) -> dict:
@@ -187,6 +191,11 @@ def pic_stats(ctx) -> dict:
 def pic_get_state(ctx, item: int, out: np.ndarray):
     _check(lib.pic_get_state(ctx, int(item), out.ctypes.data, out.nbytes), ctx)
     return out
+
+
+def pic_set_state(ctx, item: int, src: np.ndarray):
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    return _check(lib.pic_set_state(ctx, int(item), src.ctypes.data, src.nbytes), ctx)
 
 
 def pic_timing_enable(ctx, enable: bool):
@@ -262,12 +271,28 @@ class Sim:
         self.ctx, self.init_status = pic_init_manufactured(
             prob, disc, seed, replicate, precision, ptr, nbytes, self.stream.cuda_stream)
 
-    def __del__(self):
+    def close(self):
+        """Release the context (pic_destroy synchronises its stream); the
+        workspace is freed with this object."""
         ctx = getattr(self, "ctx", None)
         destroy = getattr(self, "_destroy", None)
         if ctx and destroy is not None:
             destroy(ctx)
-            self.ctx = None
+        self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        # no HIP calls while the interpreter (and with it the runtime) shuts
+        # down: contexts still open then are left to the process exit
+        if sys.is_finalizing():
+            return
+        self.close()
 
     def step(self, n: int = 1):
         pic_step(self.ctx, n)
@@ -278,8 +303,8 @@ class Sim:
         dv = torch.zeros(3 * self.np, dtype=torch.float64, device=self.device)
         src = torch.zeros(3 * self.np, dtype=torch.float64, device=self.device)
         log = torch.zeros(max(1, pairlog_cap) * 7, dtype=torch.int64, device=self.device)
-        n = pic_collide(self.ctx, call, t, dv.data_ptr(), src.data_ptr(),
-                        log.data_ptr() if pairlog_cap else 0, pairlog_cap)
+        n, self.collide_status = pic_collide(self.ctx, call, t, dv.data_ptr(), src.data_ptr(),
+                                             log.data_ptr() if pairlog_cap else 0, pairlog_cap)
         pairs = log[: 7 * min(n, pairlog_cap)].view(-1, 7).cpu().numpy() if pairlog_cap else None
         return (dv.view(3, -1).cpu().numpy(), src.view(3, -1).cpu().numpy(), pairs, n)
 
@@ -326,6 +351,10 @@ class Sim:
 
     def stats(self) -> dict:
         return pic_stats(self.ctx)
+
+    def set(self, item: int, values: np.ndarray):
+        """Replace positions (re-sort and field solve follow) or velocities."""
+        return pic_set_state(self.ctx, item, values)
 
     def get(self, item: int) -> np.ndarray:
         if item in (STATE_X, STATE_V):
