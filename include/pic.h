@@ -203,6 +203,19 @@ typedef struct {
 } pic_error_norms;
 int pic_errors(pic_ctx* ctx, pic_error_norms* out);
 
+/* pic_errors for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and result, bit for bit, with the partial sums and results in
+ * a static array of the library (131,200 bytes per GPU, held until the process
+ * ends) instead of the context's workspace.  The array's address on the
+ * context's GPU is looked up once, on the first call there.  Calls no
+ * allocating routine.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that overlap on one GPU (other
+ * threads, other contexts on concurrent streams) race and must be serialised
+ * by the caller.  Returns PIC_EINVAL if the partial sums would not fit (they
+ * always do: at most 1024 workgroups per reduction); otherwise as pic_errors. */
+int pic_errors_noalloc(pic_ctx* ctx, pic_error_norms* out);
+
 /* Scattering-angle recovery (eq. angle_recovery and the empirical-CDF errors
  * defined after it).  While a log is enabled, every accepted collision of
  * pic_step and pic_collide appends chi = acos(g'_z / g) and

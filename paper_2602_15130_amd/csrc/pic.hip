@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -780,6 +781,45 @@ int gmax_warning(pic_ctx* c) {
   return PIC_OK;
 }
 
+}  // namespace
+
+// Static scratch of pic_errors_noalloc: the error-norm partial sums and
+// results (at most kErrBlocks x 14 particle partials, kErrBlocks x 2 node
+// partials and 14 results, 131 KB).  Each GPU holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: only the address hipGetSymbolAddress returns for a device is
+// used, in kernel arguments and copies.
+constexpr int64_t kNoAllocScratchDoubles = (int64_t)kErrBlocks * 16 + 16;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch's device address on the context's GPU, looked up once per
+// device with that device current.
+int noalloc_scratch(pic_ctx* c, double** out) {
+  if (c->device < 0 || c->device >= kMaxDevices) {
+    c->err = "device index beyond the static scratch table";
+    return PIC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[c->device]) {
+    int prev = 0;
+    HIP_TRY(c, hipGetDevice(&prev));
+    if (prev != c->device) HIP_TRY(c, hipSetDevice(c->device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != c->device) HIP_TRY(c, hipSetDevice(prev));
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[c->device] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[c->device];
+  return PIC_OK;
+}
+
 // Workgroups of the error-norm kernels: one per 256 items, at most kErrBlocks.
 int err_grid(int64_t n) { return (int)std::min<int64_t>(kErrBlocks, grid_for(n)); }
 
@@ -1140,6 +1180,21 @@ int pic_collide(pic_ctx* c, int call, double t, double* dv_avg, double* dv_src, 
 int pic_errors(pic_ctx* c, pic_error_norms* out) {
   if (!c || !c->ready) return PIC_ESTATE;
   return errors_into(c, out, c->epart, c->npart, c->norms);
+}
+
+int pic_errors_noalloc(pic_ctx* c, pic_error_norms* out) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  const int npb = err_grid(c->K.np), nnb = err_grid(c->K.nn);
+  const int64_t need = (int64_t)npb * 14 + (int64_t)nnb * 2 + 16;
+  if (need > kNoAllocScratchDoubles) {
+    c->err = "pic_errors_noalloc: the partial sums need " + std::to_string(need) +
+             " doubles, more than the " + std::to_string(kNoAllocScratchDoubles) +
+             " of the static scratch";
+    return PIC_EINVAL;
+  }
+  double* s = nullptr;
+  TRY(noalloc_scratch(c, &s));
+  return errors_into(c, out, s, s + (int64_t)npb * 14, s + (int64_t)npb * 14 + (int64_t)nnb * 2);
 }
 
 namespace {

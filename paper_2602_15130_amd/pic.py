@@ -73,6 +73,7 @@ def _load():
     L.pic_stats.argtypes = [vp, P(pic_stats_t)]
     L.pic_get_state.argtypes = [vp, C.c_int, vp, i64]
     L.pic_set_state.argtypes = [vp, C.c_int, vp, i64]
+    L.pic_errors_noalloc.argtypes = [vp, P(pic_error_norms)]
     L.pic_timing_enable.argtypes = [vp, C.c_int]
     L.pic_timing_stages.argtypes = [vp, C.c_uint32]
     L.pic_timing_read.argtypes = [vp, P(C.c_double), P(i64)]
@@ -93,7 +94,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pic_workspace_size", "pic_init_manufactured", "pic_step", "pic_collide", "pic_errors",
-            "pic_stats", "pic_get_state", "pic_set_state", "pic_timing_enable", "pic_timing_stages", "pic_timing_read",
+            "pic_errors_noalloc", "pic_stats", "pic_get_state", "pic_set_state", "pic_timing_enable", "pic_timing_stages", "pic_timing_read",
             "pic_destroy",
             "pic_angle_buffer_bytes", "pic_angle_log", "pic_angle_errors",
             "pic_checkpoint_bytes", "pic_checkpoint_save", "pic_checkpoint_load",
@@ -186,6 +187,13 @@ def pic_stats(ctx) -> dict:
     return {"step": s.step, "cg_iters": s.cg_iters, "cg_relres": s.cg_relres,
             "n_accepted": s.n_accepted, "n_gmax": s.n_gmax,
             "cg_blocks": s.cg_blocks, "cg_brick": list(s.cg_brick)}
+
+
+def pic_errors_noalloc(ctx) -> dict:
+    """pic_errors with its partial sums in the library's static scratch."""
+    e = pic_error_norms()
+    st = _check(lib.pic_errors_noalloc(ctx, C.byref(e)), ctx)
+    return {"t": e.t, "l2": np.array(list(e.l2)), "linf": np.array(list(e.linf)), "status": st}
 
 
 def pic_get_state(ctx, item: int, out: np.ndarray):
