@@ -75,7 +75,7 @@ def stage_bytes(stage, prob, disc, precision, cg_iters):
 # committed counter record.
 DEVICE_SOURCES = ("pic.hip", "pic_device.hpp", "pic_kernels.hpp", "pic_particle.hpp", "pic_mixed.hpp",
                   "pic_cg_brick.hpp", "pic_lowmode.hpp", "pic_angles.hpp", "pic_collide_heavy.hpp",
-                  "pic_order.hpp")
+                  "pic_order.hpp", "pic_host.hpp")
 
 
 def measured_traffic(stage, workload):

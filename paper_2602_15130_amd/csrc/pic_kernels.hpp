@@ -549,6 +549,14 @@ __device__ inline bool spin_until(const unsigned* addr, unsigned want, int* flag
   return true;
 }
 
+// Waits until this wave's outstanding vector-memory operations have completed
+// (device code only: a host build of these headers has no such queue).
+__device__ inline void wait_vector_memory() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#endif
+}
+
 // Grid-wide sum of nv block values; every thread of every block (NT threads
 // each) gets the same nv results.  `gen` increases by one per call within a
 // launch.
@@ -561,7 +569,7 @@ __device__ inline bool grid_sum_t(const CgArgs& a, double* vals, int nv, unsigne
   // block barrier; thread 0's agent-scope release below then writes back L2
   // and so publishes the whole block's stores with its flag.  (A workgroup
   // barrier alone does not wait for outstanding vector-memory stores.)
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  wait_vector_memory();
   for (int i = 0; i < nv; ++i) tot[i] = vals[i];
   block_sum3_t<NT>(tot, nv, sh);
   if (threadIdx.x == 0) {

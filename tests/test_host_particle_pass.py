@@ -1,0 +1,234 @@
+"""The library's particle kernels run on the CPU under a workgroup emulator
+(tests/host_emu): every GPU thread is a fiber that yields at block barriers
+and wave operations, and the scheduler runs the threads of a workgroup in
+forward, reverse or freshly shuffled order between barriers.  A result that
+changes with the order exposes a missing barrier or a race on shared memory;
+the harness is built with the address and undefined-behaviour sanitizers, so
+an index outside its array faults.
+
+* One collision call of the fused kernel (collide-only mode: Algorithm 1
+  averaged over N_avg outcomes, eq. avg_outcome, and the manufactured source,
+  eq. vel_change_1c) against the oracle: equal per particle, the same accepted
+  collisions and the same recovered angles (eq. angle_recovery).
+* The fused pass (call B, second half kick, call A, first half kick, drift of
+  eq. velocity_verlet) against the separate kernels of the unfused step: bit
+  for bit, in every order.
+* A variant of the tile collisions that keeps each event's cell start and
+  count from the draw in arrays shared by the two calls' event lists (both
+  lists are drawn at the start of the tile, so the second draw overwrites the
+  first list's entries) fails the fused-pass comparison; this is the
+  mechanism behind a dropped variant that changed accepted collisions on the
+  GPU while reading the same addresses.
+"""
+import os
+import shutil
+import struct
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2602_15130_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EMU = os.path.join(ROOT, "tests", "host_emu")
+CSRC = os.path.join(ROOT, "paper_2602_15130_amd", "csrc")
+FORWARD, REVERSE, SHUFFLE = 0, 1, 2
+
+
+def _pic_structs():
+    # the C structs of include/pic.h, laid out by the binding's ctypes classes
+    from paper_2602_15130_amd import pic as P
+    return P
+
+
+def _event_variant(src):
+    """The tile collisions with each event's cell start and count kept from the
+    draw in single arrays indexed by event number, and each cell thread's
+    start and count loaded at the top of the call."""
+    def rep(s, old, new):
+        assert old in s, "variant no longer applies: " + old[:60]
+        return s.replace(old, new)
+    s = rep(src, "  int evp[CAP];      // records of the list being run\n",
+            "  int evp[CAP];      // records of the list being run\n"
+            "  int evs[CAP];\n  int evm[CAP];\n")
+    s = rep(s, "          L.evn[li][e] = (int)np_;\n",
+            "          L.evn[li][e] = (int)np_;\n          L.evs[e] = a.cstart[c];\n"
+            "          L.evm[e] = n;\n")
+    s = rep(s, "      int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];\n"
+               "      int cnt = ntc_outcome_small",
+            "      int cs = L.evs[e] - s0, n = L.evm[e];\n      int cnt = ntc_outcome_small")
+    return s
+
+
+def _compile(src_dir, exe):
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-omit-frame-pointer", "-I", EMU, "-I", src_dir, "-o", exe,
+           os.path.join(EMU, "particle_pass.cpp")]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    if not shutil.which("g++"):
+        pytest.skip("g++ not available")
+    d = tmp_path_factory.mktemp("emu")
+    var = d / "variant"
+    shutil.copytree(CSRC, var)
+    (var / "pic_particle.hpp").write_text(_event_variant((var / "pic_particle.hpp").read_text()))
+    exe, exe_var = str(d / "particle_pass"), str(d / "particle_pass_variant")
+    procs = [_compile(CSRC, exe), _compile(str(var), exe_var)]
+    for p in procs:
+        out, _ = p.communicate(timeout=600)
+        assert p.returncode == 0, out[-3000:]
+    return {"product": exe, "variant": exe_var, "dir": d}
+
+
+def _run(harness, which, prob, disc, seed, mode, order, *, steps_before=0, call=0,
+         precision=0, full=1, rng_seed=7):
+    """mode 0: collide-only at the oracle's current state; modes 1 / 2: the
+    fused pass / the separate kernels from the oracle's state after
+    steps_before steps."""
+    P = _pic_structs()
+    o = O.Sim(prob, disc, seed, 0)
+    assert o.init() == 0
+    if steps_before:
+        assert o.step(steps_before) == 0
+    v = o.get(o.V)
+    cs = o.get(o.CELL_START).astype(np.int32)
+    key = np.repeat(np.arange(len(cs) - 1, dtype=np.int32), np.diff(cs))
+    hdr = struct.pack("<QIIqiidQii", seed, 0, precision, steps_before, call, order, 0.0, rng_seed,
+                      full, mode)
+    blob = bytes(P.make_problem(prob)) + bytes(P.make_disc(disc)) + hdr
+    blob += v.tobytes() + cs.tobytes() + key.tobytes()
+    if mode:
+        blob += o.get(o.X).tobytes() + o.get(o.ID).astype(np.int32).tobytes() + o.get(o.E).tobytes()
+    fin, fout = harness["dir"] / "in.bin", harness["dir"] / "out.bin"
+    fin.write_bytes(blob)
+    r = subprocess.run([harness[which], str(fin), str(fout)], capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stderr[-3000:]
+    raw = fout.read_bytes()
+    npp, nn = disc["np"], int(np.prod(disc["nc"]))
+    pos = [0]
+
+    def take(dt, n):
+        b = np.dtype(dt).itemsize * n
+        a = np.frombuffer(raw[pos[0]:pos[0] + b], dtype=dt)
+        pos[0] += b
+        return a
+
+    out = {}
+    if mode == 0:
+        out["D"], out["S"] = take(np.float64, 3 * npp).reshape(3, -1), take(np.float64, 3 * npp).reshape(3, -1)
+    else:
+        out["x"], out["v"] = take(np.float64, 3 * npp), take(np.float64, 3 * npp)
+        out["key"], out["count"] = take(np.int32, npp), take(np.int32, nn)
+    cnt = take(np.uint64, 4)
+    out["accepted"], out["gmax"] = int(cnt[0]), int(cnt[1])
+    out["flags"] = take(np.int32, 4)
+    nrec = int(take(np.int64, 1)[0])
+    out["angles"] = take(np.float64, 2 * nrec).reshape(-1, 2)
+    return out, o
+
+
+def _paper_isolated_level1(navg=8):
+    prob = W.paper_problem(collisions=True, field_to_particles=False, particles_to_field=False,
+                           isolate=True)
+    disc = dict(W.paper_level(1))
+    disc["navg"] = navg
+    return prob, disc
+
+
+def _sorted_rows(a):
+    return a[np.lexsort(a.T[::-1])]
+
+
+@pytest.mark.parametrize("order", [FORWARD, SHUFFLE])
+def test_collision_call_matches_oracle_paper_family(harness, order):
+    """Paper family, isolated collisions, Table 1 level 1 with N_avg = 8 (the
+    case of the dropped variant), angle log on."""
+    prob, disc = _paper_isolated_level1()
+    g, o = _run(harness, "product", prob, disc, 1, 0, order)
+    a0 = o.accepted
+    with O.AngleRecorder() as rec:
+        D, S, _, _, st = o.collide(0, 0.0)
+    assert st == 0 and not g["flags"].any()
+    assert g["accepted"] == o.accepted - a0 > 1000
+    scale = np.abs(D).max()
+    assert np.abs(g["D"] - D).max() <= 1e-12 * scale
+    assert np.abs(g["S"] - S).max() <= 1e-12 * np.abs(S).max()
+    assert len(g["angles"]) == len(rec.records)
+    np.testing.assert_allclose(_sorted_rows(g["angles"]), _sorted_rows(rec.records), rtol=0,
+                               atol=1e-12)
+
+
+@pytest.mark.parametrize("navg", [4, 64])
+def test_collision_call_matches_oracle_hard_sphere(harness, navg):
+    """Configuration family, hard spheres at a collisionality where outcomes
+    have several candidate pairs (some exceed the lane-run size, and with 64
+    outcomes the tiles' event lists overflow and every cell thread runs all its
+    outcomes); lean instance, shuffled order."""
+    prob = W.cfg_problem(two_way=False, collisionality=30.0)
+    disc = W.cfg_disc(8, 16384, 1e-3, 1, navg)
+    g, o = _run(harness, "product", prob, disc, 3, 0, SHUFFLE, full=0)
+    a0 = o.accepted
+    D, S, _, _, st = o.collide(0, 0.0)
+    assert st == 0 and not g["flags"].any()
+    assert g["accepted"] == o.accepted - a0 > 1000
+    assert np.abs(g["D"] - D).max() <= 1e-12 * np.abs(D).max()
+    assert np.abs(g["S"] - S).max() <= 1e-12 * np.abs(S).max()
+
+
+def _pass_equal(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("x", "v", "key", "count")) and \
+        a["accepted"] == b["accepted"]
+
+
+@pytest.mark.parametrize("case", ["paper_isolated", "cfg_two_way"])
+def test_fused_pass_equals_separate_kernels_in_every_order(harness, case):
+    if case == "paper_isolated":
+        prob, disc = _paper_isolated_level1()
+        full, seed = 1, 1
+    else:
+        prob = W.cfg_problem(two_way=True, collisionality=30.0)
+        disc = W.cfg_disc(8, 16384, 1e-3, 1, 8)
+        full, seed = 0, 5
+    ref, _ = _run(harness, "product", prob, disc, seed, 2, FORWARD, steps_before=2, full=full)
+    assert ref["accepted"] > 1000 and not ref["flags"].any()
+    for order in (FORWARD, REVERSE, SHUFFLE):
+        got, _ = _run(harness, "product", prob, disc, seed, 1, order, steps_before=2, full=full)
+        assert _pass_equal(got, ref), (case, order)
+        if full:
+            np.testing.assert_array_equal(_sorted_rows(got["angles"]), _sorted_rows(ref["angles"]))
+
+
+def test_event_variant_is_caught(harness):
+    """The variant's fused pass differs from the separate kernels (and from
+    itself in another thread order)."""
+    prob, disc = _paper_isolated_level1()
+    ref, _ = _run(harness, "product", prob, disc, 1, 2, FORWARD, steps_before=2)
+    a, _ = _run(harness, "variant", prob, disc, 1, 1, FORWARD, steps_before=2)
+    b, _ = _run(harness, "variant", prob, disc, 1, 1, SHUFFLE, steps_before=2)
+    assert not _pass_equal(a, ref) and not _pass_equal(b, ref)
+
+
+def test_mixed_collision_call_is_order_independent_and_near_oracle(harness):
+    """The mixed form's collision call (FP32 velocity arithmetic, FP64 N_pairs,
+    integer pair selection): bitwise the same in forward and shuffled order;
+    against the FP64 oracle the accepted count differs only by near-ties and
+    all but a handful of particles agree to FP32 rounding."""
+    prob = W.cfg_problem(two_way=False, collisionality=30.0)
+    disc = W.cfg_disc(8, 16384, 1e-3, 1, 4)
+    a, o = _run(harness, "product", prob, disc, 3, 0, FORWARD, precision=1, full=0)
+    b, _ = _run(harness, "product", prob, disc, 3, 0, SHUFFLE, precision=1, full=0)
+    np.testing.assert_array_equal(a["D"], b["D"])
+    assert a["accepted"] == b["accepted"]
+    a0 = o.accepted
+    D, S, _, _, st = o.collide(0, 0.0)
+    assert abs(a["accepted"] - (o.accepted - a0)) <= 3
+    far = np.abs(a["D"] - D).max(axis=0) > 1e-5 * prob["vbar"]
+    assert far.sum() <= 12, far.sum()
+    assert np.abs(a["S"] - S).max() <= 1e-5 * np.abs(S).max()
