@@ -39,7 +39,8 @@ class OrcDisc(C.Structure):
 
 class OrcPair(C.Structure):
     _fields_ = [("cell", C.c_int64), ("call", C.c_int64), ("k", C.c_int64), ("m", C.c_int64),
-                ("p", C.c_int64), ("q", C.c_int64), ("accepted", C.c_int64)]
+                ("p", C.c_int64), ("q", C.c_int64), ("accepted", C.c_int64),
+                ("u_acc", C.c_double), ("ratio", C.c_double)]
 
 
 _lib = None
@@ -375,8 +376,10 @@ class Sim:
         ln = C.c_int64(0)
         st = lib().orc_collide(self.h, call, float(t), _dp(dv), _dp(src),
                                log if log_cap else None, log_cap, C.byref(ln))
-        pairs = [(r.cell, r.call, r.k, r.m, r.p, r.q, r.accepted)
-                 for r in list(log)[:min(ln.value, log_cap)]] if log_cap else []
+        recs = list(log)[:min(ln.value, log_cap)] if log_cap else []
+        pairs = [(r.cell, r.call, r.k, r.m, r.p, r.q, r.accepted) for r in recs]
+        # the accept test's two sides per logged pair: (U, sigma g / (sigma g)_max)
+        self.last_accept_test = np.array([(r.u_acc, r.ratio) for r in recs]).reshape(-1, 2)
         return dv, src, pairs, ln.value, st
 
     def errors(self):

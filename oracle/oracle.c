@@ -897,7 +897,8 @@ int orc_collide_cell(const orc_problem* P, const orc_disc* D, uint64_t seed, uin
       double dx = u[p] - u[q], dy = u[n + p] - u[n + q], dz = u[2 * n + p] - u[2 * n + q];
       double g = sqrt(dx * dx + dy * dy + dz * dz);
       if (g > P->g_max) ++*n_gmax;
-      int accepted = orc_u01(wa[2]) < orc_sigma_g(P, g) / sgmax;
+      double u_acc = orc_u01(wa[2]), ratio = orc_sigma_g(P, g) / sgmax;
+      int accepted = u_acc < ratio;
       if (accepted) {
         ++*n_accepted;
         double eps = TWO_PI_D * orc_u01(wa[3]);
@@ -923,7 +924,7 @@ int orc_collide_cell(const orc_problem* P, const orc_disc* D, uint64_t seed, uin
         record_angles(u[p] - u[q], u[n + p] - u[n + q], u[2 * n + p] - u[2 * n + q], g);
       }
       if (log && *log_n < log_cap) {
-        orc_pair rec = {cell, call, k, m, p, q, accepted};
+        orc_pair rec = {cell, call, k, m, p, q, accepted, u_acc, ratio};
         log[*log_n] = rec;
       }
       if (log) ++*log_n;

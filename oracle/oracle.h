@@ -130,7 +130,13 @@ void orc_stable_sort(int64_t np, int32_t ncell, const int32_t* key, int64_t* per
                      int64_t* cell_start);
 
 /* ---- one cell, one collision call: Algorithm 1 run navg times, averaged ---- */
-typedef struct { int64_t cell, call, k, m, p, q, accepted; } orc_pair;
+/* One candidate pair of Algorithm 1: where it was drawn, the pair, whether it
+ * was accepted, and the two numbers the accept test compared (U < ratio with
+ * ratio = sigma(g) g / (sigma g)_max). */
+typedef struct {
+  int64_t cell, call, k, m, p, q, accepted;
+  double u_acc, ratio;
+} orc_pair;
 int orc_collide_cell(const orc_problem* P, const orc_disc* D, uint64_t seed, uint32_t rep,
                      int64_t step, int call, int64_t cell, int64_t n, const double* v,
                      double* dv_avg, orc_pair* log, int64_t log_cap, int64_t* log_n,
