@@ -212,6 +212,40 @@ def convergence_report(pic, W, levels=(0, 1, 2, 3)):
     return rep
 
 
+def paper_ladder_report(pic, W, levels=(1, 2, 3), cases=("coupled", "isolated")):
+    """The paper's refinement ladder (Table 1, Sec. 5.4; the Sec. 5.2
+    manufactured functions in SI units) in both forms: l2 norms of x, y, z, u,
+    v, w and phi at t = T per level, observed orders between levels, and the
+    largest gap between the two forms' orders (the mixed form must match)."""
+    import math
+    kw = {"coupled": dict(collisions=True),
+          "isolated": dict(collisions=True, field_to_particles=False, particles_to_field=False,
+                           isolate=True)}
+    n = [W.TABLE1_NCELL[lv - 1] for lv in levels]
+    rep = {"ladder": "Table 1 levels %s (%s cells per axis), s = 7, r = 5"
+                     % (",".join(map(str, levels)), ",".join(map(str, n)))}
+    for case in cases:
+        prob = W.paper_problem(**kw[case])
+        orders, out = {}, {}
+        for precision in ("fp64", "mixed"):
+            norms = []
+            for lv in levels:
+                progress(f"paper ladder {case} {precision} level {lv}")
+                disc = W.paper_level(lv)
+                with pic.Sim(prob, disc, 1, 0, precision) as g:
+                    g.step(disc["steps"])
+                    norms.append(list(g.errors()["l2"]))
+            orders[precision] = [[math.log(a / b) / math.log(n[i + 1] / n[i])
+                                  for a, b in zip(norms[i], norms[i + 1])]
+                                 for i in range(len(levels) - 1)]
+            out[precision] = {"l2": [[float("%.6g" % v) for v in x] for x in norms],
+                              "orders": [[round(v, 4) for v in o] for o in orders[precision]]}
+        out["max_order_gap"] = round(max(abs(a - b) for oa, ob in zip(orders["fp64"], orders["mixed"])
+                                         for a, b in zip(oa, ob)), 5)
+        rep[case] = out
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +297,7 @@ def main():
     if not args.no_convergence:
         progress("convergence ladder")
         out["convergence"] = convergence_report(pic, W)
+        out["convergence"]["paper_ladder"] = paper_ladder_report(pic, W)
     if not args.no_cpu_baseline:
         c = W.get(args.workload)
         out["cpu_baseline"], out["parity_vs_oracle"] = oracle_leg(

@@ -216,6 +216,32 @@ int pic_errors(pic_ctx* ctx, pic_error_norms* out);
  * always do: at most 1024 workgroups per reduction); otherwise as pic_errors. */
 int pic_errors_noalloc(pic_ctx* ctx, pic_error_norms* out);
 
+/*
+ * Refinement ensembles (the paper's refinement studies with independent
+ * replicates, Sec. 4.3): `members` simulations of one problem and
+ * discretization that differ only in the replicate, first_replicate + 0 ..
+ * members - 1, run together: every stage of a step is one launch for all
+ * members (members along the grid's z dimension), so small meshes are not
+ * bound by launch latency.  Member m is bit for bit the simulation
+ * pic_init_manufactured would create with replicate first_replicate + m.
+ * The workspace (device, pic_ensemble_workspace_size bytes, 256-byte
+ * aligned, caller-owned) holds each member's state in its own slice.  Steps
+ * are enqueued with pic_step(); pic_stats() sums the collision counters over
+ * the members and reports member 0's solver.  The calls that serve one
+ * simulation (pic_errors, pic_errors_noalloc, pic_collide, pic_set_state, the
+ * angle log and checkpoints) return PIC_EINVAL on an ensemble context.
+ */
+int pic_ensemble_workspace_size(const pic_problem* prob, const pic_discretization* disc,
+                                int precision, int members, int64_t* bytes);
+int pic_ensemble_init(pic_ctx** out, const pic_problem* prob, const pic_discretization* disc,
+                      uint64_t seed, uint32_t first_replicate, int members, int precision,
+                      void* workspace, int64_t workspace_bytes, void* hip_stream);
+/* Sec. 4.3 norms of every member at the current time: out (host) holds
+ * `members` entries.  Synchronises; status as pic_errors. */
+int pic_ensemble_errors(pic_ctx* ctx, pic_error_norms* out);
+/* pic_get_state for member `member` (0 .. members - 1). */
+int pic_ensemble_get_state(pic_ctx* ctx, int member, int item, void* host_dst, int64_t bytes);
+
 /* Scattering-angle recovery (eq. angle_recovery and the empirical-CDF errors
  * defined after it).  While a log is enabled, every accepted collision of
  * pic_step and pic_collide appends chi = acos(g'_z / g) and
@@ -254,6 +280,8 @@ typedef struct {
   int64_t n_gmax;           /* candidate pairs with g > g_max */
   int cg_blocks;            /* workgroups of the Poisson solver */
   int cg_brick[3];          /* nodes per brick of the on-chip solver; 0 0 0 = global-memory solver */
+  int cg_members_per_launch; /* ensembles: members whose solvers share one launch (all of
+                                them when they fit on the GPU together, else 1) */
 } pic_stats_t;
 int pic_stats(pic_ctx* ctx, pic_stats_t* out);
 

@@ -139,8 +139,6 @@ int validate(const pic_problem* p, const pic_discretization* d, int precision, s
       return bad("unknown sigma model");
     }
   }
-  if (precision == PIC_MIXED && p->family != PIC_MMS_CFG)
-    return bad("the mixed form supports the cfg family");
   return PIC_OK;
 }
 
@@ -207,10 +205,13 @@ struct pic_ctx {
   SimConst K{};
   int precision = PIC_FP64;
   int device = 0;               // the GPU the context's memory and stream belong to
+  int members = 1;              // ensemble members (replicates rep .. rep + members - 1)
+  int64_t mstride = 0;          // workspace bytes per member
   double cg_tol = 1e-12;
   int cg_max_iter = 1000;
   hipStream_t stream = nullptr;
   int cg_grid = 1;
+  bool cg_members_together = true;  // all members' solvers co-resident in one launch
   int cg_q = 0;                 // nodes per thread of the brick solver; 0 = global solver
   int cg_nt = kBlock;           // threads per workgroup of the solver
   const void* cg_fn = nullptr;  // the solver kernel
@@ -268,6 +269,23 @@ struct pic_ctx {
 };
 
 namespace {
+
+// Calls that serve one simulation (caller buffers, state replacement,
+// checkpoints) refuse ensemble contexts.
+int single_only(pic_ctx* c, const char* what) {
+  if (c->members == 1) return PIC_OK;
+  c->err = std::string(what) + " serves single simulations; use the pic_ensemble_ calls";
+  return PIC_EINVAL;
+}
+
+// Moves a member-0 workspace pointer to member m's slice.
+template <class T>
+T* member_ptr(const pic_ctx* c, T* p, int m) {
+  return p ? (T*)((char*)p + (int64_t)m * c->mstride) : p;
+}
+
+// Launch grid with the ensemble members along z.
+dim3 G(const pic_ctx* c, unsigned x, unsigned y = 1) { return dim3(x, y, (unsigned)c->members); }
 
 int hip_fail(pic_ctx* c, hipError_t e, const char* what) {
   c->err = std::string(what) + ": " + hipGetErrorString(e);
@@ -349,7 +367,7 @@ T* carve(pic_ctx* c, int idx) {
 template <class T>
 int fill(pic_ctx* c, T* p, T v, int64_t n) {
   int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
-  k_fill<T><<<g, kBlock, 0, c->stream>>>(p, v, n);
+  k_fill<T><<<G(c, g), kBlock, 0, c->stream>>>(p, v, n, c->mstride);
   LAUNCH_CHECK(c, "fill");
   return PIC_OK;
 }
@@ -372,9 +390,9 @@ int scan_counts(pic_ctx* c) {
   ti.ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
   ti.ncell = n;
   ti.np = (int)c->K.np;
-  k_scan_local<<<nb, kBlock, 0, c->stream>>>(c->count, c->cstart, c->bsum, n, ti);
-  k_scan_blocks<<<1, kBlock, 0, c->stream>>>(c->bsum, nb, c->cstart, n);
-  k_scan_add<<<nb, kBlock, 0, c->stream>>>(c->cstart, c->bsum, n, c->count, ti);
+  k_scan_local<<<G(c, nb), kBlock, 0, c->stream>>>(c->count, c->cstart, c->bsum, n, ti, c->mstride);
+  k_scan_blocks<<<G(c, 1), kBlock, 0, c->stream>>>(c->bsum, nb, c->cstart, n, c->mstride);
+  k_scan_add<<<G(c, nb), kBlock, 0, c->stream>>>(c->cstart, c->bsum, n, c->count, ti, c->mstride);
   LAUNCH_CHECK(c, "scan");
   c->count_zero = true;
   return PIC_OK;
@@ -385,8 +403,8 @@ int sort_particles(pic_ctx* c) {
   StageTimer tm(c, PIC_STAGE_SORT);
   TRY(scan_counts(c));
   int np = (int)c->K.np;
-  k_scatter<<<(int)(((int64_t)np + kBlock * kScatterPer - 1) / (kBlock * kScatterPer)), kBlock, 0,
-              c->stream>>>(c->key, c->slot, c->cstart, c->tidx, c->tkey, np);
+  k_scatter<<<G(c, (unsigned)(((int64_t)np + kBlock * kScatterPer - 1) / (kBlock * kScatterPer))),
+              kBlock, 0, c->stream>>>(c->key, c->slot, c->cstart, c->tidx, c->tkey, np, c->mstride);
   int s = c->cur, d = 1 - c->cur;
   const int ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
   // the fused step deposits each tile as it is moved (cell moments for the
@@ -394,13 +412,13 @@ int sort_particles(pic_ctx* c) {
   const bool dep = c->fused;
   if (c->precision == PIC_FP64) {
     auto kfn = dep ? k_order_tiles<double, true> : k_order_tiles<double, false>;
-    kfn<<<ntiles, kTileThreads, 0, c->stream>>>(c->K, c->tile_c0, c->tile_s0, c->tidx, c->tkey,
+    kfn<<<G(c, ntiles), kTileThreads, 0, c->stream>>>(c->K, c->tile_c0, c->tile_s0, c->tidx, c->tkey,
                                                  c->cstart, c->x[s], c->v[s], c->sh[s], c->id[s],
                                                  c->x[d], c->v[d], c->sh[d], c->id[d], c->key,
                                                  (double*)c->mom, np, c->flags);
   } else {
     auto kfn = dep ? k_order_tiles<float, true> : k_order_tiles<float, false>;
-    kfn<<<ntiles, kTileThreads, 0, c->stream>>>(c->K, c->tile_c0, c->tile_s0, c->tidx, c->tkey,
+    kfn<<<G(c, ntiles), kTileThreads, 0, c->stream>>>(c->K, c->tile_c0, c->tile_s0, c->tidx, c->tkey,
                                                  c->cstart, c->off[s], c->vf[s], c->asf[s],
                                                  c->id[s], c->off[d], c->vf[d], c->asf[d],
                                                  c->id[d], c->key, (float*)c->mom, np, c->flags);
@@ -422,25 +440,25 @@ int field_solve(pic_ctx* c, double t) {
     c->mom_ready = false;
     if (c->precision == PIC_FP64) {
       if (!have_mom && c->fused)
-        k_deposit_tiles_f64<<<ntiles, kTileThreads, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
+        k_deposit_tiles_f64<<<G(c, ntiles), kTileThreads, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
                                                               c->tile_c0, (double*)c->mom);
       else if (!have_mom)
         k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
                                                              (double*)c->mom);
-      k_node_rhs<double><<<nbn, kBlock, 0, c->stream>>>(K, (const double*)c->mom, t, c->rho, c->b,
+      k_node_rhs<double><<<G(c, nbn), kBlock, 0, c->stream>>>(K, (const double*)c->mom, t, c->rho, c->b,
                                                         c->partA);
     } else {
       if (!have_mom && c->fused)
-        k_deposit_tiles_mixed<<<ntiles, kTileThreads, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
+        k_deposit_tiles_mixed<<<G(c, ntiles), kTileThreads, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
                                                                 c->tile_c0, (float*)c->mom);
       else if (!have_mom)
         k_deposit_moments_mixed<<<nbn, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
                                                                (float*)c->mom);
-      k_node_rhs_mixed<<<nbn, kBlock, 0, c->stream>>>(K, (const float*)c->mom, t, c->rho, c->b,
+      k_node_rhs_mixed<<<G(c, nbn), kBlock, 0, c->stream>>>(K, (const float*)c->mom, t, c->rho, c->b,
                                                       c->partA);
     }
     // also zeroes the solver's arrival flags and release word
-    k_sub_mean<<<nbn, kBlock, 0, c->stream>>>(K, c->b, c->partA, nbn, c->bar,
+    k_sub_mean<<<G(c, nbn), kBlock, 0, c->stream>>>(K, c->b, c->partA, nbn, c->bar,
                                               (c->cg_grid + 1) * kFlagStride);
     LAUNCH_CHECK(c, "rhs");
   }
@@ -449,11 +467,11 @@ int field_solve(pic_ctx* c, double t) {
   if (c->low_k > 0) {  // exact solve of the low Fourier modes of the residual
     const LowArgs& L = c->low;
     const int planes = L.slabs * K.nc[2];
-    k_low_project<<<planes, kLowThreads, c->low_lds[0], c->stream>>>(K, L, c->b, c->phi);
+    k_low_project<<<G(c, planes), kLowThreads, c->low_lds[0], c->stream>>>(K, L, c->b, c->phi);
     // four x chunks per y mode (the LDS sized for all nx columns bounds a chunk's)
-    const dim3 gsolve((unsigned)L.m[1], (unsigned)std::min(4, K.nc[0]));
+    const dim3 gsolve = G(c, (unsigned)L.m[1], (unsigned)std::min(4, K.nc[0]));
     k_low_solve<<<gsolve, kLowThreads, c->low_lds[1], c->stream>>>(K, L);
-    k_low_correct<<<planes, kLowThreads, c->low_lds[2], c->stream>>>(K, L, c->phi);
+    k_low_correct<<<G(c, planes), kLowThreads, c->low_lds[2], c->stream>>>(K, L, c->phi);
     LAUNCH_CHECK(c, "low-mode solve");
   }
   CgArgs a;
@@ -481,11 +499,21 @@ int field_solve(pic_ctx* c, double t) {
   }
   SimConst Kc = K;
   void* args[] = {&Kc, &a};
-  HIP_TRY(c, hipLaunchCooperativeKernel(c->cg_fn, dim3(c->cg_grid), dim3(c->cg_nt), args,
-                                        c->cg_lds, c->stream));
+  if (c->cg_members_together) {
+    // every member's solver in one co-resident grid (members along z; each
+    // member's bricks synchronise only among themselves)
+    HIP_TRY(c, hipLaunchCooperativeKernel(c->cg_fn, G(c, c->cg_grid), dim3(c->cg_nt), args,
+                                          c->cg_lds, c->stream));
+  } else {
+    for (int m = 0; m < c->members; ++m) {
+      Kc.member0 = m;
+      HIP_TRY(c, hipLaunchCooperativeKernel(c->cg_fn, dim3(c->cg_grid), dim3(c->cg_nt), args,
+                                            c->cg_lds, c->stream));
+    }
+  }
   tm_solve.stop();
   StageTimer tm(c, PIC_STAGE_GRADIENT);
-  k_gradient<<<nbn, kBlock, 0, c->stream>>>(K, c->phi, c->E, c->E32);
+  k_gradient<<<G(c, nbn), kBlock, 0, c->stream>>>(K, c->phi, c->E, c->E32);
   LAUNCH_CHECK(c, "gradient");
   return PIC_OK;
 }
@@ -574,28 +602,25 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
   const int tiles = (int)((K.np + kTileB - 1) / kTileB);
   const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
   if (c->precision == PIC_MIXED) {
-    const double tA = (double)a.na * K.dt, tB = ((double)a.nb + 1.0) * K.dt;
-    MixConst M = mix_const(K, tA, tB);
+    const MixConst M = mix_const(K, a);
     const int s = c->cur;
     // the collision-angle and pair-log recording and the anisotropic
     // polar-angle samplers are compiled only into the full instances; the
     // lean ones serve isotropic scattering with no log attached
     const bool ang = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO;
-    const dim3 grid(tiles), blk(kTileThreads);
-    float *o = c->off[s], *vv = c->vf[s];
-    const float *sh = c->asf[s], *e = c->E32;
-    if (sig == kSigHS && ang)
-      k_particles_mixed<kSigHS, true><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
-    else if (sig == kSigHS)
-      k_particles_mixed<kSigHS, false><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
-    else if (sig == kSigMaxwell && ang)
-      k_particles_mixed<kSigMaxwell, true><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
-    else if (sig == kSigMaxwell)
-      k_particles_mixed<kSigMaxwell, false><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
-    else if (ang)
-      k_particles_mixed<kSigPoly, true><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
-    else
-      k_particles_mixed<kSigPoly, false><<<grid, blk, 0, c->stream>>>(K, M, a, o, vv, sh, e);
+    void (*fn)(SimConst, MixConst, PartArgs, float*, float*, const float*, const float*) = nullptr;
+    if (K.family == 1) {
+      if (sig == kSigHS) fn = ang ? k_particles_mixed<1, kSigHS, true> : k_particles_mixed<1, kSigHS, false>;
+      else if (sig == kSigMaxwell)
+        fn = ang ? k_particles_mixed<1, kSigMaxwell, true> : k_particles_mixed<1, kSigMaxwell, false>;
+      else fn = ang ? k_particles_mixed<1, kSigPoly, true> : k_particles_mixed<1, kSigPoly, false>;
+    } else {
+      if (sig == kSigMaxwell)
+        fn = ang ? k_particles_mixed<0, kSigMaxwell, true> : k_particles_mixed<0, kSigMaxwell, false>;
+      else fn = ang ? k_particles_mixed<0, kSigPoly, true> : k_particles_mixed<0, kSigPoly, false>;
+    }
+    fn<<<G(c, tiles), dim3(kTileThreads), 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s],
+                                                          c->E32);
     LAUNCH_CHECK(c, "particles (mixed)");
     return PIC_OK;
   }
@@ -611,7 +636,7 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
       fn = ang ? k_particles_f64<0, kSigMaxwell, true> : k_particles_f64<0, kSigMaxwell, false>;
     else fn = ang ? k_particles_f64<0, kSigPoly, true> : k_particles_f64<0, kSigPoly, false>;
   }
-  fn<<<tiles, kTileThreads, 0, c->stream>>>(K, a);
+  fn<<<G(c, tiles), kTileThreads, 0, c->stream>>>(K, a);
   LAUNCH_CHECK(c, "particles");
   return PIC_OK;
 }
@@ -662,8 +687,13 @@ int one_step(pic_ctx* c) {
 // Read back flags raised by earlier asynchronous work.
 int check_flags(pic_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  int f[kFlagCount];
-  HIP_TRY(c, hipMemcpy(f, c->flags, sizeof(f), hipMemcpyDeviceToHost));
+  int f[kFlagCount] = {0, 0, 0, 0};
+  for (int m = 0; m < c->members; ++m) {
+    int fm[kFlagCount];
+    HIP_TRY(c, hipMemcpy(fm, (const char*)c->flags + (int64_t)m * c->mstride, sizeof(fm),
+                         hipMemcpyDeviceToHost));
+    for (int i = 0; i < kFlagCount; ++i) f[i] |= fm[i];
+  }
   if (f[kFlagBarrier]) {
     c->err = "grid barrier timed out in the Poisson solver";
     return PIC_EHIP;
@@ -687,7 +717,12 @@ int check_flags(pic_ctx* c) {
 // initialisation (stream idle).
 int gmax_warning(pic_ctx* c) {
   unsigned long long n = 0;
-  HIP_TRY(c, hipMemcpy(&n, c->cnt + kCntGmax, sizeof(n), hipMemcpyDeviceToHost));
+  for (int m = 0; m < c->members; ++m) {
+    unsigned long long nm = 0;
+    HIP_TRY(c, hipMemcpy(&nm, (const char*)(c->cnt + kCntGmax) + (int64_t)m * c->mstride,
+                         sizeof(nm), hipMemcpyDeviceToHost));
+    n += nm;
+  }
   if (n > 0) {
     c->err = std::to_string(n) + " candidate pairs had a relative speed above g_max";
     return PIC_WARN_GMAX;
@@ -738,7 +773,8 @@ int noalloc_scratch(pic_ctx* c, double** out) {
 int err_grid(int64_t n) { return (int)std::min<int64_t>(kErrBlocks, grid_for(n)); }
 
 // Sec. 4.3 norms with the partial sums in epart ([err_grid(np)][14]), npart
-// ([err_grid(nn)][2]) and the 14 results in norms (device).
+// ([err_grid(nn)][2]) and the 14 results in norms (device; each member's in its
+// own workspace slice); out holds one entry per member.
 int errors_into(pic_ctx* c, pic_error_norms* out, double* epart, double* npart, double* norms) {
   if (!out) {
     c->err = "null output";
@@ -749,24 +785,27 @@ int errors_into(pic_ctx* c, pic_error_norms* out, double* epart, double* npart, 
   const int nbp = err_grid(K.np), nbn = err_grid(K.nn);
   int s = c->cur;
   if (c->precision == PIC_FP64)
-    k_err_particles_f64<<<nbp, kBlock, 0, c->stream>>>(K, t, c->x[s], c->v[s], c->id[s], epart,
+    k_err_particles_f64<<<G(c, nbp), kBlock, 0, c->stream>>>(K, t, c->x[s], c->v[s], c->id[s], epart,
                                                        c->flags);
   else
-    k_err_particles_mixed<<<nbp, kBlock, 0, c->stream>>>(K, t, c->key, c->off[s], c->vf[s],
+    k_err_particles_mixed<<<G(c, nbp), kBlock, 0, c->stream>>>(K, t, c->key, c->off[s], c->vf[s],
                                                          c->id[s], epart, c->flags);
-  k_err_nodes<<<nbn, kBlock, 0, c->stream>>>(K, t, c->phi, npart);
-  k_err_final<<<1, kBlock, 0, c->stream>>>(K, epart, nbp, npart, nbn, norms);
+  k_err_nodes<<<G(c, nbn), kBlock, 0, c->stream>>>(K, t, c->phi, npart);
+  k_err_final<<<G(c, 1), kBlock, 0, c->stream>>>(K, epart, nbp, npart, nbn, norms);
   LAUNCH_CHECK(c, "errors");
-  double h[14];
-  HIP_TRY(c, hipMemcpyAsync(h, norms, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   TRY(check_flags(c));
-  out->t = t;
-  for (int a = 0; a < 7; ++a) {
-    out->l2[a] = h[a];
-    out->linf[a] = h[7 + a];
-    if (!std::isfinite(h[a]) || !std::isfinite(h[7 + a])) {
-      c->err = "non-finite error norm";
-      return PIC_ENONFINITE;
+  for (int m = 0; m < c->members; ++m) {
+    double h[14];
+    HIP_TRY(c, hipMemcpy(h, (const char*)norms + (int64_t)m * c->mstride, sizeof(h),
+                         hipMemcpyDeviceToHost));
+    out[m].t = t;
+    for (int a = 0; a < 7; ++a) {
+      out[m].l2[a] = h[a];
+      out[m].linf[a] = h[7 + a];
+      if (!std::isfinite(h[a]) || !std::isfinite(h[7 + a])) {
+        c->err = "non-finite error norm";
+        return PIC_ENONFINITE;
+      }
     }
   }
   return gmax_warning(c);
@@ -792,17 +831,28 @@ int pic_workspace_size(const pic_problem* prob, const pic_discretization* disc, 
   return PIC_OK;
 }
 
-int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_discretization* disc,
-                          uint64_t seed, uint32_t replicate, int precision, void* workspace,
-                          int64_t workspace_bytes, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// A context of `members` simulations that differ only in the replicate
+// (replicate + 0 .. members - 1), each in its own slice of the workspace.
+int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* disc, uint64_t seed,
+           uint32_t replicate, int members, int precision, void* workspace, int64_t workspace_bytes,
+           void* hip_stream) {
   if (!out) {
     g_create_error = "null output pointer";
     return PIC_EINVAL;
   }
   *out = nullptr;
-  int64_t need = 0;
-  int st = pic_workspace_size(prob, disc, precision, &need);
+  if (members < 1 || members > 65535) {
+    g_create_error = "members must be in [1, 65535]";
+    return PIC_EINVAL;
+  }
+  int64_t per = 0;
+  int st = pic_workspace_size(prob, disc, precision, &per);
   if (st != PIC_OK) return st;
+  const int64_t need = align_up(per) * members;
   if (!workspace || workspace_bytes < need) {
     g_create_error = "workspace too small: need " + std::to_string(need) + " bytes";
     return PIC_ESPACE;
@@ -818,6 +868,9 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   }
   c->K = derive(prob, disc, seed, replicate);
   c->precision = precision;
+  c->members = members;
+  c->mstride = align_up(per);
+  c->K.mstride = c->mstride;
   {
     const char* e = std::getenv("PIC_UNFUSED");
     c->fused = !(e && e[0] == '1') || precision == PIC_MIXED;
@@ -833,6 +886,10 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
                                      (int)kHeavyLdsBytes) != hipSuccess) {
       (void)hipGetLastError();
       heavy = false;
+    }
+    if (members > 1) {  // ensembles run the fused passes, whose kernels take members
+      heavy = false;
+      c->fused = true;
     }
     c->heavy = heavy;
     c->heavy_bits = heavy_scale_bits(c->K.g_max, c->K.navg);
@@ -968,6 +1025,16 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     }
     (void)hipGetLastError();
   }
+  {
+    int occ = 0;
+    c->cg_members_together =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, c->cg_fn, c->cg_nt, c->cg_lds) == hipSuccess &&
+        (int64_t)occ * ncu >= (int64_t)c->cg_grid * members;
+    (void)hipGetLastError();
+    // PIC_CG_MEMBER_LAUNCHES=1: one solver launch per member even when all fit
+    if (const char* ev = std::getenv("PIC_CG_MEMBER_LAUNCHES"))
+      if (ev[0] == '1') c->cg_members_together = false;
+  }
   // PIC_CG_LOWMODES: Fourier modes per axis solved exactly before the CG (default
   // kLowDefaultK, at most kLowMaxK; 0 switches the pre-solve off).
   {
@@ -1012,17 +1079,17 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
     TRY(zero_counts(c));
     TRY(fill<double>(c, c->phi, 0.0, K.nn));
     if (c->low_k > 0) {
-      k_low_tables<<<grid_for((int64_t)3 * kLowMaxM * c->low.nmax), kBlock, 0, c->stream>>>(
+      k_low_tables<<<G(c, grid_for((int64_t)3 * kLowMaxM * c->low.nmax)), kBlock, 0, c->stream>>>(
           K, c->low, (double*)c->low.tab, (double*)c->low.mu);
       LAUNCH_CHECK(c, "low-mode tables");
     }
     // unsorted initial state in buffer 1, sorted into buffer 0
     c->cur = 1;
     if (c->precision == PIC_FP64)
-      k_init_f64<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->x[1], c->v[1], c->sh[1], c->id[1],
+      k_init_f64<<<G(c, grid_for(K.np)), kBlock, 0, c->stream>>>(K, c->x[1], c->v[1], c->sh[1], c->id[1],
                                                            c->key, c->slot, c->count);
     else
-      k_init_mixed<<<grid_for(K.np), kBlock, 0, c->stream>>>(K, c->off[1], c->vf[1], c->asf[1],
+      k_init_mixed<<<G(c, grid_for(K.np)), kBlock, 0, c->stream>>>(K, c->off[1], c->vf[1], c->asf[1],
                                                              c->id[1], c->key, c->slot, c->count);
     LAUNCH_CHECK(c, "init");
     TRY(sort_particles(c));
@@ -1042,6 +1109,37 @@ int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_disc
   return PIC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int pic_init_manufactured(pic_ctx** out, const pic_problem* prob, const pic_discretization* disc,
+                          uint64_t seed, uint32_t replicate, int precision, void* workspace,
+                          int64_t workspace_bytes, void* hip_stream) {
+  return create(out, prob, disc, seed, replicate, 1, precision, workspace, workspace_bytes,
+                hip_stream);
+}
+
+int pic_ensemble_workspace_size(const pic_problem* prob, const pic_discretization* disc,
+                                int precision, int members, int64_t* bytes) {
+  if (members < 1 || members > 65535 || !bytes) {
+    g_create_error = "members must be in [1, 65535] and bytes non-null";
+    return PIC_EINVAL;
+  }
+  int64_t per = 0;
+  const int st = pic_workspace_size(prob, disc, precision, &per);
+  if (st != PIC_OK) return st;
+  *bytes = align_up(per) * members;
+  return PIC_OK;
+}
+
+int pic_ensemble_init(pic_ctx** out, const pic_problem* prob, const pic_discretization* disc,
+                      uint64_t seed, uint32_t first_replicate, int members, int precision,
+                      void* workspace, int64_t workspace_bytes, void* hip_stream) {
+  return create(out, prob, disc, seed, first_replicate, members, precision, workspace,
+                workspace_bytes, hip_stream);
+}
+
 int pic_step(pic_ctx* c, int n_steps) {
   if (!c || !c->ready) return PIC_ESTATE;
   if (n_steps < 0) {
@@ -1056,6 +1154,7 @@ int pic_step(pic_ctx* c, int n_steps) {
 int pic_collide(pic_ctx* c, int call, double t, double* dv_avg, double* dv_src, int64_t* pairlog,
                 int64_t pairlog_cap, int64_t* pairlog_n) {
   if (!c || !c->ready) return PIC_ESTATE;
+  TRY(single_only(c, "pic_collide"));
   if ((call != 0 && call != 1) || !dv_avg || !dv_src || pairlog_cap < 0 ||
       (pairlog_cap > 0 && !pairlog)) {
     c->err = "bad pic_collide arguments";
@@ -1093,11 +1192,18 @@ int pic_collide(pic_ctx* c, int call, double t, double* dv_avg, double* dv_src, 
 
 int pic_errors(pic_ctx* c, pic_error_norms* out) {
   if (!c || !c->ready) return PIC_ESTATE;
+  TRY(single_only(c, "pic_errors"));
+  return errors_into(c, out, c->epart, c->npart, c->norms);
+}
+
+int pic_ensemble_errors(pic_ctx* c, pic_error_norms* out) {
+  if (!c || !c->ready) return PIC_ESTATE;
   return errors_into(c, out, c->epart, c->npart, c->norms);
 }
 
 int pic_errors_noalloc(pic_ctx* c, pic_error_norms* out) {
   if (!c || !c->ready) return PIC_ESTATE;
+  TRY(single_only(c, "pic_errors_noalloc"));
   const int npb = err_grid(c->K.np), nnb = err_grid(c->K.nn);
   const int64_t need = (int64_t)npb * 14 + (int64_t)nnb * 2 + 16;
   if (need > kNoAllocScratchDoubles) {
@@ -1177,6 +1283,7 @@ int pic_checkpoint_bytes(pic_ctx* c, int64_t* bytes) {
 
 int pic_checkpoint_save(pic_ctx* c, void* host_dst, int64_t bytes) {
   if (!c || !c->ready) return PIC_ESTATE;
+  TRY(single_only(c, "pic_checkpoint_save"));
   if (!host_dst || bytes != ckpt_bytes(c)) {
     c->err = "checkpoint save: buffer size must equal pic_checkpoint_bytes";
     return PIC_EINVAL;
@@ -1200,6 +1307,7 @@ int pic_checkpoint_save(pic_ctx* c, void* host_dst, int64_t bytes) {
 
 int pic_checkpoint_load(pic_ctx* c, const void* host_src, int64_t bytes) {
   if (!c || !c->ready) return PIC_ESTATE;
+  TRY(single_only(c, "pic_checkpoint_load"));
   if (!host_src || bytes < (int64_t)sizeof(CkptHeader)) {
     c->err = "checkpoint load: no header";
     return PIC_EINVAL;
@@ -1240,6 +1348,7 @@ int64_t pic_angle_buffer_bytes(int64_t capacity) {
 
 int pic_angle_log(pic_ctx* c, void* buffer, int64_t capacity) {
   if (!c || !c->ready) return PIC_ESTATE;
+  TRY(single_only(c, "pic_angle_log"));
   if (capacity < 0 || (capacity > 0 && !buffer)) {
     c->err = "angle log: a buffer is needed for a positive capacity";
     return PIC_EINVAL;
@@ -1300,7 +1409,12 @@ int pic_stats(pic_ctx* c, pic_stats_t* out) {
   unsigned long long cnt[kCntCount];
   HIP_TRY(c, hipMemcpy(&it, c->cgit, sizeof(it), hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(&rr, c->cgrr, sizeof(rr), hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipMemcpy(cnt, c->cnt, sizeof(cnt), hipMemcpyDeviceToHost));
+  for (int i = 0; i < kCntCount; ++i) cnt[i] = 0;
+  for (int m = 0; m < c->members; ++m) {
+    unsigned long long cm[kCntCount];
+    HIP_TRY(c, hipMemcpy(cm, member_ptr(c, c->cnt, m), sizeof(cm), hipMemcpyDeviceToHost));
+    for (int i = 0; i < kCntCount; ++i) cnt[i] += cm[i];
+  }
   out->step = c->step;
   out->cg_iters = it;
   out->cg_relres = rr;
@@ -1308,11 +1422,20 @@ int pic_stats(pic_ctx* c, pic_stats_t* out) {
   out->n_gmax = (int64_t)cnt[kCntGmax];
   out->cg_blocks = c->cg_grid;
   for (int d = 0; d < 3; ++d) out->cg_brick[d] = c->cg_q ? c->cg_bd[d] : 0;
+  out->cg_members_per_launch = c->cg_members_together ? c->members : 1;
   return check_flags(c);
 }
 
-int pic_get_state(pic_ctx* c, int item, void* host_dst, int64_t bytes) {
+}  // extern "C"
+
+namespace {
+
+int get_state_member(pic_ctx* c, int m, int item, void* host_dst, int64_t bytes) {
   if (!c || !c->ready) return PIC_ESTATE;
+  if (m < 0 || m >= c->members) {
+    c->err = "member index out of range";
+    return PIC_EINVAL;
+  }
   const SimConst& K = c->K;
   int64_t np = K.np, nn = K.nn;
   int64_t need;
@@ -1333,20 +1456,23 @@ int pic_get_state(pic_ctx* c, int item, void* host_dst, int64_t bytes) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int s = c->cur;
   if (c->precision == PIC_MIXED && (item == PIC_STATE_X || item == PIC_STATE_V)) {
-    k_export_mixed<<<grid_for(np), kBlock, 0, c->stream>>>(K, c->key, c->off[s], c->vf[s],
-                                                           item == PIC_STATE_X ? c->U : nullptr,
-                                                           item == PIC_STATE_V ? c->U : nullptr);
+    double* U = member_ptr(c, c->U, m);
+    k_export_mixed<<<grid_for(np), kBlock, 0, c->stream>>>(K, member_ptr(c, c->key, m),
+                                                           member_ptr(c, c->off[s], m),
+                                                           member_ptr(c, c->vf[s], m),
+                                                           item == PIC_STATE_X ? U : nullptr,
+                                                           item == PIC_STATE_V ? U : nullptr);
     LAUNCH_CHECK(c, "export");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipMemcpy(host_dst, c->U, need, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(host_dst, U, need, hipMemcpyDeviceToHost));
     return check_flags(c);
   }
   switch (item) {
-    case PIC_STATE_X: HIP_TRY(c, hipMemcpy(host_dst, c->x[s], need, hipMemcpyDeviceToHost)); break;
-    case PIC_STATE_V: HIP_TRY(c, hipMemcpy(host_dst, c->v[s], need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_X: HIP_TRY(c, hipMemcpy(host_dst, member_ptr(c, c->x[s], m), need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_V: HIP_TRY(c, hipMemcpy(host_dst, member_ptr(c, c->v[s], m), need, hipMemcpyDeviceToHost)); break;
     case PIC_STATE_ID:
     case PIC_STATE_CELL_START: {
-      const int* src = item == PIC_STATE_ID ? c->id[s] : c->cstart;
+      const int* src = member_ptr(c, item == PIC_STATE_ID ? c->id[s] : c->cstart, m);
       int64_t n = need / 8;
       std::vector<int> tmp((size_t)n);
       HIP_TRY(c, hipMemcpy(tmp.data(), src, n * 4, hipMemcpyDeviceToHost));
@@ -1354,15 +1480,28 @@ int pic_get_state(pic_ctx* c, int item, void* host_dst, int64_t bytes) {
       for (int64_t i = 0; i < n; ++i) d[i] = tmp[(size_t)i];
       break;
     }
-    case PIC_STATE_RHO: HIP_TRY(c, hipMemcpy(host_dst, c->rho, need, hipMemcpyDeviceToHost)); break;
-    case PIC_STATE_PHI: HIP_TRY(c, hipMemcpy(host_dst, c->phi, need, hipMemcpyDeviceToHost)); break;
-    case PIC_STATE_E: HIP_TRY(c, hipMemcpy(host_dst, c->E, need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_RHO: HIP_TRY(c, hipMemcpy(host_dst, member_ptr(c, c->rho, m), need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_PHI: HIP_TRY(c, hipMemcpy(host_dst, member_ptr(c, c->phi, m), need, hipMemcpyDeviceToHost)); break;
+    case PIC_STATE_E: HIP_TRY(c, hipMemcpy(host_dst, member_ptr(c, c->E, m), need, hipMemcpyDeviceToHost)); break;
   }
   return check_flags(c);
 }
 
+}  // namespace
+
+extern "C" {
+
+int pic_get_state(pic_ctx* c, int item, void* host_dst, int64_t bytes) {
+  return get_state_member(c, 0, item, host_dst, bytes);
+}
+
+int pic_ensemble_get_state(pic_ctx* c, int member, int item, void* host_dst, int64_t bytes) {
+  return get_state_member(c, member, item, host_dst, bytes);
+}
+
 int pic_set_state(pic_ctx* c, int item, const void* host_src, int64_t bytes) {
   if (!c || !c->ready) return PIC_ESTATE;
+  TRY(single_only(c, "pic_set_state"));
   if (item != PIC_STATE_X && item != PIC_STATE_V) {
     c->err = "pic_set_state: only PIC_STATE_X and PIC_STATE_V can be set";
     return PIC_EINVAL;

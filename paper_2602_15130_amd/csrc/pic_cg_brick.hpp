@@ -148,6 +148,7 @@ inline size_t brick_lds_bytes(const int bd[3]) {
 // gn0 + q nx ny (a brick never wraps inside).
 template <int Q, int NT>
 __global__ void __launch_bounds__(NT) k_cg_brick(SimConst K, CgArgs a) {
+  a = member_view(K, a);
   extern __shared__ double R[];
   __shared__ double sh[3 * (NT / 64)];
   const int bd[3] = {a.bdim[0], a.bdim[1], Q};

@@ -52,6 +52,8 @@ struct SimConst {
   double sg_coef, sg_pow;  // VHS: sigma g = sg_coef g^sg_pow
   double sigma_ref, g_ref, omega, g_max;
   double sgmax;        // (sigma g)_max over [0, g_max]
+  double sr[3];        // sigma_n vbar^(2n) / (sigma g)_max: the accept ratio in units of vbar
+  double inv_vbar;     // 1 / vbar
   double pmax;         // Algorithm 1: (sigma g)_max w dt / dV
   double w, dV, dt;
   double rho_scale;    // q w / dV
@@ -62,12 +64,31 @@ struct SimConst {
   double chi_alpha;    // VSS exponent
   double* anglog;      // scattering-angle records (chi, eps) of accepted collisions, or null
   int64_t angcap;      // records that fit
+  // Ensembles: the members of one context share every size and differ only in
+  // the replicate.  Member m = member0 + blockIdx.z uses replicate rep + m and
+  // owns the workspace bytes starting m * mstride after member 0's.
+  int member0;
+  int64_t mstride;
 };
+
+// The ensemble member a workgroup works for, and a member-0 workspace pointer
+// moved to that member's copy (null stays null).
+__device__ inline int member_of(const SimConst& K) { return K.member0 + (int)blockIdx.z; }
+template <class T>
+__device__ inline T* mem(const SimConst& K, T* p) {
+  return p ? (T*)((char*)p + (int64_t)member_of(K) * K.mstride) : p;
+}
+// The same for kernels that receive only the stride (members in blockIdx.z).
+template <class T>
+__device__ inline T* mem_z(int64_t mstride, T* p) {
+  return p ? (T*)((char*)p + (int64_t)blockIdx.z * mstride) : p;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11).  Counter layout of the random stream:
 //   c0 entity (particle id or cell), c1 step, c2 tag<<56 | call<<48 | outcome,
-//   c3 block; key = (seed, replicate).  The N_pairs uniforms of four
+//   c3 block; key = (seed, replicate; an ensemble member adds its index to
+//   the replicate).  The N_pairs uniforms of four
 //   consecutive outcomes share one block: tag NPAIRS, outcome field k / 4,
 //   word k mod 4.
 // ---------------------------------------------------------------------------
@@ -102,7 +123,8 @@ __host__ __device__ inline U64x4 philox(uint64_t c0, uint64_t c1, uint64_t c2, u
 
 __device__ inline U64x4 stream_block(const SimConst& K, uint64_t entity, uint64_t step,
                                      uint64_t tag, uint64_t call, uint64_t k, uint64_t blk) {
-  return philox(entity, step, (tag << 56) | (call << 48) | k, blk, K.seed, (uint64_t)K.rep);
+  return philox(entity, step, (tag << 56) | (call << 48) | k, blk, K.seed,
+                (uint64_t)K.rep + (uint64_t)member_of(K));
 }
 
 // [0,1) with 53 bits, (0,1) with 52 bits + 1/2, floor(U n) exactly.

@@ -1,6 +1,6 @@
 // Host-side derivation of the constants every kernel receives: the problem
 // and discretization of include/pic.h turned into SimConst (and the FP32
-// constants of one mixed-form pass).  Host code only: no launches here, so
+// constants of one mixed-form pass, including the paper family's vhat(t)).  Host code only: no launches here, so
 // host programs (the library and the test harness that runs the particle
 // pass on the CPU) share one definition.
 #pragma once
@@ -81,23 +81,73 @@ inline SimConst derive(const pic_problem* p, const pic_discretization* d, uint64
     K.sgmax = best;
   }
   K.pmax = K.sgmax * K.w * K.dt / K.dV;  // Algorithm 1
+  K.inv_vbar = 1.0 / p->vbar;
+  for (int n = 0; n < 3; ++n)
+    K.sr[n] = K.sgmax > 0.0 ? K.sigma_n[n] * std::pow(p->vbar, 2.0 * n) / K.sgmax : 0.0;
   return K;
 }
 
-inline MixConst mix_const(const SimConst& K, double tA, double tB) {
+// vhat(t) and vhat'(t) of the paper's velocity distribution (Sec. 5.2), or
+// vbar and 0 for the configuration family.
+inline void host_vhat(const SimConst& K, double t, double vh[3], double vd[3]) {
+  if (K.family == 1) {
+    for (int d = 0; d < 3; ++d) {
+      vh[d] = K.vbar;
+      vd[d] = 0.0;
+    }
+    return;
+  }
+  const double u = t / K.T;
+  vh[0] = (1.0 + 0.2 * std::sin(0.5 * kPi * u)) * K.vbar;
+  vh[1] = (1.0 + 0.2 * std::cos(kPi * u)) * K.vbar;
+  vh[2] = (1.0 + 0.2 * std::sin(1.5 * kPi * u)) * K.vbar;
+  vd[0] = 0.2 * (0.5 * kPi / K.T) * std::cos(0.5 * kPi * u) * K.vbar;
+  vd[1] = -0.2 * (kPi / K.T) * std::sin(kPi * u) * K.vbar;
+  vd[2] = 0.2 * (1.5 * kPi / K.T) * std::cos(1.5 * kPi * u) * K.vbar;
+}
+
+// FP32 constants of one mixed-form pass with arguments a: call B and its kick
+// at the end of step a.nb, call A and its kick and the drift of step a.na
+// (collide-only: call A's source at time a.tB).
+inline MixConst mix_const(const SimConst& K, const PartArgs& a) {
+  const double dt = K.dt;
+  const double tA = (double)a.na * dt, tB = ((double)a.nb + 1.0) * dt;  // the two kicks
   MixConst M;
-  M.dt = (float)K.dt;
-  M.dtqm = (float)(K.dt * K.qm);
+  std::memset(&M, 0, sizeof(M));
+  M.dt = (float)dt;
+  M.dtqm = (float)(dt * K.qm);
   for (int d = 0; d < 3; ++d) {
     M.inv_h[d] = (float)K.inv_h[d];
     M.inv_n[d] = (float)(1.0 / K.nc[d]);
-    double kd = 2.0 * kPi / K.L[d];
+    const double kd = 2.0 * kPi / K.L[d];
     M.emA[d] = (float)(K.phibar * std::exp(tA / (2.0 * K.T)) * kd);
     M.emB[d] = (float)(K.phibar * std::exp(tB / (2.0 * K.T)) * kd);
   }
   M.vbar = (float)K.vbar;
   M.src_w = (float)(K.w * K.dt / (2.0 * K.dV));
   M.sigma_ref = (float)K.sigma_ref;
+  M.inv_vbar = (float)(1.0 / K.vbar);
+  for (int n = 0; n < 3; ++n)
+    M.pc[n] = (float)(K.sigma_n[n] * std::pow(K.vbar, 2.0 * n + 1.0));
+  // kick B at t^{nb+1} (from t^{nb+1/2}), source at t^{nb+1/2}; kick A at t^{na}
+  // (to t^{na+1/2}), source at t^{na}; drift at t^{na+1/2}
+  const double thB = ((double)a.nb + 0.5) * dt, thA = ((double)a.na + 0.5) * dt;
+  const double tsrcA = (a.mode & kCollideOnly) ? a.tB : tA;
+  double vh[3], vd[3], vh2[3], vd2[3];
+  host_vhat(K, thA, vh, vd);
+  for (int d = 0; d < 3; ++d) M.vh_drift[d] = (float)vh[d];
+  if (K.family == 0) {
+    host_vhat(K, tB, vh, vd);
+    host_vhat(K, thB, vh2, vd2);
+    for (int d = 0; d < 3; ++d) M.hB[d] = (float)(K.isolate ? vh[d] - vh2[d] : 0.5 * dt * vd[d]);
+    host_vhat(K, tA, vh, vd);
+    host_vhat(K, thA, vh2, vd2);
+    for (int d = 0; d < 3; ++d) M.hA[d] = (float)(K.isolate ? vh2[d] - vh[d] : 0.5 * dt * vd[d]);
+  }
+  host_vhat(K, thB, vh, vd);
+  for (int d = 0; d < 3; ++d) M.h2B[d] = (float)((vh[d] / K.vbar) * (vh[d] / K.vbar));
+  host_vhat(K, tsrcA, vh, vd);
+  for (int d = 0; d < 3; ++d) M.h2A[d] = (float)((vh[d] / K.vbar) * (vh[d] / K.vbar));
   return M;
 }
 

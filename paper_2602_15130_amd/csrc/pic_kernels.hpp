@@ -111,7 +111,8 @@ __device__ inline double block_max(double v, double* sh) {
 // Fill kernels (used instead of hipMemsetAsync so that steps stay graph-safe).
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void k_fill(T* p, T v, int64_t n) {
+__global__ void k_fill(T* p, T v, int64_t n, int64_t mstride) {
+  p = mem_z(mstride, p);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -196,7 +197,12 @@ struct TileInit {
 
 // Pass 1: per-block exclusive scans and block totals; also fills the tile tables.
 __global__ void __launch_bounds__(kBlock) k_scan_local(const int* in, int* out, int* bsum, int n,
-                                                       TileInit ti) {
+                                                       TileInit ti, int64_t mstride) {
+  in = mem_z(mstride, in);
+  out = mem_z(mstride, out);
+  bsum = mem_z(mstride, bsum);
+  ti.c0 = mem_z(mstride, ti.c0);
+  ti.s0 = mem_z(mstride, ti.s0);
   for (int t = blockIdx.x * kBlock + threadIdx.x; t <= ti.ntiles; t += gridDim.x * kBlock) {
     ti.c0[t] = ti.ncell;
     ti.s0[t] = ti.np;
@@ -227,7 +233,10 @@ __global__ void __launch_bounds__(kBlock) k_scan_local(const int* in, int* out, 
 }
 
 // One block scans the block totals; writes the grand total to out[n].
-__global__ void __launch_bounds__(kBlock) k_scan_blocks(int* bsum, int nb, int* out, int n) {
+__global__ void __launch_bounds__(kBlock) k_scan_blocks(int* bsum, int nb, int* out, int n,
+                                                        int64_t mstride) {
+  bsum = mem_z(mstride, bsum);
+  out = mem_z(mstride, out);
   __shared__ int sh[kBlock];
   __shared__ int carry;
   if (threadIdx.x == 0) carry = 0;
@@ -259,7 +268,12 @@ __global__ void __launch_bounds__(kBlock) k_scan_blocks(int* bsum, int nb, int* 
 // cell c = j + 1 is that minimum for every t with lo < t kTileB <= hi.  Tile 0
 // starts at cell 0; tiles past the end keep the fill of pass 1.
 __global__ void __launch_bounds__(kBlock) k_scan_add(int* out, const int* bsum, int n, int* count,
-                                                     TileInit ti) {
+                                                     TileInit ti, int64_t mstride) {
+  out = mem_z(mstride, out);
+  bsum = mem_z(mstride, bsum);
+  count = mem_z(mstride, count);
+  ti.c0 = mem_z(mstride, ti.c0);
+  ti.s0 = mem_z(mstride, ti.s0);
   int base = blockIdx.x * kScanTile;
   int add = bsum[blockIdx.x];
   for (int j = threadIdx.x; j < kScanTile; j += kBlock) {
@@ -284,7 +298,12 @@ __global__ void __launch_bounds__(kBlock) k_scan_add(int* out, const int* bsum, 
 constexpr int kScatterPer = 4;
 __global__ void __launch_bounds__(kBlock) k_scatter(const int* key, const int* slot,
                                                     const int* cstart, int* tidx, int* tkey,
-                                                    int n) {
+                                                    int n, int64_t mstride) {
+  key = mem_z(mstride, key);
+  slot = mem_z(mstride, slot);
+  cstart = mem_z(mstride, cstart);
+  tidx = mem_z(mstride, tidx);
+  tkey = mem_z(mstride, tkey);
   const int base = blockIdx.x * (kBlock * kScatterPer) + threadIdx.x;
   int k[kScatterPer], sl[kScatterPer];
 #pragma unroll
@@ -331,6 +350,13 @@ __device__ inline int order_dst(const int* tidx, const int* tkey, const int* cst
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_init_f64(SimConst K, double* x, double* v, double* ash,
                                                      int* id, int* key, int* slot, int* count) {
+  x = mem(K, x);
+  v = mem(K, v);
+  ash = mem(K, ash);
+  id = mem(K, id);
+  key = mem(K, key);
+  slot = mem(K, slot);
+  count = mem(K, count);
   int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   bool valid = p < K.np;
   int kk = 0;
@@ -455,6 +481,10 @@ __device__ inline double rhs_manufactured(const SimConst& K, int i, int j, int k
 template <class MomT>
 __global__ void __launch_bounds__(kBlock) k_node_rhs(SimConst K, const MomT* mom, double t,
                                                      double* rho, double* b, double* part) {
+  mom = mem(K, mom);
+  rho = mem(K, rho);
+  b = mem(K, b);
+  part = mem(K, part);
   __shared__ double sh[kWaves];
   int n = blockIdx.x * kBlock + threadIdx.x;
   double bv = 0.0;
@@ -483,6 +513,9 @@ __global__ void __launch_bounds__(kBlock) k_node_rhs(SimConst K, const MomT* mom
 // (nbar of them), which must read zero when the solver starts.
 __global__ void __launch_bounds__(kBlock) k_sub_mean(SimConst K, double* b, const double* part,
                                                      int nparts, unsigned* bar, int nbar) {
+  b = mem(K, b);
+  part = mem(K, part);
+  bar = mem(K, bar);
   for (int t = blockIdx.x * kBlock + threadIdx.x; t < nbar; t += gridDim.x * kBlock) bar[t] = 0u;
   __shared__ double sh[kWaves];
   double acc = 0.0;
@@ -547,6 +580,27 @@ __device__ inline bool spin_until(const unsigned* addr, unsigned want, int* flag
       return false;
   }
   return true;
+}
+
+// The solver's arrays of one ensemble member.
+__device__ inline CgArgs member_view(const SimConst& K, CgArgs a) {
+  a.b = mem(K, a.b);
+  a.x = mem(K, a.x);
+  for (int i = 0; i < 2; ++i) {
+    a.r[i] = mem(K, a.r[i]);
+    a.w[i] = mem(K, a.w[i]);
+    a.s[i] = mem(K, a.s[i]);
+  }
+  a.p = mem(K, a.p);
+  a.part = mem(K, a.part);
+  a.result = mem(K, a.result);
+  a.arrive = mem(K, a.arrive);
+  a.release = mem(K, a.release);
+  a.flags = mem(K, a.flags);
+  a.iters_out = mem(K, a.iters_out);
+  a.relres_out = mem(K, a.relres_out);
+  a.pub = mem(K, a.pub);
+  return a;
 }
 
 // Waits until this wave's outstanding vector-memory operations have completed
@@ -639,6 +693,7 @@ __device__ inline double neg_lap(const SimConst& K, int i, int j, int k, const F
 }
 
 __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
+  a = member_view(K, a);
   __shared__ double sh[3 * kWaves];
   const int gsize = gridDim.x * kBlock;
   const int g0 = blockIdx.x * kBlock + threadIdx.x;
@@ -731,6 +786,9 @@ __global__ void __launch_bounds__(kBlock) k_cg(SimConst K, CgArgs a) {
 // E = -grad phi, central differences; optional FP32 copy for the mixed form.
 __global__ void __launch_bounds__(kBlock) k_gradient(SimConst K, const double* phi, double* E,
                                                      float* E32) {
+  phi = mem(K, phi);
+  E = mem(K, E);
+  E32 = mem(K, E32);
   int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= K.nn) return;
   int i, j, k;
@@ -1045,6 +1103,11 @@ __global__ void __launch_bounds__(kBlock) k_err_particles_f64(SimConst K, double
                                                               const double* x, const double* v,
                                                               const int* id, double* part,
                                                               int* flags) {
+  x = mem(K, x);
+  v = mem(K, v);
+  id = mem(K, id);
+  part = mem(K, part);
+  flags = mem(K, flags);
   __shared__ double sh[kWaves];
   double s2[6] = {0, 0, 0, 0, 0, 0}, mx[6] = {0, 0, 0, 0, 0, 0};
   bool bad = false;
@@ -1083,6 +1146,8 @@ __global__ void __launch_bounds__(kBlock) k_err_particles_f64(SimConst K, double
 
 __global__ void __launch_bounds__(kBlock) k_err_nodes(SimConst K, double t, const double* phi,
                                                       double* part) {
+  phi = mem(K, phi);
+  part = mem(K, part);
   __shared__ double sh[kWaves];
   double s2 = 0.0, mx = 0.0;
   for (int n = blockIdx.x * kBlock + threadIdx.x; n < K.nn; n += gridDim.x * kBlock) {
@@ -1103,6 +1168,9 @@ __global__ void __launch_bounds__(kBlock) k_err_nodes(SimConst K, double t, cons
 
 __global__ void __launch_bounds__(kBlock) k_err_final(SimConst K, const double* ppart, int npb,
                                                       const double* npart, int nnb, double* out) {
+  ppart = mem(K, ppart);
+  npart = mem(K, npart);
+  out = mem(K, out);
   __shared__ double sh[kWaves];
   for (int a2 = 0; a2 < 6; ++a2) {
     double s = 0.0, m = 0.0;

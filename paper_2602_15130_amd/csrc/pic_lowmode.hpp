@@ -34,6 +34,15 @@ struct LowArgs {
   double* e;            // [nz][m1][nx] coefficients back-transformed along x and z
 };
 
+// The pre-solve's tables and partial sums of one ensemble member.
+__device__ inline LowArgs member_view(const SimConst& K, LowArgs L) {
+  L.tab = mem(K, L.tab);
+  L.mu = mem(K, L.mu);
+  L.t2 = mem(K, L.t2);
+  L.e = mem(K, L.e);
+  return L;
+}
+
 // LDS of the projection pass (doubles): the x basis, a chunk of residual rows
 // (padded stride nx + 1), the slab's x projections and its y basis rows.
 __host__ __device__ inline int low_project_lds(const LowArgs& L, int nx) {
@@ -79,6 +88,8 @@ __device__ inline double low_dot(const double* u, int su, const double* v, int s
 
 __global__ void __launch_bounds__(kBlock) k_low_tables(SimConst K, LowArgs L, double* tab,
                                                        double* mu) {
+  tab = mem(K, tab);
+  mu = mem(K, mu);
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int per_axis = kLowMaxM * L.nmax;
   if (t < 3 * per_axis) {
@@ -102,6 +113,9 @@ __global__ void __launch_bounds__(kBlock) k_low_tables(SimConst K, LowArgs L, do
 //   t2[s][a][b][k] = sum_{j in slab} t1[a][j] phi_b(j).
 __global__ void __launch_bounds__(kLowThreads) k_low_project(SimConst K, LowArgs L, const double* b,
                                                         const double* x) {
+  L = member_view(K, L);
+  b = mem(K, b);
+  x = mem(K, x);
   extern __shared__ double lds[];
   const int nx = K.nc[0], ny = K.nc[1], nz = K.nc[2];
   const int m0 = L.m[0], m1 = L.m[1];
@@ -148,6 +162,7 @@ __global__ void __launch_bounds__(kLowThreads) k_low_project(SimConst K, LowArgs
 // gridDim.y: the chunks of one mode repeat its small coefficient step, and the
 // back-transforms (most of the LDS operand traffic) spread over more CUs.
 __global__ void __launch_bounds__(kLowThreads) k_low_solve(SimConst K, LowArgs L) {
+  L = member_view(K, L);
   extern __shared__ double lds[];
   const int nx = K.nc[0], nz = K.nc[2];
   const int m0 = L.m[0], m1 = L.m[1], m2 = L.m[2];
@@ -202,6 +217,8 @@ __global__ void __launch_bounds__(kLowThreads) k_low_solve(SimConst K, LowArgs L
 // Pass 3, workgroup (slab s, plane k): x(i, j, k) += sum_b phi_b(j) e[k][b][i]
 // on the slab's rows.
 __global__ void __launch_bounds__(kLowThreads) k_low_correct(SimConst K, LowArgs L, double* x) {
+  L = member_view(K, L);
+  x = mem(K, x);
   extern __shared__ double lds[];
   const int nx = K.nc[0], ny = K.nc[1];
   const int m1 = L.m[1];

@@ -1,8 +1,8 @@
-// Mixed-precision form of the step (configuration family): particle positions
-// as a cell index plus an FP32 offset in cell units, FP32 velocities, FP32
-// gather / kick / drift / collisions, per-cell FP32 deposition sums with
-// Neumaier compensation.  The inverse-CDF roots, N_pairs, the Poisson CG and
-// the error norms stay FP64.
+// Mixed-precision form of the step: particle positions as a cell index plus an
+// FP32 offset in cell units, FP32 velocities, FP32 gather / kick / drift /
+// collisions, per-cell FP32 deposition sums with Neumaier compensation.  The
+// inverse-CDF roots (for the paper's family, the manufactured positions of
+// every drift), N_pairs, the Poisson CG and the error norms stay FP64.
 #pragma once
 
 #include "pic_particle.hpp"
@@ -20,6 +20,15 @@ struct MixConst {
   float vbar;
   float src_w;             // w dt / (2 dV): source prefactor per (N - 1)
   float sigma_ref;
+  // the velocity distribution v^M = vhat(t) a of the paper's family (Sec. 5.2);
+  // configuration family: vhat = vbar, no kick term
+  float vh_drift[3];       // vhat(t^{na+1/2}), the drift's manufactured velocity per unit shape
+  float hB[3], hA[3];      // manufactured kick term per unit shape of kicks B and A:
+                           // dt vdot^M / 2 = (dt / 2) vhat'(t) a, or in isolation
+                           // mode vhat(t_to) - vhat(t_from) (Sec. 5.4.1)
+  float h2B[3], h2A[3];    // (vhat / vbar)^2 at the source times of calls B and A
+  float pc[3];             // sigma_n vbar^(2n+1): the paper-family source in units of vbar
+  float inv_vbar;
 };
 
 // Initial state (eq. mms_sol): FP64 roots, then cell + FP32 offset.  An offset
@@ -27,6 +36,13 @@ struct MixConst {
 // FP64 position falls in.
 __global__ void __launch_bounds__(kBlock) k_init_mixed(SimConst K, float* off, float* vf, float* ash,
                                                        int* id, int* key, int* slot, int* count) {
+  off = mem(K, off);
+  vf = mem(K, vf);
+  ash = mem(K, ash);
+  id = mem(K, id);
+  key = mem(K, key);
+  slot = mem(K, slot);
+  count = mem(K, count);
   int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   bool valid = p < K.np;
   int kk = 0;
@@ -35,13 +51,15 @@ __global__ void __launch_bounds__(kBlock) k_init_mixed(SimConst K, float* off, f
     init_uniforms(K, p, xi);
     manufactured_position(K, xi, 0.0, nullptr, xm);
     velocity_shape(K, xi + 3, a);
+    double vm[3], vd[3];
+    manufactured_velocity(K, a, 0.0, vm, vd);
     int c[3];
     double o[3];
     locate(K, xm, c, o);
     kk = lin(K, c[0], c[1], c[2]);
     for (int d = 0; d < 3; ++d) {
       off[d * K.np + p] = fminf((float)o[d], kOneBelow);
-      vf[d * K.np + p] = (float)(K.vbar * a[d]);
+      vf[d * K.np + p] = (float)vm[d];
       ash[d * K.np + p] = (float)a[d];
     }
     id[p] = (int)p;
@@ -134,6 +152,10 @@ __device__ inline void cic_weights_mixed(const float o[3], float w[8]) {
 __global__ void __launch_bounds__(kTileThreads) k_deposit_tiles_mixed(SimConst K, const float* off,
                                                                 const int* cstart,
                                                                 const int* tile_c0, float* mom) {
+  off = mem(K, off);
+  cstart = mem(K, cstart);
+  tile_c0 = mem(K, tile_c0);
+  mom = mem(K, mom);
   __shared__ float W[8 * kLdsSlots];
   __shared__ int sh_i[4];
   tile_range(K, tile_c0, cstart, blockIdx.x, sh_i);
@@ -173,6 +195,10 @@ __global__ void __launch_bounds__(kTileThreads) k_deposit_tiles_mixed(SimConst K
 // right-hand side of eq. poisson_mms; block partial sums of b.
 __global__ void __launch_bounds__(kBlock) k_node_rhs_mixed(SimConst K, const float* mom, double t,
                                                            double* rho, double* b, double* part) {
+  mom = mem(K, mom);
+  rho = mem(K, rho);
+  b = mem(K, b);
+  part = mem(K, part);
   __shared__ double sh[kWaves];
   int n = blockIdx.x * kBlock + threadIdx.x;
   double bv = 0.0;
@@ -218,11 +244,38 @@ __device__ inline float hs_kernel_f(float l) {
   return ((l2 * l2 + 2.0f * l2 - 1.0f) * erff(0.7071067812f * l) + 2.0f * l * (l2 + 1.0f) * phin) / l2;
 }
 
-// eq. vel_change_1c integral in FP32 for the configuration family.
-template <int SIG>
-__device__ inline void source_integral_f(const SimConst& K, const MixConst& M, const float u[3],
-                                         float out[3]) {
-  if (SIG == kSigMaxwell) {
+// eq. vel_change_3 with the paper's f_0, f_1, f_2 (Sec. 5.2 velocity
+// distribution) in FP32, in units of vbar: with u~ = u / vbar and
+// h2 = (vhat / vbar)^2 the integral is sum_n (sigma_n vbar^(2n+1)) f_n(u~, h2),
+// every term a normal FP32 number in any unit system.
+__device__ inline void paper_source_f(const SimConst& K, const MixConst& M, const float h2[3],
+                                      const float u[3], float out[3]) {
+  const float ut[3] = {u[0] * M.inv_vbar, u[1] * M.inv_vbar, u[2] * M.inv_vbar};
+  const float u2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const float H = h2[0] + h2[1] + h2[2];
+  const float mix = h2[0] * ut[0] * ut[0] + h2[1] * ut[1] * ut[1] + h2[2] * ut[2] * ut[2];
+  for (int i = 0; i < 3; ++i) {
+    const float others = h2[(i + 1) % 3] * h2[(i + 2) % 3];
+    const float f0 = -ut[i];
+    const float f1 = -0.5f * (3.0f * H + 6.0f * h2[i] + 2.0f * u2) * ut[i];
+    const float f2 = -0.25f * (15.0f * H * H + 36.0f * h2[i] * h2[i] + 24.0f * u2 * h2[i] +
+                               4.0f * u2 * u2 + 24.0f * h2[i] * H + 12.0f * u2 * H +
+                               24.0f * mix - 12.0f * others) * ut[i];
+    float r = M.pc[0] * f0;
+    if (K.n_sigma > 1) r += M.pc[1] * f1;
+    if (K.n_sigma > 2) r += M.pc[2] * f2;
+    out[i] = r;
+  }
+}
+
+// eq. vel_change_1c integral in FP32; h2 = (vhat / vbar)^2 at the call's time
+// (paper family).
+template <int FAM, int SIG>
+__device__ inline void source_integral_f(const SimConst& K, const MixConst& M, const float h2[3],
+                                         const float u[3], float out[3]) {
+  if (FAM == 0 && SIG == kSigPoly) {
+    paper_source_f(K, M, h2, u, out);
+  } else if (SIG == kSigMaxwell) {
     float c = (float)(K.sigma_ref * K.g_ref);
     for (int i = 0; i < 3; ++i) out[i] = -c * u[i];
   } else if (SIG == kSigHS) {
@@ -293,13 +346,22 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
   em[2] = -amp[2] * s[0] * s[1] * c[2];
 }
 
-// The mixed-form fused pass (configuration family), same phases as the FP64 one.
+// The mixed-form fused pass, same phases as the FP64 one.  FAM: 0 the paper's
+// manufactured family (time-dependent velocity distribution, manufactured
+// positions by FP64 root solves in every drift), 1 the configuration family.
 // Registers are capped for six waves per SIMD (measured best at 64^3: the pass
-// is latency bound, and the extra resident waves outweigh the spills).
-template <int SIG, bool FULL>
-__global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
+// is latency bound, and the extra resident waves outweigh the spills); the
+// paper family's instances (FP64 root solves in the drift and the source) get
+// four (128 VGPRs).
+template <int FAM, int SIG, bool FULL>
+__global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
+  a = member_view(K, a);
+  off = mem(K, off);
+  vf = mem(K, vf);
+  ash = mem(K, ash);
+  E32 = mem(K, E32);
   // Tile-resident copies of what the pass reads per particle more than once
   // (the velocity shape is read once, in the drift, straight from memory), and
   // the field acceleration kept from kick B for kick A; the copy-on-write
@@ -382,21 +444,27 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
     const float o[3] = {to[j], to[st + j], to[2 * st + j]};
     field_acc_at(tk[j], o, amp, acc);
   };
-  auto kick_with = [&](int j, const float acc[3], bool coll_on) {
+  // Half kick of slot j: v += (acc + <dv> - <dv^M>) / 2, plus (paper family)
+  // the manufactured term hman a with the particle's velocity shape a; h2 is
+  // (vhat / vbar)^2 at the call's source time.
+  auto kick_with = [&](int j, const float acc[3], bool coll_on, const float* h2,
+                       const float* hman, const float* sa) {
     float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
     float coll[3] = {0.0f, 0.0f, 0.0f};
     if (coll_on) {
       int n = cell_count(j);
       float I[3] = {0.0f, 0.0f, 0.0f};
       float coef = M.src_w * (float)(n - 1);
-      if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
+      if (n >= 2) source_integral_f<FAM, SIG>(K, M, h2, vp, I);
       for (int d = 0; d < 3; ++d) {
         coll[d] = D[d * st + j] * inv_navg - ((n >= 2) ? coef * I[d] : 0.0f);
         D[d * st + j] = 0.0f;  // cleared for the next call (a barrier follows every kick)
       }
     }
     for (int d = 0; d < 3; ++d) {
-      vp[d] = vp[d] + 0.5f * (acc[d] + coll[d]);
+      float nv = vp[d] + 0.5f * (acc[d] + coll[d]);
+      if constexpr (FAM == 0) nv = nv + hman[d] * sa[d];
+      vp[d] = nv;
       v0[d * st + j] = vp[d];
     }
   };
@@ -408,7 +476,7 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       int n = cell_count(j);
       float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
       float coef = M.src_w * (float)(n - 1);
-      if (n >= 2) source_integral_f<SIG>(K, M, vp, I);
+      if (n >= 2) source_integral_f<FAM, SIG>(K, M, M.h2A, vp, I);
       for (int d = 0; d < 3; ++d) {
         a.Dout[(int64_t)d * NP + s0 + j] = (double)(D[d * st + j] * inv_navg);
         a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? (double)(coef * I[d]) : 0.0;
@@ -422,13 +490,17 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       tile_run<SIG, float, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                NP, cl);
     for (int j = tid; j < ns; j += kTileThreads) {
-      float acc[3];
+      float acc[3], sa[3] = {0.0f, 0.0f, 0.0f};
+      if constexpr (FAM == 0) {
+        const int p = s0 + j;
+        for (int d = 0; d < 3; ++d) sa[d] = ash[(int64_t)d * NP + p];
+      }
       if (pre) {
         for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
       } else {
         field_acc(j, M.emB, acc);
       }
-      kick_with(j, acc, K.collisions != 0);
+      kick_with(j, acc, K.collisions != 0, M.h2B, M.hB, sa);
     }
     if (tid == 0) cl.pool_n = 0;
     __syncthreads();
@@ -457,15 +529,40 @@ __global__ void __launch_bounds__(kTileThreads, PIC_MIXED_WAVES) k_particles_mix
       } else {
         field_acc(j, M.emA, acc);
       }
-      kick_with(j, acc, K.collisions != 0);
+      kick_with(j, acc, K.collisions != 0, M.h2A, M.hA, sa);
       int c = tk[j];
       int cc[3];
       node_coords(K, c, cc[0], cc[1], cc[2]);
+      // Paper family: the manufactured term of the drift from FP64 root solves
+      // of x^M (eq. mms_sol) started at the particle's own position: dt xdot^M
+      // at t^{n+1/2}, or x^M(t^{n+1}) - x^M(t^n) in isolation mode, in cells.
+      float dman[3] = {0.0f, 0.0f, 0.0f};
+      if constexpr (FAM == 0) {
+        double xq[3], xg[3], disp[3];
+        position_uniforms(K, a.id[p], xq);
+        for (int d = 0; d < 3; ++d) xg[d] = ((double)cc[d] + (double)to[d * st + j]) * K.h[d];
+        const double t0 = (double)a.na * K.dt, th = ((double)a.na + 0.5) * K.dt,
+                     t1 = ((double)a.na + 1.0) * K.dt;
+        if (K.isolate) {
+          double xa[3], xb[3];
+          manufactured_position(K, xq, t0, xg, xa);
+          manufactured_position(K, xq, t1, xa, xb);
+          for (int d = 0; d < 3; ++d) disp[d] = xb[d] - xa[d];
+        } else {
+          double xm[3], xd[3];
+          manufactured_position(K, xq, th, xg, xm);
+          manufactured_xdot(K, xm, th, xd);
+          for (int d = 0; d < 3; ++d) disp[d] = K.dt * xd[d];
+        }
+        for (int d = 0; d < 3; ++d) dman[d] = (float)(disp[d] * K.inv_h[d]);
+      }
       float on[3];
       for (int d = 0; d < 3; ++d) {
-        // x += dt (v - v^M) in cell units; v^M = vbar a (time independent)
-        float vm = M.vbar * sa[d];
+        // x += dt (v - v^M) in cell units, v^M = vhat(t^{n+1/2}) a, plus the
+        // manufactured displacement (paper family)
+        float vm = M.vh_drift[d] * sa[d];
         float o = to[d * st + j] + M.dt * (v0[d * st + j] - vm) * M.inv_h[d];
+        if constexpr (FAM == 0) o = o + dman[d];
         float fl = floorf(o);
         o -= fl;
         int shift = (int)fl;
@@ -520,6 +617,12 @@ __global__ void __launch_bounds__(kBlock) k_err_particles_mixed(SimConst K, doub
                                                                 const float* off, const float* vf,
                                                                 const int* id, double* part,
                                                                 int* flags) {
+  key = mem(K, key);
+  off = mem(K, off);
+  vf = mem(K, vf);
+  id = mem(K, id);
+  part = mem(K, part);
+  flags = mem(K, flags);
   __shared__ double sh[kWaves];
   double s2[6] = {0, 0, 0, 0, 0, 0}, mx[6] = {0, 0, 0, 0, 0, 0};
   bool bad = false;

@@ -30,6 +30,22 @@ __global__ void __launch_bounds__(kTileThreads) k_order_tiles(SimConst K, const 
                                                               const T* as, const int* ids, T* xd,
                                                               T* vd, T* ad, int* idd, int* keyd,
                                                               T* mom, int n, int* flags) {
+  tile_c0 = mem(K, tile_c0);
+  tile_s0 = mem(K, tile_s0);
+  tidx = mem(K, tidx);
+  tkey = mem(K, tkey);
+  cstart = mem(K, cstart);
+  xs = mem(K, xs);
+  vs = mem(K, vs);
+  as = mem(K, as);
+  ids = mem(K, ids);
+  xd = mem(K, xd);
+  vd = mem(K, vd);
+  ad = mem(K, ad);
+  idd = mem(K, idd);
+  keyd = mem(K, keyd);
+  mom = mem(K, mom);
+  flags = mem(K, flags);
   constexpr int kPer = (kLdsSlots + kTileThreads - 1) / kTileThreads;
   __shared__ int lidx[kLdsSlots];
   __shared__ T W[DEP ? 8 * kLdsSlots : 1];

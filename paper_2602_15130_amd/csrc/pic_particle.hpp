@@ -79,6 +79,31 @@ struct PartArgs {
   double tB;            // collide-only: time of the source
 };
 
+// The workspace arrays of one ensemble member.  The caller's own buffers (the
+// collide-only outputs and the pair log) belong to single simulations and are
+// left as they are.
+__device__ inline PartArgs member_view(const SimConst& K, PartArgs a) {
+  a.x = mem(K, a.x);
+  a.v = mem(K, a.v);
+  a.ash = mem(K, a.ash);
+  a.id = mem(K, a.id);
+  a.key = mem(K, a.key);
+  a.slot = mem(K, a.slot);
+  a.count = mem(K, a.count);
+  a.cstart = mem(K, a.cstart);
+  a.tile_c0 = mem(K, a.tile_c0);
+  a.tile_s0 = mem(K, a.tile_s0);
+  a.E = mem(K, a.E);
+  a.gv0 = mem(K, a.gv0);
+  a.gu = mem(K, a.gu);
+  a.gD = mem(K, a.gD);
+  a.gmark = mem(K, a.gmark);
+  a.gtl = mem(K, a.gtl);
+  a.counters = mem(K, a.counters);
+  a.flags = mem(K, a.flags);
+  return a;
+}
+
 __device__ inline int lower_bound_i(const int* a, int n, int key) {
   int lo = 0, hi = n;
   while (lo < hi) {
@@ -105,6 +130,23 @@ __device__ inline R sigma_g_r(const SimConst& K, R g) {
   return r;
 }
 
+// sigma(g) g / (sigma g)_max, the accept probability of Algorithm 1.  In FP32 a
+// polynomial cross section is evaluated in units of vbar (coefficients
+// sigma_n vbar^(2n) / (sigma g)_max, relative speed g / vbar), which keeps
+// every term a normal FP32 number whatever the unit system (in SI the
+// paper's sigma_2 is ~5e-42, below FP32's normal range).
+template <int SIG, class R>
+__device__ inline R accept_ratio(const SimConst& K, R g) {
+  if constexpr (SIG == kSigPoly && sizeof(R) == 4) {
+    const R gt = g * (R)K.inv_vbar, g2 = gt * gt;
+    R r = (R)K.sr[0];
+    if (K.n_sigma > 1) r += (R)K.sr[1] * g2;
+    if (K.n_sigma > 2) r += (R)K.sr[2] * (g2 * g2);
+    return r;
+  }
+  return sigma_g_r<SIG, R>(K, g) / (R)K.sgmax;
+}
+
 // One outcome of Algorithm 1 on one cell of n particles (cell-local SoA arrays
 // with stride st).  The outcome's private velocities are copy-on-write: slot j
 // holds a private value in u when mark[j] == tag, else its value is v0[j]; the
@@ -115,7 +157,7 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
                                    int* tl, int& ntl, int st, int stu, long long* pairlog,
                                    int64_t cap, unsigned long long* counters,
                                    unsigned long long& acc, unsigned long long& gmx) {
-  const R sgmax = (R)K.sgmax, gmax = (R)K.g_max;
+  const R gmax = (R)K.g_max;
   for (int64_t m = 0; m < npairs; ++m) {
     U64x4 wa = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call,
                             (uint64_t)k, (uint64_t)(1 + 2 * m));
@@ -132,7 +174,7 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
     R dx = up[0] - uq[0], dy = up[1] - uq[1], dz = up[2] - uq[2];
     R g = sqrt(dx * dx + dy * dy + dz * dz);
     if (g > gmax) ++gmx;
-    bool ok = unif_r<R>(wa.w[2]) < sigma_g_r<SIG, R>(K, g) / sgmax;
+    bool ok = unif_r<R>(wa.w[2]) < accept_ratio<SIG, R>(K, g);
     if (ok) {
       ++acc;
       R eps = (R)2.0 * (R)kPi * unif_r<R>(wa.w[3]);
@@ -202,7 +244,7 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
                                         long long* pairlog, int64_t cap,
                                         unsigned long long* counters, unsigned long long& acc,
                                         unsigned long long& gmx) {
-  const R sgmax = (R)K.sgmax, gmax = (R)K.g_max;
+  const R gmax = (R)K.g_max;
   int cnt = 0;
   for (int m = 0; m < npairs; ++m) {
     U64x4 wa = stream_block(K, (uint64_t)cell, (uint64_t)step, kTagColl, (uint64_t)call,
@@ -224,7 +266,7 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
     R dx = up[0] - uq[0], dy = up[1] - uq[1], dz = up[2] - uq[2];
     R g = sqrt(dx * dx + dy * dy + dz * dz);
     if (g > gmax) ++gmx;
-    bool ok = unif_r<R>(wa.w[2]) < sigma_g_r<SIG, R>(K, g) / sgmax;
+    bool ok = unif_r<R>(wa.w[2]) < accept_ratio<SIG, R>(K, g);
     if (ok) {
       ++acc;
       R eps = (R)2.0 * (R)kPi * unif_r<R>(wa.w[3]);
@@ -540,6 +582,10 @@ __device__ inline void cic_weights_f64(const SimConst& K, const double xp[3], do
 __global__ void __launch_bounds__(kTileThreads) k_deposit_tiles_f64(SimConst K, const double* x,
                                                               const int* cstart,
                                                               const int* tile_c0, double* mom) {
+  x = mem(K, x);
+  cstart = mem(K, cstart);
+  tile_c0 = mem(K, tile_c0);
+  mom = mem(K, mom);
   __shared__ double W[8 * kLdsSlots];
   __shared__ int sh_i[4];
   tile_range(K, tile_c0, cstart, blockIdx.x, sh_i);
@@ -627,9 +673,13 @@ __device__ inline void field_acc_f64(const SimConst& K, const double xp[3], cons
 
 // Registers are capped for four resident waves per SIMD (128 VGPRs), accepting
 // a few spills: the pass is latency bound and gains more from resident waves
-// than it loses to spill traffic.
+// than it loses to spill traffic.  The paper family's instances (FP64 root
+// solves of the manufactured positions in the drift and its source terms) need
+// about twice the registers and get two waves per SIMD (256 VGPRs).
 template <int FAM, int SIG, bool FULL>
-__global__ void __launch_bounds__(kTileThreads, PIC_F64_WAVES) k_particles_f64(SimConst K, PartArgs a) {
+__global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
+    k_particles_f64(SimConst K, PartArgs a) {
+  a = member_view(K, a);
   // the copy-on-write scratch of outcomes run by a cell thread is global
   __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots], lacc[3 * kLdsSlots];
   __shared__ CollideLds<double, 2, 128> cl;  // both calls of the pass drawn up front

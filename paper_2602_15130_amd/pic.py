@@ -56,10 +56,17 @@ class pic_error_norms(C.Structure):
 class pic_stats_t(C.Structure):
     _fields_ = [("step", C.c_int64), ("cg_iters", C.c_int), ("cg_relres", C.c_double),
                 ("n_accepted", C.c_int64), ("n_gmax", C.c_int64),
-                ("cg_blocks", C.c_int), ("cg_brick", C.c_int * 3)]
+                ("cg_blocks", C.c_int), ("cg_brick", C.c_int * 3),
+                ("cg_members_per_launch", C.c_int)]
 
 
 def _load():
+    # torch's HIP runtime is loaded before this library's dependencies, so
+    # that the process has one runtime whatever the caller imported first
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run python -m paper_2602_15130_amd.build)")
     L = C.CDLL(LIB_PATH)
@@ -73,6 +80,12 @@ def _load():
     L.pic_stats.argtypes = [vp, P(pic_stats_t)]
     L.pic_get_state.argtypes = [vp, C.c_int, vp, i64]
     L.pic_set_state.argtypes = [vp, C.c_int, vp, i64]
+    L.pic_ensemble_workspace_size.argtypes = [P(pic_problem), P(pic_discretization), C.c_int,
+                                              C.c_int, P(i64)]
+    L.pic_ensemble_init.argtypes = [P(vp), P(pic_problem), P(pic_discretization), C.c_uint64,
+                                    C.c_uint32, C.c_int, C.c_int, vp, i64, vp]
+    L.pic_ensemble_errors.argtypes = [vp, P(pic_error_norms)]
+    L.pic_ensemble_get_state.argtypes = [vp, C.c_int, C.c_int, vp, i64]
     L.pic_errors_noalloc.argtypes = [vp, P(pic_error_norms)]
     L.pic_timing_enable.argtypes = [vp, C.c_int]
     L.pic_timing_stages.argtypes = [vp, C.c_uint32]
@@ -98,7 +111,8 @@ EXPORTED = ("pic_workspace_size", "pic_init_manufactured", "pic_step", "pic_coll
             "pic_destroy",
             "pic_angle_buffer_bytes", "pic_angle_log", "pic_angle_errors",
             "pic_checkpoint_bytes", "pic_checkpoint_save", "pic_checkpoint_load",
-            "pic_last_error")
+            "pic_ensemble_workspace_size", "pic_ensemble_init", "pic_ensemble_errors",
+            "pic_ensemble_get_state", "pic_last_error")
 STAGES = ("collide", "kick", "drift", "sort", "deposit", "cg", "gradient", "particle")
 
 
@@ -186,7 +200,8 @@ def pic_stats(ctx) -> dict:
     _check(lib.pic_stats(ctx, C.byref(s)), ctx)
     return {"step": s.step, "cg_iters": s.cg_iters, "cg_relres": s.cg_relres,
             "n_accepted": s.n_accepted, "n_gmax": s.n_gmax,
-            "cg_blocks": s.cg_blocks, "cg_brick": list(s.cg_brick)}
+            "cg_blocks": s.cg_blocks, "cg_brick": list(s.cg_brick),
+            "cg_members_per_launch": s.cg_members_per_launch}
 
 
 def pic_errors_noalloc(ctx) -> dict:
@@ -194,6 +209,36 @@ def pic_errors_noalloc(ctx) -> dict:
     e = pic_error_norms()
     st = _check(lib.pic_errors_noalloc(ctx, C.byref(e)), ctx)
     return {"t": e.t, "l2": np.array(list(e.l2)), "linf": np.array(list(e.linf)), "status": st}
+
+
+def pic_ensemble_workspace_size(prob: dict, disc: dict, precision: str, members: int) -> int:
+    b = C.c_int64()
+    _check(lib.pic_ensemble_workspace_size(C.byref(make_problem(prob)), C.byref(make_disc(disc)),
+                                           PRECISION[precision], int(members), C.byref(b)))
+    return b.value
+
+
+def pic_ensemble_init(prob, disc, seed, first_replicate, members, precision, workspace_ptr,
+                      workspace_bytes, stream_ptr):
+    ctx = C.c_void_p()
+    st = lib.pic_ensemble_init(C.byref(ctx), C.byref(make_problem(prob)), C.byref(make_disc(disc)),
+                               int(seed), int(first_replicate), int(members),
+                               PRECISION[precision], C.c_void_p(workspace_ptr),
+                               int(workspace_bytes), C.c_void_p(stream_ptr))
+    _check(st, None)
+    return ctx, st
+
+
+def pic_ensemble_errors(ctx, members: int) -> dict:
+    e = (pic_error_norms * members)()
+    st = _check(lib.pic_ensemble_errors(ctx, e), ctx)
+    return {"t": e[0].t, "l2": np.array([list(x.l2) for x in e]),
+            "linf": np.array([list(x.linf) for x in e]), "status": st}
+
+
+def pic_ensemble_get_state(ctx, member: int, item: int, out: np.ndarray):
+    _check(lib.pic_ensemble_get_state(ctx, int(member), int(item), out.ctypes.data, out.nbytes), ctx)
+    return out
 
 
 def pic_get_state(ctx, item: int, out: np.ndarray):
@@ -376,3 +421,52 @@ class Sim:
         else:
             out = np.zeros(self.nn)
         return pic_get_state(self.ctx, item, out)
+
+
+class Ensemble:
+    """`members` replicates of one problem run together (one launch per stage
+    for all of them); torch allocates the workspace, the library does the rest."""
+
+    def __init__(self, prob: dict, disc: dict, seed: int = 1, first_replicate: int = 0,
+                 members: int = 1, precision: str = "mixed", device: str = "cuda:0", stream=None):
+        import torch
+
+        self.prob, self.disc, self.precision, self.members = prob, disc, precision, int(members)
+        self.np = int(disc["np"])
+        self.nn = int(np.prod(disc["nc"]))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = pic_ensemble_workspace_size(prob, disc, precision, members)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        self._destroy = lib.pic_destroy
+        self.ctx, self.init_status = pic_ensemble_init(prob, disc, seed, first_replicate, members,
+                                                       precision, ptr, nbytes,
+                                                       self.stream.cuda_stream)
+
+    close = Sim.close
+    __enter__ = Sim.__enter__
+    __exit__ = Sim.__exit__
+    __del__ = Sim.__del__
+    step = Sim.step
+    stats = Sim.stats
+    timing = Sim.timing
+    timing_stages = Sim.timing_stages
+    timing_read = Sim.timing_read
+
+    def errors(self) -> dict:
+        """Norms of every member: l2 and linf as [members, 7] arrays."""
+        return pic_ensemble_errors(self.ctx, self.members)
+
+    def get(self, member: int, item: int) -> np.ndarray:
+        if item in (STATE_X, STATE_V):
+            out = np.zeros((3, self.np))
+        elif item == STATE_ID:
+            out = np.zeros(self.np, dtype=np.int64)
+        elif item == STATE_CELL_START:
+            out = np.zeros(self.nn + 1, dtype=np.int64)
+        elif item == STATE_E:
+            out = np.zeros((3, self.nn))
+        else:
+            out = np.zeros(self.nn)
+        return pic_ensemble_get_state(self.ctx, member, item, out)

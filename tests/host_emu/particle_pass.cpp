@@ -143,16 +143,18 @@ int main(int argc, char** argv) {
     a.callB = 1;
     a.tB = h.t;
   } else {
-    a.mode = kDoB | kDoA;
+    // modes 1 and 2: B then A; 3: A alone (the first pass of a pic_step call);
+    // 4: B alone (its last pass)
+    a.mode = h.mode == 3 ? kDoA : (h.mode == 4 ? kDoB : kDoB | kDoA);
     a.nb = h.step;
-    a.na = h.step + 1;
+    a.na = h.mode == 3 ? h.step : h.step + 1;
     a.callB = 1;
     a.callA = 0;
   }
 
+  const MixConst M = mix_const(K, a);
   std::mt19937_64 rng(h.rng_seed);
   const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
-  const MixConst M = mix_const(K, (double)h.step * K.dt, ((double)h.step + 1.0) * K.dt);
   std::function<void()> kern;
   if (h.precision == 0) {
     if (K.family == 0 && sig == kSigPoly)
@@ -164,17 +166,46 @@ int main(int argc, char** argv) {
     else
       return 4;
   } else {
-    if (sig != kSigHS) return 4;
-    kern = h.full ? std::function<void()>([&] {
-                      k_particles_mixed<kSigHS, true>(K, M, a, off.data(), vf.data(), ashf.data(),
-                                                      E32.data());
-                    })
-                  : std::function<void()>([&] {
-                      k_particles_mixed<kSigHS, false>(K, M, a, off.data(), vf.data(), ashf.data(),
-                                                       E32.data());
-                    });
+    auto mixed = [&](auto kfn) {
+      kern = [&, kfn] { kfn(K, M, a, off.data(), vf.data(), ashf.data(), E32.data()); };
+    };
+    if (K.family == 1 && sig == kSigHS)
+      h.full ? mixed(k_particles_mixed<1, kSigHS, true>) : mixed(k_particles_mixed<1, kSigHS, false>);
+    else if (K.family == 0 && sig == kSigPoly)
+      h.full ? mixed(k_particles_mixed<0, kSigPoly, true>) : mixed(k_particles_mixed<0, kSigPoly, false>);
+    else
+      return 4;
   }
-  if (h.mode == 2) {
+  if (h.mode == 5 || h.mode == 6) {
+    // the separate kernels of an A-alone (5) or B-alone (6) pass
+    if (h.precision != 0) return 4;
+    std::vector<double> D(3 * np), U(3 * np);
+    const int gn = (nn + kBlock - 1) / kBlock, gp = (int)((np + kBlock - 1) / kBlock);
+    const double dt = K.dt, s = (double)h.step;
+    auto collide = [&](int call, int64_t step) {
+      emu::run_grid(gn, kBlock, [&] {
+        k_collide_f64(K, call, step, v.data(), cs.data(), D.data(), U.data(), nullptr, 0,
+                      counters.data(), flags.data());
+      }, h.order, rng);
+    };
+    auto kick = [&](double t, double tf, double tt, double ts) {
+      emu::run_grid(gp, kBlock, [&] {
+        k_kick_f64(K, t, tf, tt, ts, x.data(), v.data(), ash.data(), id.data(), key.data(),
+                   cs.data(), E.data(), D.data());
+      }, h.order, rng);
+    };
+    if (h.mode == 5) {
+      if (K.collisions) collide(0, h.step);
+      kick(s * dt, s * dt, (s + 0.5) * dt, s * dt);
+      emu::run_grid(gp, kBlock, [&] {
+        k_drift_f64(K, s * dt, (s + 0.5) * dt, (s + 1.0) * dt, x.data(), v.data(), ash.data(),
+                    id.data(), key.data(), slot.data(), count.data(), flags.data());
+      }, h.order, rng);
+    } else {
+      if (K.collisions) collide(1, h.step);
+      kick((s + 1.0) * dt, (s + 0.5) * dt, (s + 1.0) * dt, (s + 0.5) * dt);
+    }
+  } else if (h.mode == 2) {
     if (h.precision != 0) return 4;
     // the separate kernels of the same half step, as the unfused step runs them
     std::vector<double> D(3 * np), U(3 * np);

@@ -1,14 +1,18 @@
 """Mixed-precision form (FP32 particle stages, FP64 roots / CG / norms) against
 the FP64 oracle.
 
-Bars, per quantity:
+Bars, per quantity (the FP32 error model behind them is in the design notes:
+the rounding of a step moves a velocity by at most ~5e-7 vbar and an offset by
+~1e-7 h, so 1e-5 holds for the 10 or fewer steps these tests take):
   * candidate pair lists (cell, call, outcome, pair, p, q) and cell starts at a
     common state: bit-exact (N_pairs is FP64 and index selection is integer);
-  * accept decisions: FP32 ratio vs FP64 ratio can flip only on near-ties
-    |U - sigma g / (sigma g)_max| < ~1e-6; at most a couple per case;
-  * positions: 1e-5 h, velocities: 1e-5 vbar per step taken, for particles not
-    touched by a flipped accept or a flipped cell (those are counted and must be
-    rare);
+  * accept decisions: equal, except that the first differing decision of an
+    outcome must be a near-tie |U - sigma g / (sigma g)_max| <= 2^-22 (the
+    FP32 ratio's rounding and the 24-bit uniform);
+  * positions within 1e-5 h and velocities within 1e-5 vbar for every particle
+    not touched by a cell flip; a flipped particle must lie within 1e-5 h of a
+    face of its oracle cell, and the particles of the cells a flip touches (and,
+    step by step, of the cells those share with them) are excluded and counted;
   * phi and rho: 1e-6 relative; error norms: 1e-3 relative.
 Comparisons are by particle identity because a cell flip changes the order.
 """
@@ -20,17 +24,14 @@ from paper_2602_15130_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+from mixed_compare import TOL, Tracker, by_id as _by_id  # noqa: E402
+from mixed_compare import first_flips_are_near_ties as _first_flips_are_near_ties  # noqa: E402
+from mixed_compare import sorted_pairs as _sorted_pairs  # noqa: E402
 
 
 def _pic():
     from paper_2602_15130_amd import pic
     return pic
-
-
-def _by_id(ids, arr):
-    out = np.empty_like(arr)
-    out[..., ids] = arr
-    return out
 
 
 def _pair(prob, disc, seed=1, rep=0):
@@ -39,23 +40,6 @@ def _pair(prob, disc, seed=1, rep=0):
     o = O.Sim(prob, disc, seed, rep)
     assert o.init() == 0
     return P, g, o
-
-
-def _compare(P, g, o, prob, disc, steps, max_outliers=4, tag=""):
-    h = prob["L"][0] / disc["nc"][0]
-    ig, io = g.get(P.STATE_ID), o.get(o.ID)
-    xg, xo = _by_id(ig, g.get(P.STATE_X)), _by_id(io, o.get(o.X))
-    vg, vo = _by_id(ig, g.get(P.STATE_V)), _by_id(io, o.get(o.V))
-    dx = np.abs(xg - xo)
-    dx = np.minimum(dx, prob["L"][0] - dx).max(axis=0)
-    dv = np.abs(vg - vo).max(axis=0)
-    tol_x, tol_v = 1e-5 * h * max(1, steps), 1e-5 * prob["vbar"] * max(1, steps)
-    bad = (dx > tol_x) | (dv > tol_v)
-    assert bad.sum() <= max_outliers, f"{tag}: {bad.sum()} particles beyond tolerance " \
-        f"(max dx/h {dx.max() / h:.2e}, max dv {dv.max():.2e})"
-    good = ~bad
-    assert dx[good].max() <= tol_x and dv[good].max() <= tol_v
-    return dx.max() / h, dv[good].max()
 
 
 def test_mixed_init_matches_fp64_oracle():
@@ -81,28 +65,29 @@ def test_mixed_pair_lists_bit_exact(call):
     dg, sg, pg, ng = g.collide(call, 0.0, pairlog_cap=cap)
     do, so, po, no, st = o.collide(call, 0.0, log_cap=cap)
     assert ng == no and ng > 1000
-
-    def srt(a):
-        a = np.asarray(a, dtype=np.int64).reshape(-1, 7)
-        return a[np.lexsort((a[:, 3], a[:, 2], a[:, 1], a[:, 0]))]
-
-    a, b = srt(pg), srt(po)
+    a, _ = _sorted_pairs(pg)
+    b, ties = _sorted_pairs(po, o.last_accept_test)
     np.testing.assert_array_equal(a[:, :6], b[:, :6])
-    flips = int((a[:, 6] != b[:, 6]).sum())
+    flips = _first_flips_are_near_ties(a, b, ties)
+    # <dv> per particle within the bar, except the cells of flipped outcomes
+    cs = o.get(o.CELL_START)
+    flipped_cells = np.unique(b[a[:, 6] != b[:, 6], 0])
+    keep = np.ones(disc["np"], dtype=bool)
+    for c in flipped_cells:
+        keep[cs[c]:cs[c + 1]] = False
+    assert np.abs(dg - do)[:, keep].max() <= TOL * prob["vbar"]
     assert flips <= 2
-    if flips == 0:
-        assert np.abs(dg - do).max() < 1e-5
     assert np.abs(sg - so).max() < 1e-5 * np.abs(so).max()
 
 
 def test_mixed_steps_cfg0():
     c = W.get("cfg0")
     P, g, o = _pair(c["problem"], c["disc"])
+    tr = Tracker(c["problem"], c["disc"])
     for s in range(1, 11):
         g.step(1)
         o.step(1)
-        if s in (1, 4, 10):
-            _compare(P, g, o, c["problem"], c["disc"], s, tag=f"step {s}")
+        tr.check(P, g, o, tag=f"step {s}")
     eg, eo = g.errors(), o.errors()
     np.testing.assert_allclose(eg["l2"], eo["l2"], rtol=1e-3)
     pg, po = g.get(P.STATE_PHI), o.get(o.PHI)
@@ -113,9 +98,11 @@ def test_mixed_steps_two_way_collisional():
     prob = W.cfg_problem(two_way=True, collisionality=20.0)
     disc = W.cfg_disc(8, 12000, 2e-3, 1, 6, cg_tol=1e-13)
     P, g, o = _pair(prob, disc, seed=11)
-    g.step(4)
-    o.step(4)
-    _compare(P, g, o, prob, disc, 4, tag="two-way")
+    tr = Tracker(prob, disc)
+    for s in range(1, 5):
+        g.step(1)
+        o.step(1)
+        tr.check(P, g, o, tag=f"two-way step {s}")
     rg, ro = g.get(P.STATE_RHO), o.get(o.RHO)
     assert np.abs(rg - ro).max() < 1e-5 * np.abs(ro).max()
     eg, eo = g.errors(), o.errors()
@@ -146,9 +133,11 @@ def test_mixed_large_cells_global_path():
     prob = W.cfg_problem(collisionality=2.0)
     disc = W.cfg_disc(3, 19000, 1e-3, 1, 3, cg_tol=1e-13)
     P, g, o = _pair(prob, disc, seed=8)
-    g.step(2)
-    o.step(2)
-    _compare(P, g, o, prob, disc, 2, tag="large cells")
+    tr = Tracker(prob, disc)
+    for s in (1, 2):
+        g.step(1)
+        o.step(1)
+        tr.check(P, g, o, tag=f"large cells step {s}")
 
 
 def test_mixed_full_size_cfg3_properties():
@@ -169,3 +158,37 @@ def test_mixed_full_size_cfg3_properties():
     assert rho.sum() * (1 / 64) ** 3 == pytest.approx(prob["q"] * prob["nphys"], rel=1e-6)
     e = g.errors()
     assert np.all(np.isfinite(e["l2"])) and e["l2"][0] < 1e-3
+
+
+def test_mixed_full_size_cfg3_against_oracle():
+    """The headline configuration (64^3, 8,388,608 particles, two-way, hard
+    spheres with 16 outcomes) against the FP64 oracle at full size: the
+    initial state, one collision call with its whole pair list (about 240,000
+    candidate pairs), and one time step of every particle."""
+    c = W.get("cfg3")
+    prob, disc = c["problem"], c["disc"]
+    P, g, o = _pair(prob, disc, seed=c["seed"])
+    np.testing.assert_array_equal(g.get(P.STATE_CELL_START), o.get(o.CELL_START))
+    np.testing.assert_array_equal(g.get(P.STATE_ID), o.get(o.ID))
+    h = 1 / 64
+    assert np.abs(g.get(P.STATE_X) - o.get(o.X)).max() < 2.0**-24 * h * 1.01
+    cap = 1 << 20
+    dg, sg, pg, ng = g.collide(0, 0.0, pairlog_cap=cap)
+    do, so, po, no, st = o.collide(0, 0.0, log_cap=cap)
+    assert ng == no and 100000 < ng < cap
+    a, _ = _sorted_pairs(pg)
+    b, ties = _sorted_pairs(po, o.last_accept_test)
+    np.testing.assert_array_equal(a[:, :6], b[:, :6])
+    flips = _first_flips_are_near_ties(a, b, ties)
+    cs = o.get(o.CELL_START)
+    keep = np.ones(disc["np"], dtype=bool)
+    for cell in np.unique(b[a[:, 6] != b[:, 6], 0]):
+        keep[cs[cell]:cs[cell + 1]] = False
+    assert np.abs(dg - do)[:, keep].max() <= TOL
+    assert np.abs(sg - so).max() <= 1e-5 * np.abs(so).max()
+    g.step(1)
+    o.step(1)
+    Tracker(prob, disc).check(P, g, o, tag="cfg3 step 1")
+    pgh, poh = g.get(P.STATE_PHI), o.get(o.PHI)
+    assert np.abs(pgh - poh).max() < 1e-6 * np.abs(poh).max()
+    print(f"cfg3 full size: {ng} candidate pairs, {flips} accept flips")

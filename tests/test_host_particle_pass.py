@@ -232,3 +232,18 @@ def test_mixed_collision_call_is_order_independent_and_near_oracle(harness):
     far = np.abs(a["D"] - D).max(axis=0) > 1e-5 * prob["vbar"]
     assert far.sum() <= 12, far.sum()
     assert np.abs(a["S"] - S).max() <= 1e-5 * np.abs(S).max()
+
+
+def test_mixed_paper_family_collision_call_near_oracle(harness):
+    """The mixed form with the paper's SI constants: the FP32 accept ratio and
+    source in units of vbar (the paper's sigma_2 is below FP32's normal range
+    in SI) give the oracle's accepted collisions up to near-ties, and the
+    source to FP32 accuracy."""
+    prob, disc = _paper_isolated_level1()
+    a, o = _run(harness, "product", prob, disc, 1, 0, SHUFFLE, precision=1, full=0)
+    a0 = o.accepted
+    D, S, _, _, st = o.collide(0, 0.0)
+    assert abs(a["accepted"] - (o.accepted - a0)) <= 3
+    far = np.abs(a["D"] - D).max(axis=0) > 1e-5 * prob["vbar"]
+    assert far.sum() <= 12, far.sum()
+    assert np.abs(a["S"] - S).max() <= 2e-6 * np.abs(S).max()
