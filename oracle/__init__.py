@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -340,8 +341,9 @@ class Sim:
         self.nn = int(np.prod(disc["nc"]))
         self.h = lib().orc_create(C.byref(self._P), C.byref(self._D), seed, replicate)
 
-    def __del__(self):
-        if getattr(self, "h", None):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the process releases the memory anyway
+        if getattr(self, "h", None) and not _finalizing():
             lib().orc_destroy(self.h)
             self.h = None
 

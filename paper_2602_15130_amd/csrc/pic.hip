@@ -212,6 +212,7 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   int cg_grid = 1;
   bool cg_members_together = true;  // all members' solvers co-resident in one launch
+  bool plain_cg_launch = false;     // ordinary instead of cooperative solver launches
   int cg_q = 0;                 // nodes per thread of the brick solver; 0 = global solver
   int cg_nt = kBlock;           // threads per workgroup of the solver
   const void* cg_fn = nullptr;  // the solver kernel
@@ -499,16 +500,25 @@ int field_solve(pic_ctx* c, double t) {
   }
   SimConst Kc = K;
   void* args[] = {&Kc, &a};
+  // The solver's workgroups wait for each other, so they must be co-resident:
+  // a cooperative launch guarantees it.  With plain_cg_launch the grid (sized
+  // at creation to fit by the occupancy query) is launched ordinarily; should
+  // its workgroups not all be resident, the bounded barrier wait raises the
+  // barrier flag instead of hanging.
+  auto launch = [&](dim3 grid) {
+    return c->plain_cg_launch
+               ? hipLaunchKernel(c->cg_fn, grid, dim3(c->cg_nt), args, c->cg_lds, c->stream)
+               : hipLaunchCooperativeKernel(c->cg_fn, grid, dim3(c->cg_nt), args, c->cg_lds,
+                                            c->stream);
+  };
   if (c->cg_members_together) {
     // every member's solver in one co-resident grid (members along z; each
     // member's bricks synchronise only among themselves)
-    HIP_TRY(c, hipLaunchCooperativeKernel(c->cg_fn, G(c, c->cg_grid), dim3(c->cg_nt), args,
-                                          c->cg_lds, c->stream));
+    HIP_TRY(c, launch(G(c, c->cg_grid)));
   } else {
     for (int m = 0; m < c->members; ++m) {
       Kc.member0 = m;
-      HIP_TRY(c, hipLaunchCooperativeKernel(c->cg_fn, dim3(c->cg_grid), dim3(c->cg_nt), args,
-                                            c->cg_lds, c->stream));
+      HIP_TRY(c, launch(dim3(c->cg_grid)));
     }
   }
   tm_solve.stop();
@@ -1034,6 +1044,9 @@ int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* dis
     // PIC_CG_MEMBER_LAUNCHES=1: one solver launch per member even when all fit
     if (const char* ev = std::getenv("PIC_CG_MEMBER_LAUNCHES"))
       if (ev[0] == '1') c->cg_members_together = false;
+    // PIC_CG_PLAIN_LAUNCH=1: ordinary launches of the solver (rocprofv3 ends in
+    // a crash of its own at process exit after any cooperative launch)
+    if (const char* ev = std::getenv("PIC_CG_PLAIN_LAUNCH")) c->plain_cg_launch = ev[0] == '1';
   }
   // PIC_CG_LOWMODES: Fourier modes per axis solved exactly before the CG (default
   // kLowDefaultK, at most kLowMaxK; 0 switches the pre-solve off).

@@ -1,16 +1,18 @@
 """Refinement ensembles: levels x independent replicates of the manufactured
-problem, run through the C ABI (one context per member), with the error norms
-gathered per member, their replicate mean and spread per level, and the
-observed orders of the replicate means (Sec. 4.3; the paper runs one
-simulation per level, replicates are independent Philox streams).
+problem, with the error norms per member, their replicate mean and spread per
+level, and the observed orders of the replicate means (Sec. 4.3; the paper
+runs one simulation per level, the replicates here are independent Philox
+streams, key (seed, replicate)).
 
-Host orchestration only: members of a level run concurrently on several HIP
-streams (small meshes are launch bound, large ones fill the GPU alone), and a
-small autotuner picks the Poisson solver's workgroup count per level by timing
-a few solves.
+Each level runs as ensemble contexts of the C ABI (pic_ensemble_init): all
+members of a context advance together, one launch per stage for all of them,
+so small meshes are not bound by launch latency.  A small autotuner picks the
+Poisson solver's workgroup count per member for each (device, level, members)
+by timing two steps per choice, and keeps the result in a JSON cache.
 """
 from __future__ import annotations
 
+import json
 import math
 import os
 import time
@@ -20,74 +22,150 @@ import numpy as np
 from . import pic
 from . import workloads as W
 
-CG_GRID_CHOICES = (256, 128, 64)
+# workgroups per member of the Poisson solver tried by the autotuner
+CG_GRID_CHOICES = (256, 128, 64, 32, 16, 8)
+# workspace bytes of one ensemble context at most (larger levels are split
+# into several contexts run one after the other)
+MAX_CONTEXT_BYTES = 96 << 30
 
 
-def _with_cg_blocks(blocks, fn):
-    old = os.environ.get("PIC_CG_BLOCKS")
-    if blocks:
-        os.environ["PIC_CG_BLOCKS"] = str(blocks)
+def _with_env(name, value, fn):
+    old = os.environ.get(name)
+    if value is not None:
+        os.environ[name] = str(value)
     try:
         return fn()
     finally:
         if old is None:
-            os.environ.pop("PIC_CG_BLOCKS", None)
+            os.environ.pop(name, None)
         else:
-            os.environ["PIC_CG_BLOCKS"] = old
+            os.environ[name] = old
 
 
-def autotune_cg_blocks(prob, disc, precision, choices=CG_GRID_CHOICES, steps=3):
-    """Time a few steps of replicate 0 for each solver grid size; return the
-    fastest grid and the per-choice milliseconds per step."""
+def _cache_path():
+    base = os.environ.get("PIC_TUNE_CACHE")
+    if base:
+        return base
+    root = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(root, "paper_2602_15130_amd", "tune.json")
+
+
+def _cache_key(prob, disc, precision, members):
     import torch
 
-    timings = {}
-    for blocks in choices:
-        sim = _with_cg_blocks(blocks, lambda: pic.Sim(prob, disc, 1, 0, precision))
-        sim.step(1)
+    dev = torch.cuda.get_device_name(0)
+    nc = "x".join(str(n) for n in disc["nc"])
+    return f"{dev}|{nc}|np{disc['np']}|navg{disc['navg']}|{precision}|m{members}|" \
+           f"coll{int(bool(prob.get('collisions', True)))}"
+
+
+def _load_cache():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(cache):
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only loses the cache
+
+
+def members_per_context(prob, disc, precision, members):
+    """Members one context holds within MAX_CONTEXT_BYTES (at least one)."""
+    one = pic.pic_ensemble_workspace_size(prob, disc, precision, 1)
+    return max(1, min(members, MAX_CONTEXT_BYTES // max(one, 1)))
+
+
+def _time_steps(prob, disc, precision, members, blocks, steps=2, seed=1):
+    import torch
+
+    def make():
+        return pic.Ensemble(prob, disc, seed, 0, members, precision)
+
+    with _with_env("PIC_CG_BLOCKS", blocks, make) as ens:
+        ens.step(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim.step(steps)
+        ens.step(steps)
         torch.cuda.synchronize()
-        timings[blocks] = 1e3 * (time.perf_counter() - t0) / steps
-        del sim
+        dt = time.perf_counter() - t0
+        st = ens.stats()
+    return 1e3 * dt / steps, st
+
+
+def autotune(prob, disc, precision, members, choices=CG_GRID_CHOICES, use_cache=True):
+    """The solver workgroup count per member that steps an ensemble of
+    `members` fastest; returns (blocks, {choice: ms per step}, from_cache)."""
+    key = _cache_key(prob, disc, precision, members)
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        rec = cache[key]
+        return rec["cg_blocks"], {int(k): v for k, v in rec["ms_per_step"].items()}, True
+    timings, seen = {}, set()
+    for b in choices:
+        ms, st = _time_steps(prob, disc, precision, members, b)
+        # the library fits the request to the mesh and the GPU; requests that
+        # end in the same solver grid are timed once
+        if st["cg_blocks"] in seen:
+            continue
+        seen.add(st["cg_blocks"])
+        timings[b] = ms
     best = min(timings, key=timings.get)
-    return best, timings
+    if use_cache:
+        cache = _load_cache()
+        cache[key] = {"cg_blocks": best, "ms_per_step": {str(k): v for k, v in timings.items()}}
+        _store_cache(cache)
+    return best, timings, False
 
 
-def run_level(prob, disc, precision, replicates, seed=1, streams=4, cg_blocks=None):
-    """Run every replicate of one level to its final step; returns the l2 and
-    linf norms per replicate (arrays [R, 7]) and the wall time."""
+def run_level(prob, disc, precision, replicates, seed=1, cg_blocks=None):
+    """Every replicate of one level to its final step, members of one context
+    at a time (replicates must be consecutive).  Returns the l2 and linf norms
+    per replicate ([R, 7] arrays), the stepping wall time (init and norms
+    excluded: the state is resident when the clock starts) and solver facts."""
     import torch
 
-    dev = torch.device("cuda:0")
-    pool = [torch.cuda.Stream(dev) for _ in range(max(1, streams))]
-    l2 = np.zeros((len(replicates), 7))
-    linf = np.zeros((len(replicates), 7))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for start in range(0, len(replicates), len(pool)):
-        batch = replicates[start:start + len(pool)]
-        sims = [_with_cg_blocks(cg_blocks, lambda r=r, s=s: pic.Sim(prob, disc, seed, r, precision,
-                                                                   "cuda:0", s))
-                for r, s in zip(batch, pool)]
-        for sim in sims:
-            sim.step(disc["steps"])
-        for i, sim in enumerate(sims):
-            e = sim.errors()
-            l2[start + i], linf[start + i] = e["l2"], e["linf"]
-        if start == 0:
-            st = sims[0].stats()
-            solver = {"cg_blocks": st["cg_blocks"], "cg_brick": st["cg_brick"],
-                      "cg_iters_last": st["cg_iters"]}
-        del sims
-    torch.cuda.synchronize()
-    run_level.last_solver = solver
-    return l2, linf, time.perf_counter() - t0
+    reps = list(replicates)
+    assert reps == list(range(reps[0], reps[0] + len(reps))), "consecutive replicates"
+    per = members_per_context(prob, disc, precision, len(reps))
+    l2 = np.zeros((len(reps), 7))
+    linf = np.zeros((len(reps), 7))
+    wall = 0.0
+    solver = None
+    for start in range(0, len(reps), per):
+        n = min(per, len(reps) - start)
+
+        def make(first=reps[0] + start, n=n):
+            return pic.Ensemble(prob, disc, seed, first, n, precision)
+
+        with _with_env("PIC_CG_BLOCKS", cg_blocks, make) as ens:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ens.step(disc["steps"])
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            e = ens.errors()
+            l2[start:start + n], linf[start:start + n] = e["l2"], e["linf"]
+            if solver is None:
+                st = ens.stats()
+                solver = {"cg_blocks": st["cg_blocks"], "cg_brick": st["cg_brick"],
+                          "cg_iters_last": st["cg_iters"],
+                          "cg_members_per_launch": st["cg_members_per_launch"],
+                          "members_per_context": per}
+    return l2, linf, wall, solver
 
 
-def run_ensemble(levels=None, replicates=32, precision="mixed", seed=1, streams=4, autotune=True,
-                 n_levels=5):
+def run_ensemble(levels=None, replicates=32, precision="mixed", seed=1, tune=True, n_levels=5,
+                 use_cache=True):
     """The refinement ensemble (mesh 8^3 * 2^l, 8 particles per cell, dt halved
     per level to t = 0.01, two-way coupling, hard-sphere NTC with 16 outcomes):
     per level the replicate norms, their mean and standard deviation, and the
@@ -98,23 +176,24 @@ def run_ensemble(levels=None, replicates=32, precision="mixed", seed=1, streams=
     total_ps, total_t = 0, 0.0
     for L in levels:
         prob, disc = L["problem"], L["disc"]
-        blocks, tune = (None, None)
-        if autotune and disc["nc"][0] >= 32:
-            blocks, tune = autotune_cg_blocks(prob, disc, precision)
-        nstreams = streams if disc["np"] <= (1 << 20) else 1
-        l2, linf, wall = run_level(prob, disc, precision, reps, seed, nstreams, blocks)
+        blocks, timings, cached = None, None, None
+        if tune:
+            members = min(replicates, members_per_context(prob, disc, precision, replicates))
+            blocks, timings, cached = autotune(prob, disc, precision, members, use_cache=use_cache)
+        l2, linf, wall, solver = run_level(prob, disc, precision, reps, seed, blocks)
         ps = disc["np"] * disc["steps"] * len(reps)
         total_ps += ps
         total_t += wall
         out["levels"].append({
             "mesh": disc["nc"][0], "particles": disc["np"], "steps": disc["steps"],
-            "dt": disc["dt"], "cg_blocks": blocks, "cg_tuning_ms_per_step": tune,
-            "solver": run_level.last_solver,
+            "dt": disc["dt"], "cg_blocks": solver["cg_blocks"], "cg_tuning_ms_per_step": timings,
+            "tuning_from_cache": cached, "solver": solver,
             "l2": l2.tolist(), "linf": linf.tolist(),
-            "l2_mean": l2.mean(axis=0).tolist(), "l2_std": l2.std(axis=0, ddof=1).tolist()
-            if len(reps) > 1 else [0.0] * 7,
+            "l2_mean": l2.mean(axis=0).tolist(),
+            "l2_std": l2.std(axis=0, ddof=1).tolist() if len(reps) > 1 else [0.0] * 7,
             "linf_mean": linf.mean(axis=0).tolist(),
-            "wall_s": wall, "particle_steps_per_s": ps / wall})
+            "wall_s": wall, "particle_steps_per_s": ps / wall,
+            "ms_per_step": 1e3 * wall / disc["steps"]})
     means = [lv["l2_mean"] for lv in out["levels"]]
     out["orders_l2_mean"] = W.observed_orders(means)
     out["particle_steps"] = total_ps

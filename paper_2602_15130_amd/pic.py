@@ -340,10 +340,11 @@ class Sim:
         self.close()
         return False
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter (and with it the runtime) shuts
-        # down: contexts still open then are left to the process exit
-        if sys.is_finalizing():
+        # down: contexts still open then are left to the process exit (the
+        # check is bound at definition, module globals may be gone by then)
+        if _finalizing():
             return
         self.close()
 

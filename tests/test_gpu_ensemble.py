@@ -2,7 +2,7 @@
 per level to t = 0.01, two-way coupling, hard-sphere NTC with 16 outcomes,
 independent Philox replicates): every member against the oracle on the small
 levels, the mixed form against the FP64 form member by member, the runner's
-aggregation, and the largest level (128^3, 16,777,216 particles) by properties
+aggregation and its tuning cache, and the largest level (128^3, 16,777,216 particles) by properties
 that hold at any size."""
 import numpy as np
 import pytest
@@ -23,7 +23,8 @@ def test_members_match_oracle_on_small_levels():
     for L in _levels(2):
         prob, disc = L["problem"], L["disc"]
         reps = [0, 1, 2] if disc["nc"][0] == 8 else [0, 1]
-        l2, linf, _ = ensemble.run_level(prob, disc, "fp64", reps, streams=3)
+        l2, linf, _, solver = ensemble.run_level(prob, disc, "fp64", reps)
+        assert solver["members_per_context"] == len(reps)
         for i, r in enumerate(reps):
             o = O.Sim(prob, disc, 1, r)
             assert o.init() == 0
@@ -40,21 +41,29 @@ def test_mixed_members_match_fp64_members():
     from paper_2602_15130_amd import ensemble
     for L in _levels(3):
         prob, disc = L["problem"], L["disc"]
-        a, _, _ = ensemble.run_level(prob, disc, "fp64", [0, 1], streams=2)
-        b, _, _ = ensemble.run_level(prob, disc, "mixed", [0, 1], streams=2)
+        a = ensemble.run_level(prob, disc, "fp64", [0, 1])[0]
+        b = ensemble.run_level(prob, disc, "mixed", [0, 1])[0]
         np.testing.assert_allclose(b, a, rtol=2e-3)
 
 
-def test_runner_aggregates_and_tunes():
+def test_runner_aggregates_and_tunes(tmp_path, monkeypatch):
     from paper_2602_15130_amd import ensemble
-    out = ensemble.run_ensemble(levels=_levels(3), replicates=4, precision="mixed", streams=4)
+    monkeypatch.setenv("PIC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    out = ensemble.run_ensemble(levels=_levels(3), replicates=4, precision="mixed")
     assert len(out["levels"]) == 3 and len(out["orders_l2_mean"]) == 2
     lv = out["levels"][2]
-    assert lv["mesh"] == 32 and lv["cg_blocks"] in ensemble.CG_GRID_CHOICES
+    assert lv["mesh"] == 32 and lv["tuning_from_cache"] is False
+    tuned = lv["cg_tuning_ms_per_step"]
+    assert set(tuned) <= set(ensemble.CG_GRID_CHOICES) and len(tuned) >= 1
     l2 = np.array(lv["l2"])
     assert l2.shape == (4, 7) and np.all(np.isfinite(l2)) and np.all(l2 > 0)
     np.testing.assert_allclose(lv["l2_mean"], l2.mean(axis=0))
     assert out["particle_steps"] == sum(x["particles"] * x["steps"] * 4 for x in out["levels"])
+    # the second run takes every level's choice from the cache and gives the same norms
+    again = ensemble.run_ensemble(levels=_levels(3), replicates=4, precision="mixed")
+    for a, b in zip(out["levels"], again["levels"]):
+        assert b["tuning_from_cache"] is True and b["cg_tuning_ms_per_step"] == a["cg_tuning_ms_per_step"]
+        np.testing.assert_array_equal(np.array(a["l2"]), np.array(b["l2"]))
 
 
 def test_largest_level_properties():

@@ -88,3 +88,22 @@ def test_single_member_and_single_only_calls():
         with pytest.raises(P.PicError) as ei:
             ens.get(2, P.STATE_X)
         assert ei.value.code == P.PIC_EINVAL
+
+
+@pytest.mark.parametrize("members", [1, 3])
+def test_plain_solver_launch_is_bitwise_equal(members, monkeypatch):
+    """PIC_CG_PLAIN_LAUNCH=1 launches the solver ordinarily (for profiling
+    runs): same results bit for bit, no barrier time-out raised."""
+    P = _pic()
+    L = W.ensemble_levels(2)[1]
+    prob, disc = L["problem"], L["disc"]
+    with P.Ensemble(prob, disc, 3, 0, members, "mixed") as a:
+        a.step(3)
+        ref = [[a.get(m, getattr(P, n)) for n in ITEMS] for m in range(members)]
+    monkeypatch.setenv("PIC_CG_PLAIN_LAUNCH", "1")
+    with P.Ensemble(prob, disc, 3, 0, members, "mixed") as b:
+        b.step(3)
+        assert b.stats()["step"] == 3  # pic_stats reads the flags: no barrier time-out
+        for m in range(members):
+            for n, r in zip(ITEMS, ref[m]):
+                np.testing.assert_array_equal(b.get(m, getattr(P, n)), r, err_msg=f"{m} {n}")
