@@ -38,6 +38,7 @@ enum Arr {
   A_KEY, A_SLOT, A_TIDX, A_TKEY, A_D, A_U, A_V0G,
   A_COUNT, A_CSTART, A_BSUM, A_TILE, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_CGV, A_LOW,
   A_PART_A, A_PART_B, A_EPART, A_NPART, A_NORMS, A_BAR, A_RESULT, A_FLAGS, A_CNT, A_CGIT, A_CGRR,
+  A_DEFER,
   A_NARR
 };
 
@@ -89,6 +90,7 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_CNT] = kCntCount * 8;
   b[A_CGIT] = 4;
   b[A_CGRR] = 8;
+  b[A_DEFER] = ((np + kTileB - 1) / kTileB + 2) * 4;  // tiles the lean pass leaves to the general one
   int64_t t = 0;
   for (int i = 0; i < A_NARR; ++i) {
     L.off[i] = t;
@@ -245,6 +247,8 @@ struct pic_ctx {
   double *D{}, *U{}, *V0G{};
   float* Df{};
   bool fused = true;
+  bool lean_pass = true;        // lean pass instance first, general one for the tiles it defers
+  int* defer = nullptr;         // the deferred tiles (count, done, list)
   void* mom{};
   double *rho{}, *b{}, *phi{}, *E{}, *cgv{}, *lowbuf{}, *partA{}, *partB{};
   float* E32{};
@@ -601,52 +605,77 @@ PartArgs part_args(pic_ctx* c) {
   a.gtl = c->tkey;
   a.counters = c->cnt;
   a.flags = c->flags;
+  a.defer = c->defer;
+  a.ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
+  a.defer_list = 0;
   a.callB = 1;
   a.callA = 0;
   return a;
 }
 
-// Fused pass specialised on (manufactured family, cross-section model).
+// Instances of the fused passes: the full one (angle and pair logs, the
+// anisotropic samplers), the general lean one and the lean one that leaves
+// the tiles it cannot run on lanes alone to the general one.
+using MixedFn = void (*)(SimConst, MixConst, PartArgs, float*, float*, const float*, const float*);
+using F64Fn = void (*)(SimConst, PartArgs);
+struct PassFns {
+  MixedFn mixed[3];  // full, general, fast
+  F64Fn f64[3];
+};
+template <int FAM, int SIG>
+PassFns pass_fns() {
+  return {{k_particles_mixed<FAM, SIG, true, false>, k_particles_mixed<FAM, SIG, false, false>,
+           k_particles_mixed<FAM, SIG, false, true>},
+          {k_particles_f64<FAM, SIG, true, false>, k_particles_f64<FAM, SIG, false, false>,
+           k_particles_f64<FAM, SIG, false, true>}};
+}
+PassFns select_pass(const SimConst& K) {
+  const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
+  if (K.family == 1) {
+    if (sig == kSigHS) return pass_fns<1, kSigHS>();
+    if (sig == kSigMaxwell) return pass_fns<1, kSigMaxwell>();
+    return pass_fns<1, kSigPoly>();
+  }
+  if (sig == kSigMaxwell) return pass_fns<0, kSigMaxwell>();
+  return pass_fns<0, kSigPoly>();
+}
+
+// Workgroups of the general instance that works through the deferred tiles.
+constexpr int kDeferGrid = 2048;
+
+// Fused pass: the lean instance over all tiles, then the general one over the
+// tiles it deferred; or the general (or full) instance alone, for logged runs,
+// collide-only calls and collision loads where most tiles would be deferred.
 int launch_particles(pic_ctx* c, const PartArgs& a) {
   const SimConst& K = c->K;
   const int tiles = (int)((K.np + kTileB - 1) / kTileB);
-  const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
+  const PassFns fns = select_pass(K);
+  // the collision-angle and pair-log recording and the anisotropic polar-angle
+  // samplers are compiled only into the full instances
+  const bool full = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO;
+  const bool lean = c->lean_pass && !full && !(a.mode & kCollideOnly);
+  const int which = full ? 0 : 1;
+  PartArgs ag = a;
+  ag.defer_list = lean ? 1 : 0;
+  const dim3 grid_general = G(c, lean ? std::min(tiles, kDeferGrid) : tiles);
   if (c->precision == PIC_MIXED) {
     const MixConst M = mix_const(K, a);
     const int s = c->cur;
-    // the collision-angle and pair-log recording and the anisotropic
-    // polar-angle samplers are compiled only into the full instances; the
-    // lean ones serve isotropic scattering with no log attached
-    const bool ang = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO;
-    void (*fn)(SimConst, MixConst, PartArgs, float*, float*, const float*, const float*) = nullptr;
-    if (K.family == 1) {
-      if (sig == kSigHS) fn = ang ? k_particles_mixed<1, kSigHS, true> : k_particles_mixed<1, kSigHS, false>;
-      else if (sig == kSigMaxwell)
-        fn = ang ? k_particles_mixed<1, kSigMaxwell, true> : k_particles_mixed<1, kSigMaxwell, false>;
-      else fn = ang ? k_particles_mixed<1, kSigPoly, true> : k_particles_mixed<1, kSigPoly, false>;
-    } else {
-      if (sig == kSigMaxwell)
-        fn = ang ? k_particles_mixed<0, kSigMaxwell, true> : k_particles_mixed<0, kSigMaxwell, false>;
-      else fn = ang ? k_particles_mixed<0, kSigPoly, true> : k_particles_mixed<0, kSigPoly, false>;
+    if (lean) {
+      fns.mixed[2]<<<G(c, tiles), dim3(kTileThreads), 0, c->stream>>>(K, M, a, c->off[s], c->vf[s],
+                                                                      c->asf[s], c->E32);
+      LAUNCH_CHECK(c, "particles (mixed, lean)");
     }
-    fn<<<G(c, tiles), dim3(kTileThreads), 0, c->stream>>>(K, M, a, c->off[s], c->vf[s], c->asf[s],
-                                                          c->E32);
+    fns.mixed[which]<<<grid_general, dim3(kTileThreads), 0, c->stream>>>(K, M, ag, c->off[s], c->vf[s],
+                                                                        c->asf[s], c->E32);
     LAUNCH_CHECK(c, "particles (mixed)");
     return PIC_OK;
   }
-  const bool ang = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO;
-  void (*fn)(SimConst, PartArgs) = nullptr;
-  if (K.family == 1) {
-    if (sig == kSigHS) fn = ang ? k_particles_f64<1, kSigHS, true> : k_particles_f64<1, kSigHS, false>;
-    else if (sig == kSigMaxwell)
-      fn = ang ? k_particles_f64<1, kSigMaxwell, true> : k_particles_f64<1, kSigMaxwell, false>;
-    else fn = ang ? k_particles_f64<1, kSigPoly, true> : k_particles_f64<1, kSigPoly, false>;
-  } else {
-    if (sig == kSigMaxwell)
-      fn = ang ? k_particles_f64<0, kSigMaxwell, true> : k_particles_f64<0, kSigMaxwell, false>;
-    else fn = ang ? k_particles_f64<0, kSigPoly, true> : k_particles_f64<0, kSigPoly, false>;
+  if (lean) {
+    fns.f64[2]<<<G(c, tiles), kTileThreads, 0, c->stream>>>(K, a);
+    LAUNCH_CHECK(c, "particles (lean)");
   }
-  fn<<<G(c, tiles), kTileThreads, 0, c->stream>>>(K, a);
+  fns.f64[which]<<<grid_general, kTileThreads, 0, c->stream>>>(K, ag);
   LAUNCH_CHECK(c, "particles");
   return PIC_OK;
 }
@@ -904,6 +933,14 @@ int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* dis
     c->heavy = heavy;
     c->heavy_bits = heavy_scale_bits(c->K.g_max, c->K.navg);
     if (heavy) c->fused = false;
+    // The lean pass runs a tile's outcomes on lanes only, which needs at most
+    // kSmallPairs pairs per outcome and kPool records per call; expected pool
+    // use per call of a tile is 2 N_pairs-mean N_avg (cells per tile).  Above
+    // half the pool most tiles would be deferred, so the general instance runs
+    // alone.  PIC_LEAN_PASS=0/1 overrides.
+    const double need = 2.0 * pairs * (double)c->K.navg * ((double)kTileB / std::max(nbar, 1.0));
+    c->lean_pass = !c->K.collisions || need <= 0.5 * kPool;
+    if (const char* lp = std::getenv("PIC_LEAN_PASS")) c->lean_pass = lp[0] == '1';
   }
   c->cg_tol = disc->cg_tol;
   c->cg_max_iter = disc->cg_max_iter;
@@ -955,6 +992,7 @@ int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* dis
   c->cnt = carve<unsigned long long>(c, A_CNT);
   c->cgit = carve<int>(c, A_CGIT);
   c->cgrr = carve<double>(c, A_CGRR);
+  c->defer = carve<int>(c, A_DEFER);
 
   // Cooperative grid for the Poisson solver: one block per CU at most, never
   // more than the node count needs, and never more than can be co-resident.
@@ -1087,6 +1125,7 @@ int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* dis
   auto init = [&]() -> int {
     const SimConst& K = c->K;
     TRY(fill<int>(c, c->flags, 0, kFlagCount));
+    TRY(fill<int>(c, c->defer, 0, 2));
     TRY(fill<unsigned long long>(c, c->cnt, 0ull, kCntCount));
     c->count_zero = false;
     TRY(zero_counts(c));

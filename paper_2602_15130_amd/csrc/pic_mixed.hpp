@@ -353,7 +353,7 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 // is latency bound, and the extra resident waves outweigh the spills); the
 // paper family's instances (FP64 root solves in the drift and the source) get
 // four (128 VGPRs).
-template <int FAM, int SIG, bool FULL>
+template <int FAM, int SIG, bool FULL, bool FAST>
 __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
@@ -368,232 +368,247 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : PIC_MIXED_WAVES) 
   // scratch of outcomes run by a cell thread is global.
   __shared__ float lv0[3 * kLdsSlots], lD[3 * kLdsSlots], loff[3 * kLdsSlots],
       lacc[3 * kLdsSlots];
-  __shared__ int lkey[kLdsSlots], lcn[kLdsSlots];
+  __shared__ int lkey[kLdsSlots];
+  __shared__ int lcs[kCellCache + 1];  // cell starts of a tile of at most kCellCache cells
   __shared__ CollideLds<float, 2, 128> cl;  // both calls of the pass drawn up front
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;
-  if (tid == 0) {
-    sh_i[0] = min(a.tile_c0[blockIdx.x], K.nn);
-    sh_i[1] = min(a.tile_c0[blockIdx.x + 1], K.nn);
-    sh_i[2] = a.tile_s0[blockIdx.x];
-    sh_i[3] = a.tile_s0[blockIdx.x + 1];
-    tile_lists_clear(cl);
-  }
-  __syncthreads();
-  const int c0 = sh_i[0], ncells = max(sh_i[1] - sh_i[0], 0), s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
-  if (ns <= 0) return;
-  const bool lds = ns <= kLdsSlots;
-  const int st = lds ? kLdsSlots : NP;
-  float* v0 = lds ? lv0 : (float*)a.gv0 + s0;
-  float* D = lds ? lD : (float*)a.gD + s0;
-  const float* to = lds ? loff : off + s0;   // offsets at the start of the pass
-  const int* tk = lds ? lkey : a.key + s0;   // cells at the start of the pass
-  float* u = (float*)a.gu + s0;
-  int* mark = a.gmark + s0;
-  int* tl = a.gtl + s0;
-  const float navg_f = (float)K.navg;
-  const float inv_navg = 1.0f / navg_f;  // exact for a power-of-two N_avg
-
-  // Field part of a half kick: dt q/m (E - E^M) at cell c, offset o.
-  auto field_acc_at = [&](int c, const float o[3], const float amp[3], float acc[3]) {
-    int ci, cj, ck;
-    node_coords(K, c, ci, cj, ck);
-    float ep[3], em[3];
-    gather_mixed(K, E32, ci, cj, ck, o, ep);
-    EM_mixed(M, ci, cj, ck, o, amp, em);
-    for (int d = 0; d < 3; ++d) acc[d] = M.dtqm * (ep[d] - em[d]);
-  };
-  // A tile held in LDS computes the field part of its first kick while it
-  // loads (the gather's loads then overlap the tile's other loads) and keeps
-  // it in lacc; with both halves in one pass, kick B (end of step n) and kick A
-  // (start of step n + 1) are at the same time t^{n+1} and position (no drift
-  // between them, one field solve before the pass), so kick A reuses it:
-  // bitwise what it would compute again.
-  const bool pre = lds && !(a.mode & kCollideOnly);
-  const bool reuse_A = pre && (!(a.mode & kDoB) || a.na == a.nb + 1);
-  const float* amp0 = (a.mode & kDoB) ? M.emB : M.emA;
-  const bool pass_coll = K.collisions && !(a.mode & kCollideOnly);
-  if (pass_coll) tile_zero_D(ns, st, D);
-  for (int j = tid; j < ns; j += kTileThreads) {
-    const int p = s0 + j;
-    for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + p];
-    if (lds) {
-      const int c = a.key[p];
-      const float o[3] = {off[p], off[(int64_t)NP + p], off[2 * (int64_t)NP + p]};
-      for (int d = 0; d < 3; ++d) loff[d * kLdsSlots + j] = o[d];
-      lkey[j] = c;
-      lcn[j] = a.cstart[c + 1] - a.cstart[c];
-      if (pre) {
-        float acc[3];
-        field_acc_at(c, o, amp0, acc);
-        for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
-      }
+  auto tile = [&](const int b) __attribute__((always_inline)) {
+    if (tid == 0) {
+      sh_i[0] = min(a.tile_c0[b], K.nn);
+      sh_i[1] = min(a.tile_c0[b + 1], K.nn);
+      sh_i[2] = a.tile_s0[b];
+      sh_i[3] = a.tile_s0[b + 1];
+      tile_lists_clear(cl);
     }
-  }
-  if (pass_coll) tile_draw_pass(K, a, c0, ncells, cl);
-  __syncthreads();
-  auto cell_count = [&](int j) {
-    if (lds) return lcn[j];
-    const int c = tk[j];
-    return a.cstart[c + 1] - a.cstart[c];
-  };
-
-  // Field part of a half kick at slot j (tiles not held in LDS).
-  auto field_acc = [&](int j, const float amp[3], float acc[3]) {
-    const float o[3] = {to[j], to[st + j], to[2 * st + j]};
-    field_acc_at(tk[j], o, amp, acc);
-  };
-  // Half kick of slot j: v += (acc + <dv> - <dv^M>) / 2, plus (paper family)
-  // the manufactured term hman a with the particle's velocity shape a; h2 is
-  // (vhat / vbar)^2 at the call's source time.
-  auto kick_with = [&](int j, const float acc[3], bool coll_on, const float* h2,
-                       const float* hman, const float* sa) {
-    float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
-    float coll[3] = {0.0f, 0.0f, 0.0f};
-    if (coll_on) {
-      int n = cell_count(j);
-      float I[3] = {0.0f, 0.0f, 0.0f};
-      float coef = M.src_w * (float)(n - 1);
-      if (n >= 2) source_integral_f<FAM, SIG>(K, M, h2, vp, I);
-      for (int d = 0; d < 3; ++d) {
-        coll[d] = D[d * st + j] * inv_navg - ((n >= 2) ? coef * I[d] : 0.0f);
-        D[d * st + j] = 0.0f;  // cleared for the next call (a barrier follows every kick)
-      }
-    }
-    for (int d = 0; d < 3; ++d) {
-      float nv = vp[d] + 0.5f * (acc[d] + coll[d]);
-      if constexpr (FAM == 0) nv = nv + hman[d] * sa[d];
-      vp[d] = nv;
-      v0[d * st + j] = vp[d];
-    }
-  };
-
-  if (a.mode & kCollideOnly) {
-    tile_collide<SIG, float, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                             NP, cl);
-    for (int j = tid; j < ns; j += kTileThreads) {
-      int n = cell_count(j);
-      float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
-      float coef = M.src_w * (float)(n - 1);
-      if (n >= 2) source_integral_f<FAM, SIG>(K, M, M.h2A, vp, I);
-      for (int d = 0; d < 3; ++d) {
-        a.Dout[(int64_t)d * NP + s0 + j] = (double)(D[d * st + j] * inv_navg);
-        a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? (double)(coef * I[d]) : 0.0;
-      }
-    }
-    return;
-  }
-
-  if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
-    if (K.collisions)
-      tile_run<SIG, float, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                               NP, cl);
-    for (int j = tid; j < ns; j += kTileThreads) {
-      float acc[3], sa[3] = {0.0f, 0.0f, 0.0f};
-      if constexpr (FAM == 0) {
-        const int p = s0 + j;
-        for (int d = 0; d < 3; ++d) sa[d] = ash[(int64_t)d * NP + p];
-      }
-      if (pre) {
-        for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
-      } else {
-        field_acc(j, M.emB, acc);
-      }
-      kick_with(j, acc, K.collisions != 0, M.h2B, M.hB, sa);
-    }
-    if (tid == 0) cl.pool_n = 0;
     __syncthreads();
-    if (!(a.mode & kDoA)) {
-      for (int j = tid; j < ns; j += kTileThreads)
-        for (int d = 0; d < 3; ++d) vf[(int64_t)d * NP + s0 + j] = v0[d * st + j];
+    const int c0 = sh_i[0], ncells = max(sh_i[1] - sh_i[0], 0), s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
+    if (ns <= 0) return;
+    if (FAST && ns > kLdsSlots) {  // (uniform) the general instance takes this tile
+      defer_tile(a, b);
       return;
     }
-  }
+    const bool lds = FAST || ns <= kLdsSlots;
+    const int st = lds ? kLdsSlots : NP;
+    float* v0 = lds ? lv0 : (float*)a.gv0 + s0;
+    float* D = lds ? lD : (float*)a.gD + s0;
+    const float* to = lds ? loff : off + s0;   // offsets at the start of the pass
+    const int* tk = lds ? lkey : a.key + s0;   // cells at the start of the pass
+    float* u = (float*)a.gu + s0;
+    int* mark = a.gmark + s0;
+    int* tl = a.gtl + s0;
+    const float navg_f = (float)K.navg;
+    const float inv_navg = 1.0f / navg_f;  // exact for a power-of-two N_avg
 
-  // call A at t^{na}, first half kick, drift to t^{na+1}
-  if (K.collisions)
-    tile_run<SIG, float, FULL>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
-                             st, NP, cl);
-  for (int base = 0; base < ns; base += kTileThreads) {
-    int j = base + tid;
-    bool valid = j < ns;
-    int kk = 0;
-    if (valid) {
-      int p = s0 + j;
-      // the velocity shape for the drift, loaded before the kick hides its latency
-      const float sa[3] = {ash[p], ash[(int64_t)NP + p], ash[2 * (int64_t)NP + p]};
-      float acc[3];
-      if (reuse_A) {
-        for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
-      } else {
-        field_acc(j, M.emA, acc);
-      }
-      kick_with(j, acc, K.collisions != 0, M.h2A, M.hA, sa);
-      int c = tk[j];
-      int cc[3];
-      node_coords(K, c, cc[0], cc[1], cc[2]);
-      // Paper family: the manufactured term of the drift from FP64 root solves
-      // of x^M (eq. mms_sol) started at the particle's own position: dt xdot^M
-      // at t^{n+1/2}, or x^M(t^{n+1}) - x^M(t^n) in isolation mode, in cells.
-      float dman[3] = {0.0f, 0.0f, 0.0f};
-      if constexpr (FAM == 0) {
-        double xq[3], xg[3], disp[3];
-        position_uniforms(K, a.id[p], xq);
-        for (int d = 0; d < 3; ++d) xg[d] = ((double)cc[d] + (double)to[d * st + j]) * K.h[d];
-        const double t0 = (double)a.na * K.dt, th = ((double)a.na + 0.5) * K.dt,
-                     t1 = ((double)a.na + 1.0) * K.dt;
-        if (K.isolate) {
-          double xa[3], xb[3];
-          manufactured_position(K, xq, t0, xg, xa);
-          manufactured_position(K, xq, t1, xa, xb);
-          for (int d = 0; d < 3; ++d) disp[d] = xb[d] - xa[d];
-        } else {
-          double xm[3], xd[3];
-          manufactured_position(K, xq, th, xg, xm);
-          manufactured_xdot(K, xm, th, xd);
-          for (int d = 0; d < 3; ++d) disp[d] = K.dt * xd[d];
+    // Field part of a half kick: dt q/m (E - E^M) at cell c, offset o.
+    auto field_acc_at = [&](int c, const float o[3], const float amp[3], float acc[3]) {
+      int ci, cj, ck;
+      node_coords(K, c, ci, cj, ck);
+      float ep[3], em[3];
+      gather_mixed(K, E32, ci, cj, ck, o, ep);
+      EM_mixed(M, ci, cj, ck, o, amp, em);
+      for (int d = 0; d < 3; ++d) acc[d] = M.dtqm * (ep[d] - em[d]);
+    };
+    // A tile held in LDS computes the field part of its first kick while it
+    // loads (the gather's loads then overlap the tile's other loads) and keeps
+    // it in lacc; with both halves in one pass, kick B (end of step n) and kick A
+    // (start of step n + 1) are at the same time t^{n+1} and position (no drift
+    // between them, one field solve before the pass), so kick A reuses it:
+    // bitwise what it would compute again.
+    const bool pre = lds && !(a.mode & kCollideOnly);
+    const bool reuse_A = pre && (!(a.mode & kDoB) || a.na == a.nb + 1);
+    const float* amp0 = (a.mode & kDoB) ? M.emB : M.emA;
+    const bool pass_coll = K.collisions && !(a.mode & kCollideOnly);
+    if (pass_coll) tile_zero_D(ns, st, D);
+    for (int j = tid; j < ns; j += kTileThreads) {
+      const int p = s0 + j;
+      for (int d = 0; d < 3; ++d) v0[d * st + j] = vf[(int64_t)d * NP + p];
+      if (lds) {
+        const int c = a.key[p];
+        const float o[3] = {off[p], off[(int64_t)NP + p], off[2 * (int64_t)NP + p]};
+        for (int d = 0; d < 3; ++d) loff[d * kLdsSlots + j] = o[d];
+        lkey[j] = c;
+        if (pre) {
+          float acc[3];
+          field_acc_at(c, o, amp0, acc);
+          for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
         }
-        for (int d = 0; d < 3; ++d) dman[d] = (float)(disp[d] * K.inv_h[d]);
       }
-      float on[3];
-      for (int d = 0; d < 3; ++d) {
-        // x += dt (v - v^M) in cell units, v^M = vhat(t^{n+1/2}) a, plus the
-        // manufactured displacement (paper family)
-        float vm = M.vh_drift[d] * sa[d];
-        float o = to[d * st + j] + M.dt * (v0[d * st + j] - vm) * M.inv_h[d];
-        if constexpr (FAM == 0) o = o + dman[d];
-        float fl = floorf(o);
-        o -= fl;
-        int shift = (int)fl;
-        if (o >= 1.0f) {  // a tiny negative offset rounds up to 1 after adding 1
-          o -= 1.0f;
-          shift += 1;
-        }
-        if (!(o >= 0.0f && o < 1.0f)) {  // non-finite
-          atomicOr(&a.flags[kFlagNonFinite], 1);
-          o = 0.0f;
-          shift = 0;
-        }
-        const int nd = K.nc[d];
-        if (shift >= nd || shift <= -nd) shift %= nd;  // more than a box length: rare
-        int ni = cc[d] + shift;
-        ni = ni < 0 ? ni + nd : (ni >= nd ? ni - nd : ni);
-        cc[d] = ni;
-        on[d] = o;
-      }
-      // (the global copies are written only now: in a large tile `to` and
-      // `tk` read the global arrays themselves)
-      for (int d = 0; d < 3; ++d) {
-        off[(int64_t)d * NP + p] = on[d];
-        vf[(int64_t)d * NP + p] = v0[d * st + j];
-      }
-      kk = (cc[2] * K.nc[1] + cc[1]) * K.nc[0] + cc[0];
-      a.key[p] = kk;
     }
-    int sl = wave_aggregated_slot(a.count, kk, valid);
-    if (valid) a.slot[s0 + j] = sl;
-  }
+    const bool few_cells = ncells <= kCellCache;
+    if (few_cells)
+      for (int i = tid; i <= ncells; i += kTileThreads) lcs[i] = a.cstart[c0 + i];
+    if (pass_coll) tile_draw_pass(K, a, c0, ncells, cl);
+    __syncthreads();
+    if (FAST && pass_coll &&
+        !tile_lane_only(cl, (a.mode & kDoB) ? 0 : 1, (a.mode & kDoA) ? 2 : 1)) {
+      defer_tile(a, b);  // (uniform, and nothing written to memory yet)
+      return;
+    }
+    auto cell_count = [&](int j) {
+      const int c = tk[j];
+      if (few_cells) return lcs[c - c0 + 1] - lcs[c - c0];
+      return a.cstart[c + 1] - a.cstart[c];
+    };
+
+    // Field part of a half kick at slot j (tiles not held in LDS).
+    auto field_acc = [&](int j, const float amp[3], float acc[3]) {
+      const float o[3] = {to[j], to[st + j], to[2 * st + j]};
+      field_acc_at(tk[j], o, amp, acc);
+    };
+    // Half kick of slot j: v += (acc + <dv> - <dv^M>) / 2, plus (paper family)
+    // the manufactured term hman a with the particle's velocity shape a; h2 is
+    // (vhat / vbar)^2 at the call's source time.
+    auto kick_with = [&](int j, const float acc[3], bool coll_on, const float* h2,
+                         const float* hman, const float* sa) {
+      float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
+      float coll[3] = {0.0f, 0.0f, 0.0f};
+      if (coll_on) {
+        int n = cell_count(j);
+        float I[3] = {0.0f, 0.0f, 0.0f};
+        float coef = M.src_w * (float)(n - 1);
+        if (n >= 2) source_integral_f<FAM, SIG>(K, M, h2, vp, I);
+        for (int d = 0; d < 3; ++d) {
+          coll[d] = D[d * st + j] * inv_navg - ((n >= 2) ? coef * I[d] : 0.0f);
+          D[d * st + j] = 0.0f;  // cleared for the next call (a barrier follows every kick)
+        }
+      }
+      for (int d = 0; d < 3; ++d) {
+        float nv = vp[d] + 0.5f * (acc[d] + coll[d]);
+        if constexpr (FAM == 0) nv = nv + hman[d] * sa[d];
+        vp[d] = nv;
+        v0[d * st + j] = vp[d];
+      }
+    };
+
+    if (!FAST && (a.mode & kCollideOnly)) {  // (the lean instance never runs collide-only)
+      tile_collide<SIG, float, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+                               NP, cl);
+      for (int j = tid; j < ns; j += kTileThreads) {
+        int n = cell_count(j);
+        float vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
+        float coef = M.src_w * (float)(n - 1);
+        if (n >= 2) source_integral_f<FAM, SIG>(K, M, M.h2A, vp, I);
+        for (int d = 0; d < 3; ++d) {
+          a.Dout[(int64_t)d * NP + s0 + j] = (double)(D[d * st + j] * inv_navg);
+          a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? (double)(coef * I[d]) : 0.0;
+        }
+      }
+      return;
+    }
+
+    if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
+      if (K.collisions)
+        tile_run<SIG, float, FULL, FAST>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+                                 NP, cl);
+      for (int j = tid; j < ns; j += kTileThreads) {
+        float acc[3], sa[3] = {0.0f, 0.0f, 0.0f};
+        if constexpr (FAM == 0) {
+          const int p = s0 + j;
+          for (int d = 0; d < 3; ++d) sa[d] = ash[(int64_t)d * NP + p];
+        }
+        if (pre) {
+          for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
+        } else {
+          field_acc(j, M.emB, acc);
+        }
+        kick_with(j, acc, K.collisions != 0, M.h2B, M.hB, sa);
+      }
+      if (tid == 0) cl.pool_n = 0;
+      __syncthreads();
+      if (!(a.mode & kDoA)) {
+        for (int j = tid; j < ns; j += kTileThreads)
+          for (int d = 0; d < 3; ++d) vf[(int64_t)d * NP + s0 + j] = v0[d * st + j];
+        return;
+      }
+    }
+
+    // call A at t^{na}, first half kick, drift to t^{na+1}
+    if (K.collisions)
+      tile_run<SIG, float, FULL, FAST>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+                               st, NP, cl);
+    for (int base = 0; base < ns; base += kTileThreads) {
+      int j = base + tid;
+      bool valid = j < ns;
+      int kk = 0;
+      if (valid) {
+        int p = s0 + j;
+        // the velocity shape for the drift, loaded before the kick hides its latency
+        const float sa[3] = {ash[p], ash[(int64_t)NP + p], ash[2 * (int64_t)NP + p]};
+        float acc[3];
+        if (reuse_A) {
+          for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
+        } else {
+          field_acc(j, M.emA, acc);
+        }
+        kick_with(j, acc, K.collisions != 0, M.h2A, M.hA, sa);
+        int c = tk[j];
+        int cc[3];
+        node_coords(K, c, cc[0], cc[1], cc[2]);
+        // Paper family: the manufactured term of the drift from FP64 root solves
+        // of x^M (eq. mms_sol) started at the particle's own position: dt xdot^M
+        // at t^{n+1/2}, or x^M(t^{n+1}) - x^M(t^n) in isolation mode, in cells.
+        float dman[3] = {0.0f, 0.0f, 0.0f};
+        if constexpr (FAM == 0) {
+          double xq[3], xg[3], disp[3];
+          position_uniforms(K, a.id[p], xq);
+          for (int d = 0; d < 3; ++d) xg[d] = ((double)cc[d] + (double)to[d * st + j]) * K.h[d];
+          const double t0 = (double)a.na * K.dt, th = ((double)a.na + 0.5) * K.dt,
+                       t1 = ((double)a.na + 1.0) * K.dt;
+          if (K.isolate) {
+            double xa[3], xb[3];
+            manufactured_position(K, xq, t0, xg, xa);
+            manufactured_position(K, xq, t1, xa, xb);
+            for (int d = 0; d < 3; ++d) disp[d] = xb[d] - xa[d];
+          } else {
+            double xm[3], xd[3];
+            manufactured_position(K, xq, th, xg, xm);
+            manufactured_xdot(K, xm, th, xd);
+            for (int d = 0; d < 3; ++d) disp[d] = K.dt * xd[d];
+          }
+          for (int d = 0; d < 3; ++d) dman[d] = (float)(disp[d] * K.inv_h[d]);
+        }
+        float on[3];
+        for (int d = 0; d < 3; ++d) {
+          // x += dt (v - v^M) in cell units, v^M = vhat(t^{n+1/2}) a, plus the
+          // manufactured displacement (paper family)
+          float vm = M.vh_drift[d] * sa[d];
+          float o = to[d * st + j] + M.dt * (v0[d * st + j] - vm) * M.inv_h[d];
+          if constexpr (FAM == 0) o = o + dman[d];
+          float fl = floorf(o);
+          o -= fl;
+          int shift = (int)fl;
+          if (o >= 1.0f) {  // a tiny negative offset rounds up to 1 after adding 1
+            o -= 1.0f;
+            shift += 1;
+          }
+          if (!(o >= 0.0f && o < 1.0f)) {  // non-finite
+            atomicOr(&a.flags[kFlagNonFinite], 1);
+            o = 0.0f;
+            shift = 0;
+          }
+          const int nd = K.nc[d];
+          if (shift >= nd || shift <= -nd) shift %= nd;  // more than a box length: rare
+          int ni = cc[d] + shift;
+          ni = ni < 0 ? ni + nd : (ni >= nd ? ni - nd : ni);
+          cc[d] = ni;
+          on[d] = o;
+        }
+        // (the global copies are written only now: in a large tile `to` and
+        // `tk` read the global arrays themselves)
+        for (int d = 0; d < 3; ++d) {
+          off[(int64_t)d * NP + p] = on[d];
+          vf[(int64_t)d * NP + p] = v0[d * st + j];
+        }
+        kk = (cc[2] * K.nc[1] + cc[1]) * K.nc[0] + cc[0];
+        a.key[p] = kk;
+      }
+      int sl = wave_aggregated_slot(a.count, kk, valid);
+      if (valid) a.slot[s0 + j] = sl;
+    }
+  };
+  tile_sweep<FAST>(a, tile);
 }
 
 // Positions and velocities exported as FP64 (component-major).

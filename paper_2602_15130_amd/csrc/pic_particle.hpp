@@ -28,6 +28,7 @@ namespace pic {
 
 constexpr int kSmallPairs = 4;    // outcomes with at most this many pairs run one per lane
 constexpr int kPool = 64;         // velocity-change records of those outcomes per tile
+constexpr int kCellCache = 64;    // cells of a tile whose starts the mixed pass keeps in LDS
 
 // LDS of one collision call over a tile: the events ((cell, outcome) lanes
 // with candidate pairs), their pair counts, and the velocity changes of the
@@ -39,11 +40,11 @@ constexpr int kPool = 64;         // velocity-change records of those outcomes p
 template <class R, int NL, int CAP>
 struct CollideLds {
   static constexpr int kLists = NL, kCap = CAP;
-  int evc[NL][CAP];  // tile-local cell of the event
-  int evk[NL][CAP];  // its outcome
-  int evn[NL][CAP];  // its N_pairs
+  int evck[NL][CAP];  // tile-local cell of the event << 16 | its outcome
+  int evn[NL][CAP];   // its N_pairs
   int evp[CAP];      // records of the list being run
   int n_evt[NL], overflow[NL], pool_n;
+  int need[NL], big[NL];  // pool records the list's outcomes need; an outcome over kSmallPairs
   int pslot[kPool];
   R pdv[3 * kPool];
 };
@@ -73,6 +74,11 @@ struct PartArgs {
   int64_t cap;
   unsigned long long* counters;
   int* flags;
+  // tiles the lean instance leaves to the general one: [0] count, [1] workgroups
+  // done with the list, [2 ..] tile indices; the general instance works through
+  // the list when defer_list is set, else through all tiles
+  int* defer;
+  int ntiles, defer_list;
   int mode;
   int64_t nb, na;       // step index of call B (second half) and of call A (first half)
   int callB, callA;     // random-stream call tags (collide-only mode uses callA)
@@ -101,7 +107,43 @@ __device__ inline PartArgs member_view(const SimConst& K, PartArgs a) {
   a.gtl = mem(K, a.gtl);
   a.counters = mem(K, a.counters);
   a.flags = mem(K, a.flags);
+  a.defer = mem(K, a.defer);
   return a;
+}
+
+// Hands tile b to the general instance (thread 0; the caller returns uniformly).
+__device__ inline void defer_tile(const PartArgs& a, int b) {
+  if (threadIdx.x == 0) {
+    const int i = atomicAdd(&a.defer[0], 1);
+    if (i < a.ntiles) a.defer[2 + i] = b;
+  }
+}
+
+// The tiles of one launch: the lean instance (FAST) and a plain general launch
+// take tile blockIdx.x; the general instance after a lean one takes the
+// deferred tiles, workgroup-strided, and its last workgroup (per member)
+// empties the list for the next pass.
+template <bool FAST, class F>
+__device__ __attribute__((always_inline)) inline void tile_sweep(const PartArgs& a, F&& tile) {
+  const bool list = !FAST && a.defer_list;
+  int* dl = a.defer;
+  const int n = list ? min(__hip_atomic_load(&dl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                           a.ntiles)
+                     : (int)blockIdx.x + 1;
+  for (int i = blockIdx.x; i < n; i += list ? (int)gridDim.x : 1) {
+    tile(list ? dl[2 + i] : i);
+    if (list) __syncthreads();
+  }
+  if (list) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd((unsigned*)&dl[1], 1u) == gridDim.x - 1) {
+        dl[0] = 0;
+        dl[1] = 0;
+      }
+    }
+  }
 }
 
 __device__ inline int lower_bound_i(const int* a, int n, int key) {
@@ -309,8 +351,8 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
 // is read).  Outcomes already run by a lane contribute their stored changes;
 // the others run here.  Only the particles an outcome changed contribute to
 // the sum; the others would add exact zeros.
-template <int SIG, class R, bool FULL, class Lds>
-__device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
+template <int SIG, class R, bool FULL, bool LANE_ONLY, class Lds>
+__device__ __attribute__((always_inline)) inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
                                      int c, int ci, int cs, int n, const R* v0, R* u, R* D,
                                      int* mark, int* tl, int tagbase, int st, int stu,
                                      const Lds& L, int li, int ne, bool all,
@@ -325,7 +367,7 @@ __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int c
     } else {  // next event of this cell in increasing outcome order
       k = navg;
       for (int e = 0; e < ne; ++e) {
-        const int eci = L.evc[li][e], ek = L.evk[li][e];
+        const int eci = L.evck[li][e] >> 16, ek = L.evck[li][e] & 0xffff;
         if (eci == ci && ek > last && ek < k) {
           k = ek;
           ev = e;
@@ -334,7 +376,7 @@ __device__ inline void cell_outcomes(const SimConst& K, const PartArgs& a, int c
       if (k == navg) break;
     }
     last = k;
-    if (ev >= 0 && L.evp[ev] >= 0) {  // run by a lane: add its stored changes
+    if (LANE_ONLY || (ev >= 0 && L.evp[ev] >= 0)) {  // run by a lane: add its stored changes
       const int r0 = L.evp[ev] & 0xffff, nr = L.evp[ev] >> 16;
       for (int t = 0; t < nr; ++t) {
         int j = cs + L.pslot[r0 + t];
@@ -426,11 +468,13 @@ __device__ inline void tile_draw(const SimConst& K, const PartArgs& a, int lo, i
       if (k >= navg) break;
       int64_t np_ = npairs_from(K, n, w.w[kk], a.flags);
       if (np_ > 0) {
-        int e = atomicAdd(&L.n_evt[li], 1);
+        // (cells and outcomes beyond 16 bits go the overflow way)
+        int e = ci < 0x8000 && k < 0x10000 ? atomicAdd(&L.n_evt[li], 1) : Lds::kCap;
         if (e < Lds::kCap) {
-          L.evc[li][e] = ci;
-          L.evk[li][e] = k;
+          L.evck[li][e] = ci << 16 | k;
           L.evn[li][e] = (int)np_;
+          if (np_ > kSmallPairs) L.big[li] = 1;
+          else atomicAdd(&L.need[li], 2 * (int)np_);
         } else {
           L.overflow[li] = 1;
         }
@@ -446,29 +490,30 @@ __device__ inline void tile_draw(const SimConst& K, const PartArgs& a, int lo, i
 // caller has zeroed D[0, ns) and the record pool count before a barrier (each
 // block-wide barrier costs the whole tile its slowest wave, so none is spent
 // on that here).
-template <int SIG, class R, bool FULL, class Lds>
-__device__ inline void tile_run(const SimConst& K, const PartArgs& a, int li, int call,
+template <int SIG, class R, bool FULL, bool LANE_ONLY, class Lds>
+__device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K, const PartArgs& a, int li, int call,
                                 int64_t step, int c0, int ncells, int s0, int ns, const R* v0,
                                 R* u, R* D, int* mark, int* tl, int tagbase, int st, int stu,
                                 Lds& L) {
   const int tid = threadIdx.x;
   const int ne = min(L.n_evt[li], Lds::kCap);
-  const bool all = L.overflow[li] != 0;
+  // LANE_ONLY: the caller has checked tile_lane_only, so every event runs on a lane
+  const bool all = !LANE_ONLY && L.overflow[li] != 0;
   unsigned long long acc = 0, gmx = 0;
   // small outcomes, one per lane, into the record pool
   if (!all) {
     for (int e = tid; e < ne; e += kTileThreads) {
       int np_ = L.evn[li][e];
       int start = -1;
-      if (np_ <= kSmallPairs) {
+      if (LANE_ONLY || np_ <= kSmallPairs) {
         start = atomicAdd(&L.pool_n, 2 * np_);
-        if (start + 2 * np_ > kPool) start = -1;
+        if (!LANE_ONLY && start + 2 * np_ > kPool) start = -1;
       }
-      if (start < 0) {
+      if (!LANE_ONLY && start < 0) {
         L.evp[e] = -1;
         continue;
       }
-      int ci = L.evc[li][e], k = L.evk[li][e];
+      int ci = L.evck[li][e] >> 16, k = L.evck[li][e] & 0xffff;
       int c = c0 + ci;
       int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
       int cnt = ntc_outcome_small<SIG, R, FULL>(K, c, step, call, k, np_, n, v0 + cs, st,
@@ -485,10 +530,11 @@ __device__ inline void tile_run(const SimConst& K, const PartArgs& a, int li, in
     if (n < 2) continue;
     if (!all) {  // skip cells without events quickly
       bool any = false;
-      for (int e = 0; e < ne; ++e) any |= L.evc[li][e] == ci;
+      for (int e = 0; e < ne; ++e) any |= (L.evck[li][e] >> 16) == ci;
       if (!any) continue;
     }
-    cell_outcomes<SIG, R, FULL>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase, st, stu, L,
+    cell_outcomes<SIG, R, FULL, LANE_ONLY>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase,
+                                           st, stu, L,
                           li, ne, all, acc, gmx);
   }
   if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
@@ -501,7 +547,7 @@ __device__ inline void tile_run(const SimConst& K, const PartArgs& a, int li, in
 // barrier that ends the tile's loads).
 template <class Lds>
 __device__ inline void tile_lists_clear(Lds& L) {
-  for (int i = 0; i < Lds::kLists; ++i) L.n_evt[i] = L.overflow[i] = 0;
+  for (int i = 0; i < Lds::kLists; ++i) L.n_evt[i] = L.overflow[i] = L.need[i] = L.big[i] = 0;
   L.pool_n = 0;
 }
 
@@ -519,6 +565,8 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
   if (threadIdx.x == 0) {
     L.n_evt[0] = 0;
     L.overflow[0] = 0;
+    L.need[0] = 0;
+    L.big[0] = 0;
     L.pool_n = 0;
   }
   for (int j = threadIdx.x; j < ns; j += kTileThreads) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
@@ -527,7 +575,7 @@ __device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int ca
   const int64_t steps[2] = {step, step};
   tile_draw(K, a, 0, 1, calls, steps, c0, ncells, L);
   __syncthreads();
-  tile_run<SIG, R, FULL>(K, a, 0, call, step, c0, ncells, s0, ns, v0, u, D, mark, tl, tagbase, st,
+  tile_run<SIG, R, FULL, false>(K, a, 0, call, step, c0, ncells, s0, ns, v0, u, D, mark, tl, tagbase, st,
                          stu, L);
 }
 
@@ -544,6 +592,17 @@ __device__ inline void tile_draw_pass(const SimConst& K, const PartArgs& a, int 
   const int64_t steps[2] = {a.nb, a.na};
   const int lo = (a.mode & kDoB) ? 0 : 1, hi = (a.mode & kDoA) ? 2 : 1;
   tile_draw(K, a, lo, hi, calls, steps, c0, ncells, L);
+}
+
+// Whether every outcome of the drawn lists [lo, hi) runs on a lane: no list
+// overflowed, no outcome has more than kSmallPairs pairs, and each list's
+// records fit the pool.  Read after the barrier that ends the draw.
+template <class Lds>
+__device__ inline bool tile_lane_only(const Lds& L, int lo, int hi) {
+  bool ok = true;
+  for (int li = lo; li < hi; ++li)
+    ok = ok && !L.overflow[li] && !L.big[li] && L.need[li] <= kPool;
+  return ok;
 }
 
 // Tile bounds of block b: first cell, cell count, first particle, particle count.
@@ -676,7 +735,7 @@ __device__ inline void field_acc_f64(const SimConst& K, const double xp[3], cons
 // than it loses to spill traffic.  The paper family's instances (FP64 root
 // solves of the manufactured positions in the drift and its source terms) need
 // about twice the registers and get two waves per SIMD (256 VGPRs).
-template <int FAM, int SIG, bool FULL>
+template <int FAM, int SIG, bool FULL, bool FAST>
 __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
     k_particles_f64(SimConst K, PartArgs a) {
   a = member_view(K, a);
@@ -686,164 +745,176 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;
-  if (tid == 0) {
-    sh_i[0] = min(a.tile_c0[blockIdx.x], K.nn);
-    sh_i[1] = min(a.tile_c0[blockIdx.x + 1], K.nn);
-    sh_i[2] = a.tile_s0[blockIdx.x];
-    sh_i[3] = a.tile_s0[blockIdx.x + 1];
-    tile_lists_clear(cl);
-  }
-  __syncthreads();
-  const int c0 = sh_i[0], ncells = max(sh_i[1] - sh_i[0], 0), s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
-  if (ns <= 0) return;
-  const bool lds = ns <= kLdsSlots;
-  const int st = lds ? kLdsSlots : NP;
-  double* v0 = lds ? lv0 : a.gv0 + s0;
-  double* u = a.gu + s0;
-  double* D = lds ? lD : a.gD + s0;
-  int* mark = a.gmark + s0;
-  int* tl = a.gtl + s0;
-  const double dt = K.dt;
-  const double inv_navg_den = (double)K.navg;
-
-  const bool pass_coll = K.collisions && !(a.mode & kCollideOnly);
-  if (pass_coll) tile_zero_D(ns, st, D);
-  for (int j = tid; j < ns; j += kTileThreads)
-    for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
-  if (pass_coll) tile_draw_pass(K, a, c0, ncells, cl);
-  __syncthreads();
-
-  if (a.mode & kCollideOnly) {
-    tile_collide<SIG, double, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                              NP, cl);
-    for (int j = tid; j < ns; j += kTileThreads) {
-      int c = a.key[s0 + j];
-      int n = a.cstart[c + 1] - a.cstart[c];
-      double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
-      double coef = (K.w * K.dt * (double)(n - 1)) / (2.0 * K.dV);
-      if (n >= 2) source_integral_t<SIG>(K, vp, a.tB, I);
-      for (int d = 0; d < 3; ++d) {
-        a.Dout[(int64_t)d * NP + s0 + j] = D[d * st + j] / inv_navg_den;
-        a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? coef * I[d] : 0.0;
-      }
+  auto tile = [&](const int b) __attribute__((always_inline)) {
+    if (tid == 0) {
+      sh_i[0] = min(a.tile_c0[b], K.nn);
+      sh_i[1] = min(a.tile_c0[b + 1], K.nn);
+      sh_i[2] = a.tile_s0[b];
+      sh_i[3] = a.tile_s0[b + 1];
+      tile_lists_clear(cl);
     }
-    return;
-  }
-
-  // With both halves in one pass, kick B (end of step n) and kick A (start of
-  // step n + 1) are at the same time t^{n+1} and position, so the field part
-  // of the acceleration is computed once and kept per slot in LDS (bitwise the
-  // same).
-  const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 && lds;
-  if (a.mode & kDoB) {
-    // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
-    const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
-    if (K.collisions)
-      tile_run<SIG, double, FULL>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                                NP, cl);
-    for (int j = tid; j < ns; j += kTileThreads) {
-      int p = s0 + j;
-      double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3], acc[3];
-      int cc[3];
-      gather_f64(K, a.E, xp, ep, cc);
-      field_acc_f64(K, xp, ep, t1, acc);
-      if (reuse)
-        for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
-      int c = a.key[p];
-      int n = a.cstart[c + 1] - a.cstart[c];
-      double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
-      double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
-      double Dj[3] = {0.0, 0.0, 0.0};
-      if (K.collisions)
-        for (int d = 0; d < 3; ++d) {
-          Dj[d] = D[d * st + j] / inv_navg_den;
-          D[d * st + j] = 0.0;  // cleared for call A (the barrier below orders it)
-        }
-      half_kick_f64<FAM, SIG>(K, acc, t1, th, t1, th, aa, n, Dj, vp);
-      for (int d = 0; d < 3; ++d) v0[d * st + j] = vp[d];
-    }
-    if (tid == 0) cl.pool_n = 0;
     __syncthreads();
-    if (!(a.mode & kDoA)) {
-      for (int j = tid; j < ns; j += kTileThreads)
-        for (int d = 0; d < 3; ++d) a.v[(int64_t)d * NP + s0 + j] = v0[d * st + j];
+    const int c0 = sh_i[0], ncells = max(sh_i[1] - sh_i[0], 0), s0 = sh_i[2], ns = sh_i[3] - sh_i[2];
+    if (ns <= 0) return;
+    if (FAST && ns > kLdsSlots) {  // (uniform) the general instance takes this tile
+      defer_tile(a, b);
       return;
     }
-  }
+    const bool lds = FAST || ns <= kLdsSlots;
+    const int st = lds ? kLdsSlots : NP;
+    double* v0 = lds ? lv0 : a.gv0 + s0;
+    double* u = a.gu + s0;
+    double* D = lds ? lD : a.gD + s0;
+    int* mark = a.gmark + s0;
+    int* tl = a.gtl + s0;
+    const double dt = K.dt;
+    const double inv_navg_den = (double)K.navg;
 
-  // collision call A at t^{na} on v^{na}, first half kick, drift to t^{na+1}
-  const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
-  if (K.collisions)
-    tile_run<SIG, double, FULL>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
-                              st, NP, cl);
-  for (int base = 0; base < ns; base += kTileThreads) {
-    int j = base + tid;
-    bool valid = j < ns;
-    int kk = 0;
-    if (valid) {
-      int p = s0 + j;
-      double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, acc[3];
-      if (reuse) {
-        for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
-      } else {
-        double ep[3];
+    const bool pass_coll = K.collisions && !(a.mode & kCollideOnly);
+    if (pass_coll) tile_zero_D(ns, st, D);
+    for (int j = tid; j < ns; j += kTileThreads)
+      for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
+    if (pass_coll) tile_draw_pass(K, a, c0, ncells, cl);
+    __syncthreads();
+    if (FAST && pass_coll &&
+        !tile_lane_only(cl, (a.mode & kDoB) ? 0 : 1, (a.mode & kDoA) ? 2 : 1)) {
+      defer_tile(a, b);  // (uniform, and nothing written to memory yet)
+      return;
+    }
+
+    if (!FAST && (a.mode & kCollideOnly)) {  // (the lean instance never runs collide-only)
+      tile_collide<SIG, double, FULL>(K, a, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+                                NP, cl);
+      for (int j = tid; j < ns; j += kTileThreads) {
+        int c = a.key[s0 + j];
+        int n = a.cstart[c + 1] - a.cstart[c];
+        double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]}, I[3] = {0, 0, 0};
+        double coef = (K.w * K.dt * (double)(n - 1)) / (2.0 * K.dV);
+        if (n >= 2) source_integral_t<SIG>(K, vp, a.tB, I);
+        for (int d = 0; d < 3; ++d) {
+          a.Dout[(int64_t)d * NP + s0 + j] = D[d * st + j] / inv_navg_den;
+          a.Sout[(int64_t)d * NP + s0 + j] = (n >= 2) ? coef * I[d] : 0.0;
+        }
+      }
+      return;
+    }
+
+    // With both halves in one pass, kick B (end of step n) and kick A (start of
+    // step n + 1) are at the same time t^{n+1} and position, so the field part
+    // of the acceleration is computed once and kept per slot in LDS (bitwise the
+    // same).
+    const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 && lds;
+    if (a.mode & kDoB) {
+      // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
+      const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
+      if (K.collisions)
+        tile_run<SIG, double, FULL, FAST>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+                                  NP, cl);
+      for (int j = tid; j < ns; j += kTileThreads) {
+        int p = s0 + j;
+        double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3], acc[3];
         int cc[3];
         gather_f64(K, a.E, xp, ep, cc);
-        field_acc_f64(K, xp, ep, t0, acc);
+        field_acc_f64(K, xp, ep, t1, acc);
+        if (reuse)
+          for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
+        int c = a.key[p];
+        int n = a.cstart[c + 1] - a.cstart[c];
+        double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
+        double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
+        double Dj[3] = {0.0, 0.0, 0.0};
+        if (K.collisions)
+          for (int d = 0; d < 3; ++d) {
+            Dj[d] = D[d * st + j] / inv_navg_den;
+            D[d * st + j] = 0.0;  // cleared for call A (the barrier below orders it)
+          }
+        half_kick_f64<FAM, SIG>(K, acc, t1, th, t1, th, aa, n, Dj, vp);
+        for (int d = 0; d < 3; ++d) v0[d * st + j] = vp[d];
       }
-      int c = a.key[p];
-      int n = a.cstart[c + 1] - a.cstart[c];
-      double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
-      double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
-      double Dj[3] = {0.0, 0.0, 0.0};
-      if (K.collisions)
-        for (int d = 0; d < 3; ++d) Dj[d] = D[d * st + j] / inv_navg_den;
-      half_kick_f64<FAM, SIG>(K, acc, t0, t0, th, t0, aa, n, Dj, vp);
-      // drift (eq. velocity_verlet) with the manufactured term
-      double vm[3], vdm[3], h[3] = {0.0, 0.0, 0.0};
-      if (FAM == 1) {
-        for (int d = 0; d < 3; ++d) vm[d] = K.vbar * aa[d];
-      } else {
-        manufactured_velocity(K, aa, th, vm, vdm);
+      if (tid == 0) cl.pool_n = 0;
+      __syncthreads();
+      if (!(a.mode & kDoA)) {
+        for (int j = tid; j < ns; j += kTileThreads)
+          for (int d = 0; d < 3; ++d) a.v[(int64_t)d * NP + s0 + j] = v0[d * st + j];
+        return;
       }
-      if (FAM == 0) {
-        int pid = a.id[p];
-        double xq[3];
-        position_uniforms(K, pid, xq);
-        if (K.isolate) {
-          double xa[3], xb[3];
-          manufactured_position(K, xq, t0, nullptr, xa);
-          manufactured_position(K, xq, t1, nullptr, xb);
-          for (int d = 0; d < 3; ++d) h[d] = xb[d] - xa[d];
-        } else {
-          double xm[3], xd[3];
-          manufactured_position(K, xq, th, nullptr, xm);
-          manufactured_xdot(K, xm, th, xd);
-          for (int d = 0; d < 3; ++d) h[d] = dt * xd[d];
-        }
-      }
-      for (int d = 0; d < 3; ++d) {
-        double xn = xp[d] + dt * (vp[d] - vm[d]) + h[d];
-        if (xn < 0.0) xn += K.L[d];
-        if (xn >= K.L[d]) xn -= K.L[d];
-        if (!(xn >= 0.0 && xn < K.L[d])) {  // non-finite or more than a box length
-          atomicOr(&a.flags[kFlagNonFinite], 1);
-          xn = isfinite(xn) ? xn - floor(xn / K.L[d]) * K.L[d] : 0.0;
-          if (!(xn >= 0.0 && xn < K.L[d])) xn = 0.0;
-        }
-        xp[d] = xn;
-        a.x[(int64_t)d * NP + p] = xn;
-        a.v[(int64_t)d * NP + p] = vp[d];
-      }
-      int ci[3];
-      double o[3];
-      locate(K, xp, ci, o);
-      kk = lin(K, ci[0], ci[1], ci[2]);
-      a.key[p] = kk;
     }
-    int sl = wave_aggregated_slot(a.count, kk, valid);
-    if (valid) a.slot[s0 + j] = sl;
-  }
+
+    // collision call A at t^{na} on v^{na}, first half kick, drift to t^{na+1}
+    const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
+    if (K.collisions)
+      tile_run<SIG, double, FULL, FAST>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+                                st, NP, cl);
+    for (int base = 0; base < ns; base += kTileThreads) {
+      int j = base + tid;
+      bool valid = j < ns;
+      int kk = 0;
+      if (valid) {
+        int p = s0 + j;
+        double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, acc[3];
+        if (reuse) {
+          for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
+        } else {
+          double ep[3];
+          int cc[3];
+          gather_f64(K, a.E, xp, ep, cc);
+          field_acc_f64(K, xp, ep, t0, acc);
+        }
+        int c = a.key[p];
+        int n = a.cstart[c + 1] - a.cstart[c];
+        double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
+        double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
+        double Dj[3] = {0.0, 0.0, 0.0};
+        if (K.collisions)
+          for (int d = 0; d < 3; ++d) Dj[d] = D[d * st + j] / inv_navg_den;
+        half_kick_f64<FAM, SIG>(K, acc, t0, t0, th, t0, aa, n, Dj, vp);
+        // drift (eq. velocity_verlet) with the manufactured term
+        double vm[3], vdm[3], h[3] = {0.0, 0.0, 0.0};
+        if (FAM == 1) {
+          for (int d = 0; d < 3; ++d) vm[d] = K.vbar * aa[d];
+        } else {
+          manufactured_velocity(K, aa, th, vm, vdm);
+        }
+        if (FAM == 0) {
+          int pid = a.id[p];
+          double xq[3];
+          position_uniforms(K, pid, xq);
+          if (K.isolate) {
+            double xa[3], xb[3];
+            manufactured_position(K, xq, t0, nullptr, xa);
+            manufactured_position(K, xq, t1, nullptr, xb);
+            for (int d = 0; d < 3; ++d) h[d] = xb[d] - xa[d];
+          } else {
+            double xm[3], xd[3];
+            manufactured_position(K, xq, th, nullptr, xm);
+            manufactured_xdot(K, xm, th, xd);
+            for (int d = 0; d < 3; ++d) h[d] = dt * xd[d];
+          }
+        }
+        for (int d = 0; d < 3; ++d) {
+          double xn = xp[d] + dt * (vp[d] - vm[d]) + h[d];
+          if (xn < 0.0) xn += K.L[d];
+          if (xn >= K.L[d]) xn -= K.L[d];
+          if (!(xn >= 0.0 && xn < K.L[d])) {  // non-finite or more than a box length
+            atomicOr(&a.flags[kFlagNonFinite], 1);
+            xn = isfinite(xn) ? xn - floor(xn / K.L[d]) * K.L[d] : 0.0;
+            if (!(xn >= 0.0 && xn < K.L[d])) xn = 0.0;
+          }
+          xp[d] = xn;
+          a.x[(int64_t)d * NP + p] = xn;
+          a.v[(int64_t)d * NP + p] = vp[d];
+        }
+        int ci[3];
+        double o[3];
+        locate(K, xp, ci, o);
+        kk = lin(K, ci[0], ci[1], ci[2]);
+        a.key[p] = kk;
+      }
+      int sl = wave_aggregated_slot(a.count, kk, valid);
+      if (valid) a.slot[s0 + j] = sl;
+    }
+  };
+  tile_sweep<FAST>(a, tile);
 }
 
 }  // namespace pic

@@ -56,6 +56,7 @@ template <class T, class U> inline T atomicOr(T* p, U v) {
 #define __hip_atomic_load(p, order, scope) (*(p))
 #define __hip_atomic_store(p, v, order, scope) (*(p) = (v))
 #define __builtin_amdgcn_fence(order, scope) ((void)0)
+inline void __threadfence() {}
 #define __builtin_amdgcn_s_sleep(n) ((void)0)
 
 // device math with no standard C++ counterpart

@@ -136,6 +136,11 @@ int main(int argc, char** argv) {
   a.Sout = Sout.data();
   a.counters = counters.data();
   a.flags = flags.data();
+  std::vector<int> defer(ntiles + 2, 0);
+  int deferred = 0;
+  a.defer = defer.data();
+  a.ntiles = ntiles;
+  a.defer_list = 0;
   if (h.mode == 0) {
     a.mode = kCollideOnly;
     a.na = h.step;
@@ -155,27 +160,45 @@ int main(int argc, char** argv) {
   const MixConst M = mix_const(K, a);
   std::mt19937_64 rng(h.rng_seed);
   const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
-  std::function<void()> kern;
+  // full: 1 the full instance alone; 0 the lean instance, then the general
+  // one over the tiles it deferred (the library's default); 2 the general
+  // lean instance alone
+  std::function<void()> kern, kern_lean;
+  PartArgs ag = a;
+  ag.defer_list = h.full == 0 ? 1 : 0;
   if (h.precision == 0) {
+    auto f64 = [&](auto kfull, auto kgen, auto kfast) {
+      if (h.full == 1) kern = [&, kfull] { kfull(K, a); };
+      else kern = [&, kgen] { kgen(K, ag); };
+      kern_lean = [&, kfast] { kfast(K, a); };
+    };
     if (K.family == 0 && sig == kSigPoly)
-      kern = h.full ? std::function<void()>([&] { k_particles_f64<0, kSigPoly, true>(K, a); })
-                    : std::function<void()>([&] { k_particles_f64<0, kSigPoly, false>(K, a); });
+      f64(k_particles_f64<0, kSigPoly, true, false>, k_particles_f64<0, kSigPoly, false, false>,
+          k_particles_f64<0, kSigPoly, false, true>);
     else if (K.family == 1 && sig == kSigHS)
-      kern = h.full ? std::function<void()>([&] { k_particles_f64<1, kSigHS, true>(K, a); })
-                    : std::function<void()>([&] { k_particles_f64<1, kSigHS, false>(K, a); });
+      f64(k_particles_f64<1, kSigHS, true, false>, k_particles_f64<1, kSigHS, false, false>,
+          k_particles_f64<1, kSigHS, false, true>);
     else
       return 4;
   } else {
-    auto mixed = [&](auto kfn) {
-      kern = [&, kfn] { kfn(K, M, a, off.data(), vf.data(), ashf.data(), E32.data()); };
+    auto mixed = [&](auto kfull, auto kgen, auto kfast) {
+      if (h.full == 1)
+        kern = [&, kfull] { kfull(K, M, a, off.data(), vf.data(), ashf.data(), E32.data()); };
+      else
+        kern = [&, kgen] { kgen(K, M, ag, off.data(), vf.data(), ashf.data(), E32.data()); };
+      kern_lean = [&, kfast] { kfast(K, M, a, off.data(), vf.data(), ashf.data(), E32.data()); };
     };
     if (K.family == 1 && sig == kSigHS)
-      h.full ? mixed(k_particles_mixed<1, kSigHS, true>) : mixed(k_particles_mixed<1, kSigHS, false>);
+      mixed(k_particles_mixed<1, kSigHS, true, false>, k_particles_mixed<1, kSigHS, false, false>,
+            k_particles_mixed<1, kSigHS, false, true>);
     else if (K.family == 0 && sig == kSigPoly)
-      h.full ? mixed(k_particles_mixed<0, kSigPoly, true>) : mixed(k_particles_mixed<0, kSigPoly, false>);
+      mixed(k_particles_mixed<0, kSigPoly, true, false>, k_particles_mixed<0, kSigPoly, false, false>,
+            k_particles_mixed<0, kSigPoly, false, true>);
     else
       return 4;
   }
+  const bool lean = h.full == 0 && h.mode != 0;  // (collide-only runs the general instance)
+  if (!lean) ag.defer_list = 0;
   if (h.mode == 5 || h.mode == 6) {
     // the separate kernels of an A-alone (5) or B-alone (6) pass
     if (h.precision != 0) return 4;
@@ -234,6 +257,13 @@ int main(int argc, char** argv) {
       k_drift_f64(K, t0a, tha, t1a, x.data(), v.data(), ash.data(), id.data(), key.data(),
                   slot.data(), count.data(), flags.data());
     }, h.order, rng);
+  } else if (lean) {
+    emu::run_grid((unsigned)ntiles, kTileThreads, kern_lean, h.order, rng);
+    deferred = defer[0];
+    // the general instance over the deferred tiles, on fewer workgroups than
+    // tiles so that each works through several
+    emu::run_grid((unsigned)std::max(1, std::min(ntiles, 7)), kTileThreads, kern, h.order, rng);
+    if (defer[0] != 0 || defer[1] != 0) return 5;  // the list was not emptied
   } else {
     emu::run_grid((unsigned)ntiles, kTileThreads, kern, h.order, rng);
   }
@@ -255,7 +285,7 @@ int main(int argc, char** argv) {
   wr(out, &nrec, 1);
   if (nrec) wr(out, angles.data(), 2 * nrec);
   std::fclose(out);
-  std::fprintf(stderr, "emu: %d tiles, %llu block barriers\n", ntiles,
+  std::fprintf(stderr, "emu: %d tiles, %d deferred, %llu block barriers\n", ntiles, deferred,
                (unsigned long long)emu::g.barriers);
   return 0;
 }

@@ -28,6 +28,7 @@ import sys
 
 import numpy as np
 import pytest
+import re
 
 import oracle as O
 from paper_2602_15130_amd import workloads as W
@@ -131,6 +132,8 @@ def _run(harness, which, prob, disc, seed, mode, order, *, steps_before=0, call=
     out["flags"] = take(np.int32, 4)
     nrec = int(take(np.int64, 1)[0])
     out["angles"] = take(np.float64, 2 * nrec).reshape(-1, 2)
+    m = re.search(r"emu: \d+ tiles, (\d+) deferred", r.stderr)
+    out["deferred"] = int(m.group(1)) if m else None
     return out, o
 
 
@@ -180,6 +183,28 @@ def test_collision_call_matches_oracle_hard_sphere(harness, navg):
     assert g["accepted"] == o.accepted - a0 > 1000
     assert np.abs(g["D"] - D).max() <= 1e-12 * np.abs(D).max()
     assert np.abs(g["S"] - S).max() <= 1e-12 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lean_pass_with_deferred_tiles_equals_general_pass(harness, precision):
+    """The lean instance runs the tiles whose outcomes all fit the lane path
+    and defers the others (an outcome over the lane-run size, a full record
+    pool, tiles larger than their LDS slots) to the general instance, which
+    works through the list on fewer workgroups; the result equals the general
+    instance's alone bit for bit, in every thread and workgroup order."""
+    prob = W.cfg_problem(two_way=True, collisionality=2.0)
+    for nc, npart in ((8, 16384), (3, 19000)):
+        disc = W.cfg_disc(nc, npart, 1e-3, 1, 8)
+        ref, _ = _run(harness, "product", prob, disc, 5, 1, FORWARD, steps_before=1, full=2,
+                      precision=precision)
+        assert ref["accepted"] > 100 and not ref["flags"].any()
+        for order in (FORWARD, REVERSE, SHUFFLE):
+            got, _ = _run(harness, "product", prob, disc, 5, 1, order, steps_before=1, full=0,
+                          precision=precision)
+            assert _pass_equal(got, ref), (nc, order)
+            assert 0 < got["deferred"], got["deferred"]
+            if nc == 8:
+                assert got["deferred"] < 64  # most of the 64 tiles run lean
 
 
 def _pass_equal(a, b):
