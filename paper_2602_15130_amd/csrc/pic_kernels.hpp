@@ -30,6 +30,13 @@ constexpr int kLdsSlots = PIC_LDS_SLOTS;          // LDS-resident slots per tile
 #ifndef PIC_F64_WAVES
 #define PIC_F64_WAVES 4  // also the LDS limit: four 33 KB tiles per CU
 #endif
+// The same for the lean instances (smaller: no general collision path).
+#ifndef PIC_MIXED_LEAN_WAVES
+#define PIC_MIXED_LEAN_WAVES 6
+#endif
+#ifndef PIC_F64_LEAN_WAVES
+#define PIC_F64_LEAN_WAVES 4
+#endif
 
 // Flags raised by kernels and read back at the next synchronising call.
 enum { kFlagCgNoConv = 0, kFlagBarrier = 1, kFlagNonFinite = 2, kFlagCapacity = 3, kFlagCount = 4 };

@@ -354,7 +354,7 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 // paper family's instances (FP64 root solves in the drift and the source) get
 // four (128 VGPRs).
 template <int FAM, int SIG, bool FULL, bool FAST>
-__global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
+__global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : (FAST ? PIC_MIXED_LEAN_WAVES : PIC_MIXED_WAVES)) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
   a = member_view(K, a);
@@ -501,7 +501,7 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : PIC_MIXED_WAVES) 
     if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
       if (K.collisions)
         tile_run<SIG, float, FULL, FAST>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                                 NP, cl);
+                                 NP, cl, few_cells ? lcs : nullptr);
       for (int j = tid; j < ns; j += kTileThreads) {
         float acc[3], sa[3] = {0.0f, 0.0f, 0.0f};
         if constexpr (FAM == 0) {
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : PIC_MIXED_WAVES) 
     // call A at t^{na}, first half kick, drift to t^{na+1}
     if (K.collisions)
       tile_run<SIG, float, FULL, FAST>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
-                               st, NP, cl);
+                               st, NP, cl, few_cells ? lcs : nullptr);
     for (int base = 0; base < ns; base += kTileThreads) {
       int j = base + tid;
       bool valid = j < ns;

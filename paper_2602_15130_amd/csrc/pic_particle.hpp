@@ -494,9 +494,11 @@ template <int SIG, class R, bool FULL, bool LANE_ONLY, class Lds>
 __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K, const PartArgs& a, int li, int call,
                                 int64_t step, int c0, int ncells, int s0, int ns, const R* v0,
                                 R* u, R* D, int* mark, int* tl, int tagbase, int st, int stu,
-                                Lds& L) {
+                                Lds& L, const int* lcs = nullptr) {
   const int tid = threadIdx.x;
   const int ne = min(L.n_evt[li], Lds::kCap);
+  // start of tile-local cell ci: the tile's copy in LDS when the caller keeps one
+  auto cell_start = [&](int ci) { return lcs ? lcs[ci] : a.cstart[c0 + ci]; };
   // LANE_ONLY: the caller has checked tile_lane_only, so every event runs on a lane
   const bool all = !LANE_ONLY && L.overflow[li] != 0;
   unsigned long long acc = 0, gmx = 0;
@@ -515,7 +517,7 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
       }
       int ci = L.evck[li][e] >> 16, k = L.evck[li][e] & 0xffff;
       int c = c0 + ci;
-      int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
+      int cs = cell_start(ci) - s0, n = cell_start(ci + 1) - cell_start(ci);
       int cnt = ntc_outcome_small<SIG, R, FULL>(K, c, step, call, k, np_, n, v0 + cs, st,
                                           L.pslot + start, L.pdv + start, a.pairlog, a.cap,
                                           a.counters, acc, gmx);
@@ -526,7 +528,7 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
   // per cell, in increasing outcome order
   for (int ci = tid; ci < ncells; ci += kTileThreads) {
     int c = c0 + ci;
-    int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];
+    int cs = cell_start(ci) - s0, n = cell_start(ci + 1) - cell_start(ci);
     if (n < 2) continue;
     if (!all) {  // skip cells without events quickly
       bool any = false;
@@ -736,11 +738,13 @@ __device__ inline void field_acc_f64(const SimConst& K, const double xp[3], cons
 // solves of the manufactured positions in the drift and its source terms) need
 // about twice the registers and get two waves per SIMD (256 VGPRs).
 template <int FAM, int SIG, bool FULL, bool FAST>
-__global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
+__global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : (FAST ? PIC_F64_LEAN_WAVES : PIC_F64_WAVES))
     k_particles_f64(SimConst K, PartArgs a) {
   a = member_view(K, a);
   // the copy-on-write scratch of outcomes run by a cell thread is global
   __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots], lacc[3 * kLdsSlots];
+  __shared__ int lkey[kLdsSlots];
+  __shared__ int lcs[kCellCache + 1];  // cell starts of a tile of at most kCellCache cells
   __shared__ CollideLds<double, 2, 128> cl;  // both calls of the pass drawn up front
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
@@ -771,11 +775,38 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
     const double inv_navg_den = (double)K.navg;
 
     const bool pass_coll = K.collisions && !(a.mode & kCollideOnly);
+    // A tile held in LDS computes the field part of its first kick while it
+    // loads and keeps it in lacc; with both halves in one pass kick B (end of
+    // step n) and kick A (start of step n + 1) are at the same time and
+    // position, so kick A reuses it (bitwise what it would compute again).
+    const bool pre = lds && !(a.mode & kCollideOnly);
+    const bool reuse_A = pre && (!(a.mode & kDoB) || a.na == a.nb + 1);
+    const double t_pre = (a.mode & kDoB) ? ((double)a.nb + 1.0) * dt : (double)a.na * dt;
     if (pass_coll) tile_zero_D(ns, st, D);
-    for (int j = tid; j < ns; j += kTileThreads)
-      for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + s0 + j];
+    for (int j = tid; j < ns; j += kTileThreads) {
+      const int p = s0 + j;
+      for (int d = 0; d < 3; ++d) v0[d * st + j] = a.v[(int64_t)d * NP + p];
+      if (lds) {
+        lkey[j] = a.key[p];
+        if (pre) {
+          double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3], acc[3];
+          int cc[3];
+          gather_f64(K, a.E, xp, ep, cc);
+          field_acc_f64(K, xp, ep, t_pre, acc);
+          for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
+        }
+      }
+    }
+    const bool few_cells = ncells <= kCellCache;
+    if (few_cells)
+      for (int i = tid; i <= ncells; i += kTileThreads) lcs[i] = a.cstart[c0 + i];
     if (pass_coll) tile_draw_pass(K, a, c0, ncells, cl);
     __syncthreads();
+    // cell and particle count of slot j at the start of the pass
+    auto cell_of = [&](int j) { return lds ? lkey[j] : a.key[s0 + j]; };
+    auto count_of = [&](int c) {
+      return few_cells ? lcs[c - c0 + 1] - lcs[c - c0] : a.cstart[c + 1] - a.cstart[c];
+    };
     if (FAST && pass_coll &&
         !tile_lane_only(cl, (a.mode & kDoB) ? 0 : 1, (a.mode & kDoA) ? 2 : 1)) {
       defer_tile(a, b);  // (uniform, and nothing written to memory yet)
@@ -803,23 +834,24 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
     // step n + 1) are at the same time t^{n+1} and position, so the field part
     // of the acceleration is computed once and kept per slot in LDS (bitwise the
     // same).
-    const bool reuse = (a.mode & kDoB) && (a.mode & kDoA) && a.na == a.nb + 1 && lds;
     if (a.mode & kDoB) {
       // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
       const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
       if (K.collisions)
         tile_run<SIG, double, FULL, FAST>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
-                                  NP, cl);
+                                  NP, cl, few_cells ? lcs : nullptr);
       for (int j = tid; j < ns; j += kTileThreads) {
         int p = s0 + j;
-        double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3], acc[3];
-        int cc[3];
-        gather_f64(K, a.E, xp, ep, cc);
-        field_acc_f64(K, xp, ep, t1, acc);
-        if (reuse)
-          for (int d = 0; d < 3; ++d) lacc[d * kLdsSlots + j] = acc[d];
-        int c = a.key[p];
-        int n = a.cstart[c + 1] - a.cstart[c];
+        double acc[3];
+        if (pre) {
+          for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
+        } else {
+          double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, ep[3];
+          int cc[3];
+          gather_f64(K, a.E, xp, ep, cc);
+          field_acc_f64(K, xp, ep, t1, acc);
+        }
+        const int n = count_of(cell_of(j));
         double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
         double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
         double Dj[3] = {0.0, 0.0, 0.0};
@@ -844,7 +876,7 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
     const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
     if (K.collisions)
       tile_run<SIG, double, FULL, FAST>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
-                                st, NP, cl);
+                                st, NP, cl, few_cells ? lcs : nullptr);
     for (int base = 0; base < ns; base += kTileThreads) {
       int j = base + tid;
       bool valid = j < ns;
@@ -852,7 +884,7 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
       if (valid) {
         int p = s0 + j;
         double xp[3] = {a.x[p], a.x[NP + p], a.x[2 * NP + p]}, acc[3];
-        if (reuse) {
+        if (reuse_A) {
           for (int d = 0; d < 3; ++d) acc[d] = lacc[d * kLdsSlots + j];
         } else {
           double ep[3];
@@ -860,8 +892,7 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : PIC_F64_WAVES)
           gather_f64(K, a.E, xp, ep, cc);
           field_acc_f64(K, xp, ep, t0, acc);
         }
-        int c = a.key[p];
-        int n = a.cstart[c + 1] - a.cstart[c];
+        const int n = count_of(cell_of(j));
         double vp[3] = {v0[j], v0[st + j], v0[2 * st + j]};
         double aa[3] = {a.ash[p], a.ash[NP + p], a.ash[2 * NP + p]};
         double Dj[3] = {0.0, 0.0, 0.0};

@@ -58,7 +58,7 @@ def _event_variant(src):
     s = rep(s, "          L.evn[li][e] = (int)np_;\n",
             "          L.evn[li][e] = (int)np_;\n          L.evs[e] = a.cstart[c];\n"
             "          L.evm[e] = n;\n")
-    s = rep(s, "      int cs = a.cstart[c] - s0, n = a.cstart[c + 1] - a.cstart[c];\n"
+    s = rep(s, "      int cs = cell_start(ci) - s0, n = cell_start(ci + 1) - cell_start(ci);\n"
                "      int cnt = ntc_outcome_small",
             "      int cs = L.evs[e] - s0, n = L.evm[e];\n      int cnt = ntc_outcome_small")
     return s
