@@ -107,10 +107,11 @@ __global__ void __launch_bounds__(64 * kHeavyWaves) k_collide_heavy(SimConst K, 
           const bool ok = W.pacc[j] < sigma_g(K, g) / K.sgmax;
           if (ok) {
             ++nacc;
-            const double eps = 2.0 * kPi * W.peps[j];
+            double seps, ceps;  // eps = 2 pi U_eps, as sin(pi 2 U) and cos(pi 2 U)
+            sincospi(2.0 * W.peps[j], &seps, &ceps);
             const double cchi = cos_chi<double>(K, W.pchi[j]);  // eq. chi
             const double schi = sqrt(fmax(0.0, (1.0 - cchi) * (1.0 + cchi)));
-            const double nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
+            const double nv[3] = {ceps * schi, seps * schi, cchi};  // eq. n
             if (ip < 0) {
               ip = cnt++;
               W.lslot[ip] = p;

@@ -944,10 +944,11 @@ __global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, in
       bool ok = unif(wa.w[2]) < sigma_g(K, g) / K.sgmax;
       if (ok) {
         ++acc;
-        double eps = 2.0 * kPi * unif(wa.w[3]);
+        double seps, ceps;  // eps = 2 pi U_eps, as sin(pi 2 U) and cos(pi 2 U)
+        sincospi(2.0 * unif(wa.w[3]), &seps, &ceps);
         double cchi = cos_chi<double>(K, unif(wb.w[0]));  // eq. chi
         double schi = sqrt(fmax(0.0, (1.0 - cchi) * (1.0 + cchi)));
-        double nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
+        double nv[3] = {ceps * schi, seps * schi, cchi};  // eq. n
         for (int d = 0; d < 3; ++d) {
           double vcm = 0.5 * (*up[d] + *uq[d]);
           *up[d] = vcm + 0.5 * g * nv[d];

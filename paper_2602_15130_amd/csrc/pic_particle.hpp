@@ -159,6 +159,11 @@ __device__ inline int lower_bound_i(const int* a, int n, int key) {
 // FP64 form, FP32 in the mixed form (uniforms from the top 24 bits of the same
 // words, so both forms draw from one stream).
 template <class R> __device__ inline R unif_r(uint64_t w);
+// sin(pi x) and cos(pi x) in the working precision (the azimuth eps = 2 pi U
+// of a collision is evaluated as pi (2 U): 2 U is exact, and the argument
+// reduction of a general sin / cos is not needed)
+__device__ inline void sincospi_r(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ inline void sincospi_r(double x, double* s, double* c) { sincospi(x, s, c); }
 template <> __device__ inline double unif_r<double>(uint64_t w) { return unif(w); }
 template <> __device__ inline float unif_r<float>(uint64_t w) { return unif32(w); }
 
@@ -219,10 +224,11 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
     bool ok = unif_r<R>(wa.w[2]) < accept_ratio<SIG, R>(K, g);
     if (ok) {
       ++acc;
-      R eps = (R)2.0 * (R)kPi * unif_r<R>(wa.w[3]);
+      R seps, ceps;  // eps = 2 pi U_eps, as sin(pi 2 U) and cos(pi 2 U)
+      sincospi_r((R)2.0 * unif_r<R>(wa.w[3]), &seps, &ceps);
       R cchi = cos_chi<R, FULL>(K, unif_r<R>(wb.w[0]));  // eq. chi
       R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
-      R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
+      R nv[3] = {ceps * schi, seps * schi, cchi};  // eq. n
       R pn[3], qn[3];
       for (int d = 0; d < 3; ++d) {
         R vcm = (R)0.5 * (up[d] + uq[d]);
@@ -311,10 +317,11 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
     bool ok = unif_r<R>(wa.w[2]) < accept_ratio<SIG, R>(K, g);
     if (ok) {
       ++acc;
-      R eps = (R)2.0 * (R)kPi * unif_r<R>(wa.w[3]);
+      R seps, ceps;  // eps = 2 pi U_eps, as sin(pi 2 U) and cos(pi 2 U)
+      sincospi_r((R)2.0 * unif_r<R>(wa.w[3]), &seps, &ceps);
       R cchi = cos_chi<R, FULL>(K, unif_r<R>(wb.w[0]));  // eq. chi
       R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
-      R nv[3] = {cos(eps) * schi, sin(eps) * schi, cchi};  // eq. n
+      R nv[3] = {ceps * schi, seps * schi, cchi};  // eq. n
       if (ip < 0) {
         ip = cnt++;
         pslot[ip] = p;

@@ -62,6 +62,10 @@ inline void __threadfence() {}
 // device math with no standard C++ counterpart
 inline double emu_sinpi(double x) { return std::sin(M_PI * x); }
 inline double emu_cospi(double x) { return std::cos(M_PI * x); }
+inline void emu_sincospi(double x, double* s, double* c) {
+  *s = std::sin(M_PI * x);
+  *c = std::cos(M_PI * x);
+}
 inline void emu_sincospif(float x, float* s, float* c) {
   *s = std::sin((float)M_PI * x);
   *c = std::cos((float)M_PI * x);
@@ -69,6 +73,7 @@ inline void emu_sincospif(float x, float* s, float* c) {
 #define sinpi emu_sinpi
 #define cospi emu_cospi
 #define sincospif emu_sincospif
+#define sincospi emu_sincospi
 
 template <class A, class B> inline auto min(A a, B b) -> decltype(a < b ? a : b) {
   return a < b ? a : b;
