@@ -112,6 +112,11 @@ typedef struct {
   int isolate;              /* 1 => exact-difference substitution of the
                                manufactured time derivatives (Sec. 5.4.1) */
   double chi_alpha;         /* VSS exponent alpha in [1, 2] (PIC_CHI_VSS) */
+  int coding_error;         /* the deliberate coding errors of Sec. 5.4.1, for
+                               verification studies only: 0 none; 1 Error 1,
+                               v_cm = (v_p - v_q) / 2 in the collision; 2 Error 2,
+                               an accepted pair swaps its velocities when
+                               U_chi < 1/2 and is left unchanged otherwise */
 } pic_problem;
 
 /* The discretization (Table 1 columns). */

@@ -127,6 +127,7 @@ int validate(const pic_problem* p, const pic_discretization* d, int precision, s
   if (p->chi_model < PIC_CHI_ISO || p->chi_model > PIC_CHI_VSS) return bad("chi_model must be 0, 1 or 2");
   if (p->chi_model == PIC_CHI_VSS && !(p->chi_alpha >= 1.0 && p->chi_alpha <= 2.0))
     return bad("chi_alpha must lie in [1, 2]");
+  if (p->coding_error < 0 || p->coding_error > 2) return bad("coding_error must be 0, 1 or 2");
   if (p->collisions) {
     if (!(p->g_max > 0.0)) return bad("g_max must be positive");
     if (p->sigma_model == PIC_SIGMA_POLY) {
@@ -652,7 +653,8 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
   const PassFns fns = select_pass(K);
   // the collision-angle and pair-log recording and the anisotropic polar-angle
   // samplers are compiled only into the full instances
-  const bool full = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO;
+  const bool full = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO ||
+                    K.coding_error != 0;
   const bool lean = c->lean_pass && !full && !(a.mode & kCollideOnly);
   const int which = full ? 0 : 1;
   PartArgs ag = a;

@@ -123,10 +123,8 @@ __global__ void __launch_bounds__(64 * kHeavyWaves) k_collide_heavy(SimConst K, 
               W.mark[q] = (tag << 9) | (unsigned)iq;
             }
             double pn[3], qn[3];
+            post_collision<double, true>(K, up, uq, g, nv, W.pchi[j], pn, qn);
             for (int d = 0; d < 3; ++d) {
-              const double vcm = 0.5 * (up[d] + uq[d]);
-              pn[d] = vcm + 0.5 * g * nv[d];
-              qn[d] = vcm - 0.5 * g * nv[d];
               W.lval[d][ip] = pn[d];
               W.lval[d][iq] = qn[d];
             }

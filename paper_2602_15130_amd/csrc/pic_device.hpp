@@ -62,6 +62,7 @@ struct SimConst {
   int poisson_op;      // field discretization: 0 7-point differences, 1 trilinear elements
   int chi_model;       // polar-angle model: 0 isotropic, 1 manufactured anisotropy, 2 VSS
   double chi_alpha;    // VSS exponent
+  int coding_error;    // Sec. 5.4.1 Error 1 / Error 2 (verification studies), 0 none
   double* anglog;      // scattering-angle records (chi, eps) of accepted collisions, or null
   int64_t angcap;      // records that fit
   // Ensembles: the members of one context share every size and differ only in

@@ -32,6 +32,7 @@ inline SimConst derive(const pic_problem* p, const pic_discretization* d, uint64
   K.isolate = p->isolate;
   K.chi_model = p->chi_model;
   K.chi_alpha = p->chi_model == PIC_CHI_VSS ? p->chi_alpha : 1.0;
+  K.coding_error = p->coding_error;
   K.navg = d->n_avg;
   K.np = d->n_particles;
   K.nn = d->ncell[0] * d->ncell[1] * d->ncell[2];

@@ -890,6 +890,29 @@ __device__ inline R cos_chi(const SimConst& K, R xi) {
   return (R)1.0 - (R)2.0 * xi;
 }
 
+// Post-collision velocities of an accepted pair: v_cm +- g n / 2 (Algorithm 1).
+// The full instances also carry the deliberate coding errors of Sec. 5.4.1
+// for verification studies: Error 1 takes v_cm = (v_p - v_q) / 2; Error 2
+// swaps the two velocities when U_chi < 1/2 and leaves them unchanged
+// otherwise.
+template <class R, bool FULL>
+__device__ inline void post_collision(const SimConst& K, const R up[3], const R uq[3], R g,
+                                      const R nv[3], R uchi, R pn[3], R qn[3]) {
+  if (FULL && K.coding_error == 2) {
+    const bool swap = uchi < (R)0.5;
+    for (int d = 0; d < 3; ++d) {
+      pn[d] = swap ? uq[d] : up[d];
+      qn[d] = swap ? up[d] : uq[d];
+    }
+    return;
+  }
+  for (int d = 0; d < 3; ++d) {
+    const R vcm = (FULL && K.coding_error == 1) ? (R)0.5 * (up[d] - uq[d]) : (R)0.5 * (up[d] + uq[d]);
+    pn[d] = vcm + (R)0.5 * g * nv[d];
+    qn[d] = vcm - (R)0.5 * g * nv[d];
+  }
+}
+
 // Capacity of the workgroup-per-cell collision kernel (k_collide_heavy):
 // particles per cell and candidate pairs per outcome.  A cell that could
 // exceed either (N_pairs = floor(n (n - 1) P_max / 2 + U) < n (n - 1) P_max / 2 + 1)
@@ -946,15 +969,17 @@ __global__ void __launch_bounds__(kBlock) k_collide_f64(SimConst K, int call, in
         ++acc;
         double seps, ceps;  // eps = 2 pi U_eps, as sin(pi 2 U) and cos(pi 2 U)
         sincospi(2.0 * unif(wa.w[3]), &seps, &ceps);
-        double cchi = cos_chi<double>(K, unif(wb.w[0]));  // eq. chi
+        const double uchi = unif(wb.w[0]);
+        double cchi = cos_chi<double>(K, uchi);  // eq. chi
         double schi = sqrt(fmax(0.0, (1.0 - cchi) * (1.0 + cchi)));
         double nv[3] = {ceps * schi, seps * schi, cchi};  // eq. n
+        const double p0[3] = {*up[0], *up[1], *up[2]}, q0[3] = {*uq[0], *uq[1], *uq[2]};
+        double pv[3], qv[3];
+        post_collision<double, true>(K, p0, q0, g, nv, uchi, pv, qv);
         for (int d = 0; d < 3; ++d) {
-          double vcm = 0.5 * (*up[d] + *uq[d]);
-          *up[d] = vcm + 0.5 * g * nv[d];
-          *uq[d] = vcm - 0.5 * g * nv[d];
+          *up[d] = pv[d];
+          *uq[d] = qv[d];
         }
-        const double pv[3] = {*up[0], *up[1], *up[2]}, qv[3] = {*uq[0], *uq[1], *uq[2]};
         record_angles<double>(pv, qv, g, K.anglog, K.angcap, counters);
       }
       if (pairlog) {

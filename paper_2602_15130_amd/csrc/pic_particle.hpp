@@ -164,6 +164,7 @@ template <class R> __device__ inline R unif_r(uint64_t w);
 // reduction of a general sin / cos is not needed)
 __device__ inline void sincospi_r(float x, float* s, float* c) { sincospif(x, s, c); }
 __device__ inline void sincospi_r(double x, double* s, double* c) { sincospi(x, s, c); }
+
 template <> __device__ inline double unif_r<double>(uint64_t w) { return unif(w); }
 template <> __device__ inline float unif_r<float>(uint64_t w) { return unif32(w); }
 
@@ -226,14 +227,13 @@ __device__ inline void ntc_outcome(const SimConst& K, int cell, int64_t step, in
       ++acc;
       R seps, ceps;  // eps = 2 pi U_eps, as sin(pi 2 U) and cos(pi 2 U)
       sincospi_r((R)2.0 * unif_r<R>(wa.w[3]), &seps, &ceps);
-      R cchi = cos_chi<R, FULL>(K, unif_r<R>(wb.w[0]));  // eq. chi
+      const R uchi = unif_r<R>(wb.w[0]);
+      R cchi = cos_chi<R, FULL>(K, uchi);  // eq. chi
       R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
       R nv[3] = {ceps * schi, seps * schi, cchi};  // eq. n
       R pn[3], qn[3];
+      post_collision<R, FULL>(K, up, uq, g, nv, uchi, pn, qn);
       for (int d = 0; d < 3; ++d) {
-        R vcm = (R)0.5 * (up[d] + uq[d]);
-        pn[d] = vcm + (R)0.5 * g * nv[d];
-        qn[d] = vcm - (R)0.5 * g * nv[d];
         u[d * stu + p] = pn[d];
         u[d * stu + q] = qn[d];
       }
@@ -319,7 +319,8 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
       ++acc;
       R seps, ceps;  // eps = 2 pi U_eps, as sin(pi 2 U) and cos(pi 2 U)
       sincospi_r((R)2.0 * unif_r<R>(wa.w[3]), &seps, &ceps);
-      R cchi = cos_chi<R, FULL>(K, unif_r<R>(wb.w[0]));  // eq. chi
+      const R uchi = unif_r<R>(wb.w[0]);
+      R cchi = cos_chi<R, FULL>(K, uchi);  // eq. chi
       R schi = sqrt(fmax((R)0.0, ((R)1.0 - cchi) * ((R)1.0 + cchi)));
       R nv[3] = {ceps * schi, seps * schi, cchi};  // eq. n
       if (ip < 0) {
@@ -331,10 +332,8 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
         pslot[iq] = q;
       }
       R pn[3], qn[3];
+      post_collision<R, FULL>(K, up, uq, g, nv, uchi, pn, qn);
       for (int d = 0; d < 3; ++d) {
-        R vcm = (R)0.5 * (up[d] + uq[d]);
-        pn[d] = vcm + (R)0.5 * g * nv[d];
-        qn[d] = vcm - (R)0.5 * g * nv[d];
         pdv[d * kPool + ip] = pn[d];
         pdv[d * kPool + iq] = qn[d];
       }

@@ -40,6 +40,7 @@ class pic_problem(C.Structure):
         ("g_ref", C.c_double), ("omega", C.c_double), ("g_max", C.c_double),
         ("chi_model", C.c_int), ("field_to_particles", C.c_int), ("particles_to_field", C.c_int),
         ("collisions", C.c_int), ("isolate", C.c_int), ("chi_alpha", C.c_double),
+        ("coding_error", C.c_int),
     ]
 
 
@@ -129,6 +130,7 @@ def make_problem(p: dict) -> pic_problem:
     s.sigma_n = (C.c_double * 3)(*sn)
     s.chi_model = int(p.get("chi_model", 0))
     s.chi_alpha = float(p.get("chi_alpha", 1.0))
+    s.coding_error = int(p.get("coding_error", 0))
     for k in ("field_to_particles", "particles_to_field", "collisions", "isolate"):
         setattr(s, k, int(p[k]))
     return s

@@ -168,6 +168,19 @@ def test_collision_call_matches_oracle_paper_family(harness, order):
                                atol=1e-12)
 
 
+@pytest.mark.parametrize("err", [1, 2])
+def test_collision_call_with_coding_errors_matches_oracle(harness, err):
+    """Sec. 5.4.1 Error 1 and Error 2 in the full instance: one collision
+    call equals the oracle's mutated Algorithm 1 per particle."""
+    prob, disc = _paper_isolated_level1()
+    prob["coding_error"] = err
+    g, o = _run(harness, "product", prob, disc, 1, 0, SHUFFLE)
+    a0 = o.accepted
+    D, S, _, _, st = o.collide(0, 0.0)
+    assert st == 0 and g["accepted"] == o.accepted - a0 > 1000
+    assert np.abs(g["D"] - D).max() <= 1e-12 * np.abs(D).max()
+
+
 @pytest.mark.parametrize("navg", [4, 64])
 def test_collision_call_matches_oracle_hard_sphere(harness, navg):
     """Configuration family, hard spheres at a collisionality where outcomes
