@@ -247,6 +247,20 @@ int pic_ensemble_errors(pic_ctx* ctx, pic_error_norms* out);
 /* pic_get_state for member `member` (0 .. members - 1). */
 int pic_ensemble_get_state(pic_ctx* ctx, int member, int item, void* host_dst, int64_t bytes);
 
+/* Captured steps.  With enable != 0, pic_step(n) for n >= 4 records the
+ * inner part of two time steps (sort, field solve, the particle pass that
+ * finishes one step and starts the next) as a HIP graph once per
+ * double-buffer parity, on a private stream, and replays it on the context's
+ * stream, two steps per launch; the kernels then read the step index from a
+ * counter in the workspace.  The results are bit for bit those of ordinary
+ * stepping.  The Poisson solver's workgroups are co-resident by the creation
+ * time occupancy check, so inside a graph it is launched ordinarily.  Steps
+ * with stage timing switched on run without graphs; the angle log and
+ * checkpoint loads drop the recorded graphs.  Returns PIC_EINVAL when the
+ * context does not use the fused step (PIC_UNFUSED, the collision-heavy FP64
+ * mode). */
+int pic_use_graphs(pic_ctx* ctx, int enable);
+
 /* Scattering-angle recovery (eq. angle_recovery and the empirical-CDF errors
  * defined after it).  While a log is enabled, every accepted collision of
  * pic_step and pic_collide appends chi = acos(g'_z / g) and

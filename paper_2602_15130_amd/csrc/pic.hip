@@ -38,7 +38,7 @@ enum Arr {
   A_KEY, A_SLOT, A_TIDX, A_TKEY, A_D, A_U, A_V0G,
   A_COUNT, A_CSTART, A_BSUM, A_TILE, A_MOM, A_RHO, A_B, A_PHI, A_E, A_E32, A_CGV, A_LOW,
   A_PART_A, A_PART_B, A_EPART, A_NPART, A_NORMS, A_BAR, A_RESULT, A_FLAGS, A_CNT, A_CGIT, A_CGRR,
-  A_DEFER,
+  A_DEFER, A_STEPC, A_MIXC,
   A_NARR
 };
 
@@ -91,6 +91,8 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_CGIT] = 4;
   b[A_CGRR] = 8;
   b[A_DEFER] = ((np + kTileB - 1) / kTileB + 2) * 4;  // tiles the lean pass leaves to the general one
+  b[A_STEPC] = 8;                   // completed steps, for captured steps
+  b[A_MIXC] = sizeof(MixConst);     // the mixed pass's constants of a captured step
   int64_t t = 0;
   for (int i = 0; i < A_NARR; ++i) {
     L.off[i] = t;
@@ -249,6 +251,14 @@ struct pic_ctx {
   float* Df{};
   bool fused = true;
   bool lean_pass = true;        // lean pass instance first, general one for the tiles it defers
+  // Captured steps (pic_use_graphs): two steps per graph, one graph per
+  // double-buffer parity, recorded on a private stream and replayed on the
+  // context's stream; kernels then take the step from *stepc.
+  bool graphs = false, capturing = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
+  long long* stepc = nullptr;
+  MixConst* mixc = nullptr;
   int* defer = nullptr;         // the deferred tiles (count, done, list)
   void* mom{};
   double *rho{}, *b{}, *phi{}, *E{}, *cgv{}, *lowbuf{}, *partA{}, *partB{};
@@ -271,6 +281,9 @@ struct pic_ctx {
   ~pic_ctx() {
     for (auto& t : timed) event_pool.push_back(t.a), event_pool.push_back(t.b);
     for (auto e : event_pool) (void)hipEventDestroy(e);
+    for (auto& g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -452,7 +465,7 @@ int field_solve(pic_ctx* c, double t) {
         k_deposit_moments_f64<<<nbn, kBlock, 0, c->stream>>>(K, c->x[c->cur], c->cstart,
                                                              (double*)c->mom);
       k_node_rhs<double><<<G(c, nbn), kBlock, 0, c->stream>>>(K, (const double*)c->mom, t, c->rho, c->b,
-                                                        c->partA);
+                                                        c->partA, c->capturing ? c->stepc : nullptr);
     } else {
       if (!have_mom && c->fused)
         k_deposit_tiles_mixed<<<G(c, ntiles), kTileThreads, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
@@ -461,7 +474,7 @@ int field_solve(pic_ctx* c, double t) {
         k_deposit_moments_mixed<<<nbn, kBlock, 0, c->stream>>>(K, c->off[c->cur], c->cstart,
                                                                (float*)c->mom);
       k_node_rhs_mixed<<<G(c, nbn), kBlock, 0, c->stream>>>(K, (const float*)c->mom, t, c->rho, c->b,
-                                                      c->partA);
+                                                      c->partA, c->capturing ? c->stepc : nullptr);
     }
     // also zeroes the solver's arrival flags and release word
     k_sub_mean<<<G(c, nbn), kBlock, 0, c->stream>>>(K, c->b, c->partA, nbn, c->bar,
@@ -511,7 +524,7 @@ int field_solve(pic_ctx* c, double t) {
   // its workgroups not all be resident, the bounded barrier wait raises the
   // barrier flag instead of hanging.
   auto launch = [&](dim3 grid) {
-    return c->plain_cg_launch
+    return (c->plain_cg_launch || c->capturing)
                ? hipLaunchKernel(c->cg_fn, grid, dim3(c->cg_nt), args, c->cg_lds, c->stream)
                : hipLaunchCooperativeKernel(c->cg_fn, grid, dim3(c->cg_nt), args, c->cg_lds,
                                             c->stream);
@@ -614,6 +627,16 @@ PartArgs part_args(pic_ctx* c) {
   return a;
 }
 
+// A captured step's pass constants: step nb = *stepc (call B and the end of
+// that step), na = nb + 1, and the mixed pass's FP32 constants at those times.
+__global__ void k_step_consts(SimConst K, PartArgs a, MixConst* out) {
+  a.nb = *K.stepc;
+  a.na = a.nb + 1;
+  *out = mix_const(K, a);
+}
+// The end of a captured step.
+__global__ void k_step_advance(long long* stepc) { *stepc += 1; }
+
 // Instances of the fused passes: the full one (angle and pair logs, the
 // anisotropic samplers), the general lean one and the lean one that leaves
 // the tiles it cannot run on lanes alone to the general one.
@@ -690,6 +713,14 @@ int particle_pass(pic_ctx* c, int mode, int64_t nb, int64_t na) {
   a.mode = mode;
   a.nb = nb;
   a.na = na;
+  if (c->capturing) {  // the step index (and the mixed pass's constants) from the device
+    a.step_dev = 1;
+    a.mixc = c->mixc;
+    if (c->precision == PIC_MIXED) {
+      k_step_consts<<<1, 1, 0, c->stream>>>(c->K, a, c->mixc);
+      LAUNCH_CHECK(c, "step constants");
+    }
+  }
   TRY(launch_particles(c, a));
   return PIC_OK;
 }
@@ -697,17 +728,85 @@ int particle_pass(pic_ctx* c, int mode, int64_t nb, int64_t na) {
 // n_steps of eq. velocity_verlet with the fused particle pass: the pass after
 // each field solve finishes step s (call B, kick 2) and starts step s + 1
 // (call A, kick 1, drift).
-int fused_steps(pic_ctx* c, int n_steps) {
-  for (int i = 0; i < n_steps; ++i) {
-    const int64_t s = c->step;
-    if (i == 0) TRY(particle_pass(c, kDoA, 0, s));
-    TRY(sort_particles(c));
-    TRY(field_solve(c, ((double)s + 1.0) * c->K.dt));
-    if (i == n_steps - 1) TRY(particle_pass(c, kDoB, s, 0));
-    else TRY(particle_pass(c, kDoB | kDoA, s, s + 1));
-    c->step = s + 1;
+// One inner iteration of the fused stepping: sort, field solve at t^{s+1},
+// and the pass that finishes step s and starts step s + 1.
+int inner_step(pic_ctx* c) {
+  const int64_t s = c->step;
+  TRY(sort_particles(c));
+  TRY(field_solve(c, ((double)s + 1.0) * c->K.dt));
+  TRY(particle_pass(c, kDoB | kDoA, s, s + 1));
+  if (c->capturing) {
+    k_step_advance<<<1, 1, 0, c->stream>>>(c->stepc);
+    LAUNCH_CHECK(c, "step advance");
   }
+  c->step = s + 1;
   return PIC_OK;
+}
+
+// Records two inner iterations into the graph of the current buffer parity.
+// Nothing runs while recording; the host bookkeeping (buffer parity, flags)
+// advances as the two iterations would, and is back where it started after
+// them, so the graph replays from any even offset of that parity.
+int capture_two_steps(pic_ctx* c) {
+  const int par = c->cur;
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const hipStream_t user = c->stream;
+  const int64_t step0 = c->step;
+  c->stream = c->cap_stream;
+  c->capturing = true;
+  int rc = PIC_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = PIC_EHIP;
+  } else {
+    for (int i = 0; i < 2 && rc == PIC_OK; ++i) rc = inner_step(c);
+    if (hipStreamEndCapture(c->cap_stream, &g) != hipSuccess && rc == PIC_OK) rc = PIC_EHIP;
+  }
+  c->capturing = false;
+  c->stream = user;
+  c->step = step0;
+  if (rc == PIC_OK && c->cur != par) rc = PIC_EHIP;  // (the parity returns after two steps)
+  if (rc == PIC_OK && hipGraphInstantiate(&c->gexec[par], g, nullptr, nullptr, 0) != hipSuccess)
+    rc = PIC_EHIP;
+  if (g) (void)hipGraphDestroy(g);
+  if (rc != PIC_OK) {
+    (void)hipGetLastError();
+    c->err = "step capture failed";
+  }
+  return rc;
+}
+
+int fused_steps(pic_ctx* c, int n_steps) {
+  if (n_steps <= 0) return PIC_OK;
+  TRY(particle_pass(c, kDoA, 0, c->step));
+  int inner = n_steps - 1;
+  if (c->graphs && !c->timing && inner >= 2) {
+    // the device counter starts at the host's; each replay advances both by two
+    TRY(fill<long long>(c, c->stepc, (long long)c->step, 1));
+    while (inner >= 2) {
+      if (!c->gexec[c->cur]) TRY(capture_two_steps(c));
+      HIP_TRY(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
+      c->step += 2;
+      inner -= 2;
+    }
+  }
+  for (; inner > 0; --inner) TRY(inner_step(c));
+  const int64_t s = c->step;
+  TRY(sort_particles(c));
+  TRY(field_solve(c, ((double)s + 1.0) * c->K.dt));
+  TRY(particle_pass(c, kDoB, s, 0));
+  c->step = s + 1;
+  return PIC_OK;
+}
+
+// Recorded steps bake in the context's constants and launch choices: drop
+// them whenever those change.
+void drop_graphs(pic_ctx* c) {
+  for (auto& g : c->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 
 int one_step(pic_ctx* c) {
@@ -995,6 +1094,9 @@ int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* dis
   c->cgit = carve<int>(c, A_CGIT);
   c->cgrr = carve<double>(c, A_CGRR);
   c->defer = carve<int>(c, A_DEFER);
+  c->stepc = carve<long long>(c, A_STEPC);  // member 0's: one counter for all members
+  c->mixc = carve<MixConst>(c, A_MIXC);
+  c->K.stepc = c->stepc;
 
   // Cooperative grid for the Poisson solver: one block per CU at most, never
   // more than the node count needs, and never more than can be co-resident.
@@ -1360,6 +1462,7 @@ int pic_checkpoint_save(pic_ctx* c, void* host_dst, int64_t bytes) {
 }
 
 int pic_checkpoint_load(pic_ctx* c, const void* host_src, int64_t bytes) {
+  if (c) drop_graphs(c);
   if (!c || !c->ready) return PIC_ESTATE;
   TRY(single_only(c, "pic_checkpoint_load"));
   if (!host_src || bytes < (int64_t)sizeof(CkptHeader)) {
@@ -1401,6 +1504,7 @@ int64_t pic_angle_buffer_bytes(int64_t capacity) {
 }
 
 int pic_angle_log(pic_ctx* c, void* buffer, int64_t capacity) {
+  if (c) drop_graphs(c);  // the log selects another pass instance
   if (!c || !c->ready) return PIC_ESTATE;
   TRY(single_only(c, "pic_angle_log"));
   if (capacity < 0 || (capacity > 0 && !buffer)) {
@@ -1594,6 +1698,17 @@ int pic_set_state(pic_ctx* c, int item, const void* host_src, int64_t bytes) {
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return check_flags(c);
+}
+
+int pic_use_graphs(pic_ctx* c, int enable) {
+  if (!c || !c->ready) return PIC_ESTATE;
+  if (!c->fused) {
+    c->err = "captured steps need the fused step (not PIC_UNFUSED, not the collision-heavy FP64 mode)";
+    return PIC_EINVAL;
+  }
+  c->graphs = enable != 0;
+  if (!c->graphs) drop_graphs(c);
+  return PIC_OK;
 }
 
 int pic_timing_stages(pic_ctx* c, uint32_t mask) {

@@ -63,6 +63,9 @@ struct SimConst {
   int chi_model;       // polar-angle model: 0 isotropic, 1 manufactured anisotropy, 2 VSS
   double chi_alpha;    // VSS exponent
   int coding_error;    // Sec. 5.4.1 Error 1 / Error 2 (verification studies), 0 none
+  // completed steps, kept on the device for captured steps (shared by all
+  // ensemble members; null when unused)
+  const long long* stepc;
   double* anglog;      // scattering-angle records (chi, eps) of accepted collisions, or null
   int64_t angcap;      // records that fit
   // Ensembles: the members of one context share every size and differ only in

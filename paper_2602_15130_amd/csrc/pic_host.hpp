@@ -89,8 +89,9 @@ inline SimConst derive(const pic_problem* p, const pic_discretization* d, uint64
 }
 
 // vhat(t) and vhat'(t) of the paper's velocity distribution (Sec. 5.2), or
-// vbar and 0 for the configuration family.
-inline void host_vhat(const SimConst& K, double t, double vh[3], double vd[3]) {
+// vbar and 0 for the configuration family.  (Host and device: a captured step
+// computes the constants of its pass on the device from the step counter.)
+__host__ __device__ inline void host_vhat(const SimConst& K, double t, double vh[3], double vd[3]) {
   if (K.family == 1) {
     for (int d = 0; d < 3; ++d) {
       vh[d] = K.vbar;
@@ -99,37 +100,36 @@ inline void host_vhat(const SimConst& K, double t, double vh[3], double vd[3]) {
     return;
   }
   const double u = t / K.T;
-  vh[0] = (1.0 + 0.2 * std::sin(0.5 * kPi * u)) * K.vbar;
-  vh[1] = (1.0 + 0.2 * std::cos(kPi * u)) * K.vbar;
-  vh[2] = (1.0 + 0.2 * std::sin(1.5 * kPi * u)) * K.vbar;
-  vd[0] = 0.2 * (0.5 * kPi / K.T) * std::cos(0.5 * kPi * u) * K.vbar;
-  vd[1] = -0.2 * (kPi / K.T) * std::sin(kPi * u) * K.vbar;
-  vd[2] = 0.2 * (1.5 * kPi / K.T) * std::cos(1.5 * kPi * u) * K.vbar;
+  vh[0] = (1.0 + 0.2 * sin(0.5 * kPi * u)) * K.vbar;
+  vh[1] = (1.0 + 0.2 * cos(kPi * u)) * K.vbar;
+  vh[2] = (1.0 + 0.2 * sin(1.5 * kPi * u)) * K.vbar;
+  vd[0] = 0.2 * (0.5 * kPi / K.T) * cos(0.5 * kPi * u) * K.vbar;
+  vd[1] = -0.2 * (kPi / K.T) * sin(kPi * u) * K.vbar;
+  vd[2] = 0.2 * (1.5 * kPi / K.T) * cos(1.5 * kPi * u) * K.vbar;
 }
 
 // FP32 constants of one mixed-form pass with arguments a: call B and its kick
 // at the end of step a.nb, call A and its kick and the drift of step a.na
 // (collide-only: call A's source at time a.tB).
-inline MixConst mix_const(const SimConst& K, const PartArgs& a) {
+__host__ __device__ inline MixConst mix_const(const SimConst& K, const PartArgs& a) {
   const double dt = K.dt;
   const double tA = (double)a.na * dt, tB = ((double)a.nb + 1.0) * dt;  // the two kicks
-  MixConst M;
-  std::memset(&M, 0, sizeof(M));
+  MixConst M{};
   M.dt = (float)dt;
   M.dtqm = (float)(dt * K.qm);
   for (int d = 0; d < 3; ++d) {
     M.inv_h[d] = (float)K.inv_h[d];
     M.inv_n[d] = (float)(1.0 / K.nc[d]);
     const double kd = 2.0 * kPi / K.L[d];
-    M.emA[d] = (float)(K.phibar * std::exp(tA / (2.0 * K.T)) * kd);
-    M.emB[d] = (float)(K.phibar * std::exp(tB / (2.0 * K.T)) * kd);
+    M.emA[d] = (float)(K.phibar * exp(tA / (2.0 * K.T)) * kd);
+    M.emB[d] = (float)(K.phibar * exp(tB / (2.0 * K.T)) * kd);
   }
   M.vbar = (float)K.vbar;
   M.src_w = (float)(K.w * K.dt / (2.0 * K.dV));
   M.sigma_ref = (float)K.sigma_ref;
   M.inv_vbar = (float)(1.0 / K.vbar);
   for (int n = 0; n < 3; ++n)
-    M.pc[n] = (float)(K.sigma_n[n] * std::pow(K.vbar, 2.0 * n + 1.0));
+    M.pc[n] = (float)(K.sigma_n[n] * pow(K.vbar, 2.0 * n + 1.0));
   // kick B at t^{nb+1} (from t^{nb+1/2}), source at t^{nb+1/2}; kick A at t^{na}
   // (to t^{na+1/2}), source at t^{na}; drift at t^{na+1/2}
   const double thB = ((double)a.nb + 0.5) * dt, thA = ((double)a.na + 0.5) * dt;

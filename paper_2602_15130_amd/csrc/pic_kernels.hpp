@@ -487,7 +487,9 @@ __device__ inline double rhs_manufactured(const SimConst& K, int i, int j, int k
 // of b for the mean removal.
 template <class MomT>
 __global__ void __launch_bounds__(kBlock) k_node_rhs(SimConst K, const MomT* mom, double t,
-                                                     double* rho, double* b, double* part) {
+                                                     double* rho, double* b, double* part,
+                                                     const long long* tstep) {
+  if (tstep) t = ((double)*tstep + 1.0) * K.dt;  // a captured step: the end of step *tstep
   mom = mem(K, mom);
   rho = mem(K, rho);
   b = mem(K, b);
@@ -626,6 +628,18 @@ __device__ inline bool grid_sum_t(const CgArgs& a, double* vals, int nv, unsigne
   __shared__ int ok;
   __shared__ double res[kMaxRed];
   double tot[kMaxRed];
+  if (gridDim.x == 1) {
+    // One workgroup per solve: the block sum is the grid sum (the value the
+    // flag protocol below would return, plus exact zeros); the workgroup
+    // barrier inside it, after every wave's stores have completed, is the
+    // ordering the solver's sweeps and face exchange need.
+    wait_vector_memory();
+    block_sum3_t<NT>(vals, nv, sh);
+    // (as after the flag protocol: later plain loads must not hit lines of
+    // this CU's cache that other waves' stores have made stale)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+  }
   // Every wave waits until its own global stores have reached L2 before the
   // block barrier; thread 0's agent-scope release below then writes back L2
   // and so publishes the whole block's stores with its flag.  (A workgroup

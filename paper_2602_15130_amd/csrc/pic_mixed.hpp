@@ -194,7 +194,9 @@ __global__ void __launch_bounds__(kTileThreads) k_deposit_tiles_mixed(SimConst K
 // Node charge from the compensated FP32 cell moments (summed in FP64) and the
 // right-hand side of eq. poisson_mms; block partial sums of b.
 __global__ void __launch_bounds__(kBlock) k_node_rhs_mixed(SimConst K, const float* mom, double t,
-                                                           double* rho, double* b, double* part) {
+                                                           double* rho, double* b, double* part,
+                                                           const long long* tstep) {
+  if (tstep) t = ((double)*tstep + 1.0) * K.dt;  // a captured step: the end of step *tstep
   mom = mem(K, mom);
   rho = mem(K, rho);
   b = mem(K, b);
@@ -362,6 +364,11 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : (FAST ? PIC_MIXED
   vf = mem(K, vf);
   ash = mem(K, ash);
   E32 = mem(K, E32);
+  if (a.step_dev) {  // a captured step: its step index and constants from the device
+    M = *a.mixc;
+    a.nb = *K.stepc;
+    a.na = a.nb + 1;
+  }
   // Tile-resident copies of what the pass reads per particle more than once
   // (the velocity shape is read once, in the drift, straight from memory), and
   // the field acceleration kept from kick B for kick A; the copy-on-write

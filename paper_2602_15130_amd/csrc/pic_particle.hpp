@@ -79,6 +79,10 @@ struct PartArgs {
   // the list when defer_list is set, else through all tiles
   int* defer;
   int ntiles, defer_list;
+  // captured steps: nb = *K.stepc, na = nb + 1, and (mixed form) the pass's
+  // FP32 constants from mixc, written by k_step_consts
+  int step_dev;
+  const struct MixConst* mixc;
   int mode;
   int64_t nb, na;       // step index of call B (second half) and of call A (first half)
   int callB, callA;     // random-stream call tags (collide-only mode uses callA)
@@ -747,6 +751,10 @@ template <int FAM, int SIG, bool FULL, bool FAST>
 __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : (FAST ? PIC_F64_LEAN_WAVES : PIC_F64_WAVES))
     k_particles_f64(SimConst K, PartArgs a) {
   a = member_view(K, a);
+  if (a.step_dev) {  // a captured step: its step index from the device
+    a.nb = *K.stepc;
+    a.na = a.nb + 1;
+  }
   // the copy-on-write scratch of outcomes run by a cell thread is global
   __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots], lacc[3 * kLdsSlots];
   __shared__ int lkey[kLdsSlots];

@@ -6,9 +6,11 @@ streams, key (seed, replicate)).
 
 Each level runs as ensemble contexts of the C ABI (pic_ensemble_init): all
 members of a context advance together, one launch per stage for all of them,
-so small meshes are not bound by launch latency.  A small autotuner picks the
-Poisson solver's workgroup count per member for each (device, level, members)
-by timing two steps per choice, and keeps the result in a JSON cache.
+so small meshes are not bound by launch latency, and the steps are replayed
+from recorded two-step HIP graphs (pic_use_graphs).  A small autotuner picks
+the Poisson solver's workgroup count per member for each (device, level,
+members) by timing a few steps per choice, and keeps the result in a JSON
+cache.
 """
 from __future__ import annotations
 
@@ -23,7 +25,7 @@ from . import pic
 from . import workloads as W
 
 # workgroups per member of the Poisson solver tried by the autotuner
-CG_GRID_CHOICES = (256, 128, 64, 32, 16, 8)
+CG_GRID_CHOICES = (256, 128, 64, 32, 16, 8, 4, 2, 1)
 # workspace bytes of one ensemble context at most (larger levels are split
 # into several contexts run one after the other)
 MAX_CONTEXT_BYTES = 96 << 30
@@ -50,13 +52,13 @@ def _cache_path():
     return os.path.join(root, "paper_2602_15130_amd", "tune.json")
 
 
-def _cache_key(prob, disc, precision, members):
+def _cache_key(prob, disc, precision, members, graphs):
     import torch
 
     dev = torch.cuda.get_device_name(0)
     nc = "x".join(str(n) for n in disc["nc"])
     return f"{dev}|{nc}|np{disc['np']}|navg{disc['navg']}|{precision}|m{members}|" \
-           f"coll{int(bool(prob.get('collisions', True)))}"
+           f"coll{int(bool(prob.get('collisions', True)))}|graphs{int(bool(graphs))}"
 
 
 def _load_cache():
@@ -85,13 +87,15 @@ def members_per_context(prob, disc, precision, members):
     return max(1, min(members, MAX_CONTEXT_BYTES // max(one, 1)))
 
 
-def _time_steps(prob, disc, precision, members, blocks, steps=2, seed=1):
+def _time_steps(prob, disc, precision, members, blocks, steps=4, seed=1, graphs=True):
     import torch
 
     def make():
         return pic.Ensemble(prob, disc, seed, 0, members, precision)
 
     with _with_env("PIC_CG_BLOCKS", blocks, make) as ens:
+        if graphs:
+            ens.use_graphs(True)
         ens.step(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -102,17 +106,17 @@ def _time_steps(prob, disc, precision, members, blocks, steps=2, seed=1):
     return 1e3 * dt / steps, st
 
 
-def autotune(prob, disc, precision, members, choices=CG_GRID_CHOICES, use_cache=True):
+def autotune(prob, disc, precision, members, choices=CG_GRID_CHOICES, use_cache=True, graphs=True):
     """The solver workgroup count per member that steps an ensemble of
     `members` fastest; returns (blocks, {choice: ms per step}, from_cache)."""
-    key = _cache_key(prob, disc, precision, members)
+    key = _cache_key(prob, disc, precision, members, graphs)
     cache = _load_cache() if use_cache else {}
     if key in cache:
         rec = cache[key]
         return rec["cg_blocks"], {int(k): v for k, v in rec["ms_per_step"].items()}, True
     timings, seen = {}, set()
     for b in choices:
-        ms, st = _time_steps(prob, disc, precision, members, b)
+        ms, st = _time_steps(prob, disc, precision, members, b, graphs=graphs)
         # the library fits the request to the mesh and the GPU; requests that
         # end in the same solver grid are timed once
         if st["cg_blocks"] in seen:
@@ -127,7 +131,7 @@ def autotune(prob, disc, precision, members, choices=CG_GRID_CHOICES, use_cache=
     return best, timings, False
 
 
-def run_level(prob, disc, precision, replicates, seed=1, cg_blocks=None):
+def run_level(prob, disc, precision, replicates, seed=1, cg_blocks=None, graphs=True):
     """Every replicate of one level to its final step, members of one context
     at a time (replicates must be consecutive).  Returns the l2 and linf norms
     per replicate ([R, 7] arrays), the stepping wall time (init and norms
@@ -148,6 +152,8 @@ def run_level(prob, disc, precision, replicates, seed=1, cg_blocks=None):
             return pic.Ensemble(prob, disc, seed, first, n, precision)
 
         with _with_env("PIC_CG_BLOCKS", cg_blocks, make) as ens:
+            if graphs:
+                ens.use_graphs(True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ens.step(disc["steps"])
@@ -165,22 +171,23 @@ def run_level(prob, disc, precision, replicates, seed=1, cg_blocks=None):
 
 
 def run_ensemble(levels=None, replicates=32, precision="mixed", seed=1, tune=True, n_levels=5,
-                 use_cache=True):
+                 use_cache=True, graphs=True):
     """The refinement ensemble (mesh 8^3 * 2^l, 8 particles per cell, dt halved
     per level to t = 0.01, two-way coupling, hard-sphere NTC with 16 outcomes):
     per level the replicate norms, their mean and standard deviation, and the
     observed orders of the means."""
     levels = levels if levels is not None else W.ensemble_levels(n_levels)
     reps = list(range(replicates))
-    out = {"precision": precision, "replicates": replicates, "levels": []}
+    out = {"precision": precision, "replicates": replicates, "graphs": bool(graphs), "levels": []}
     total_ps, total_t = 0, 0.0
     for L in levels:
         prob, disc = L["problem"], L["disc"]
         blocks, timings, cached = None, None, None
         if tune:
             members = min(replicates, members_per_context(prob, disc, precision, replicates))
-            blocks, timings, cached = autotune(prob, disc, precision, members, use_cache=use_cache)
-        l2, linf, wall, solver = run_level(prob, disc, precision, reps, seed, blocks)
+            blocks, timings, cached = autotune(prob, disc, precision, members, use_cache=use_cache,
+                                               graphs=graphs)
+        l2, linf, wall, solver = run_level(prob, disc, precision, reps, seed, blocks, graphs)
         ps = disc["np"] * disc["steps"] * len(reps)
         total_ps += ps
         total_t += wall

@@ -113,7 +113,7 @@ EXPORTED = ("pic_workspace_size", "pic_init_manufactured", "pic_step", "pic_coll
             "pic_angle_buffer_bytes", "pic_angle_log", "pic_angle_errors",
             "pic_checkpoint_bytes", "pic_checkpoint_save", "pic_checkpoint_load",
             "pic_ensemble_workspace_size", "pic_ensemble_init", "pic_ensemble_errors",
-            "pic_ensemble_get_state", "pic_last_error")
+            "pic_ensemble_get_state", "pic_use_graphs", "pic_last_error")
 STAGES = ("collide", "kick", "drift", "sort", "deposit", "cg", "gradient", "particle")
 
 
@@ -251,6 +251,10 @@ def pic_get_state(ctx, item: int, out: np.ndarray):
 def pic_set_state(ctx, item: int, src: np.ndarray):
     src = np.ascontiguousarray(src, dtype=np.float64)
     return _check(lib.pic_set_state(ctx, int(item), src.ctypes.data, src.nbytes), ctx)
+
+
+def pic_use_graphs(ctx, enable: bool):
+    return _check(lib.pic_use_graphs(ctx, int(bool(enable))), ctx)
 
 
 def pic_timing_enable(ctx, enable: bool):
@@ -396,6 +400,10 @@ class Sim:
         raw = self._ang[off: off + 16 * n].view(torch.float64)
         return raw.cpu().numpy().reshape(n, 2)
 
+    def use_graphs(self, enable: bool = True):
+        """Replay recorded two-step graphs in pic_step (bitwise the same results)."""
+        pic_use_graphs(self.ctx, enable)
+
     def timing(self, enable: bool):
         pic_timing_enable(self.ctx, enable)
 
@@ -453,6 +461,7 @@ class Ensemble:
     __del__ = Sim.__del__
     step = Sim.step
     stats = Sim.stats
+    use_graphs = Sim.use_graphs
     timing = Sim.timing
     timing_stages = Sim.timing_stages
     timing_read = Sim.timing_read
