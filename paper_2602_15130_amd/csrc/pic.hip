@@ -620,6 +620,7 @@ PartArgs part_args(pic_ctx* c) {
   a.counters = c->cnt;
   a.flags = c->flags;
   a.defer = c->defer;
+  a.mixc = c->mixc;
   a.ntiles = (int)((c->K.np + kTileB - 1) / kTileB);
   a.defer_list = 0;
   a.callB = 1;
@@ -627,11 +628,13 @@ PartArgs part_args(pic_ctx* c) {
   return a;
 }
 
-// A captured step's pass constants: step nb = *stepc (call B and the end of
-// that step), na = nb + 1, and the mixed pass's FP32 constants at those times.
+// A captured step's mixed-pass FP32 constants (one thread): nb = *stepc
+// (call B and the end of that step), na = nb + 1, written for the pass to read.
 __global__ void k_step_consts(SimConst K, PartArgs a, MixConst* out) {
-  a.nb = *K.stepc;
-  a.na = a.nb + 1;
+  if (a.step_dev) {
+    a.nb = *K.stepc;
+    a.na = a.nb + 1;
+  }
   *out = mix_const(K, a);
 }
 // The end of a captured step.
@@ -643,13 +646,16 @@ __global__ void k_step_advance(long long* stepc) { *stepc += 1; }
 using MixedFn = void (*)(SimConst, MixConst, PartArgs, float*, float*, const float*, const float*);
 using F64Fn = void (*)(SimConst, PartArgs);
 struct PassFns {
-  MixedFn mixed[3];  // full, general, fast
+  MixedFn mixed[3];      // full, general, fast
+  MixedFn mixed_dev[3];  // (none), general, fast of captured steps
   F64Fn f64[3];
 };
 template <int FAM, int SIG>
 PassFns pass_fns() {
   return {{k_particles_mixed<FAM, SIG, true, false>, k_particles_mixed<FAM, SIG, false, false>,
            k_particles_mixed<FAM, SIG, false, true>},
+          {nullptr, k_particles_mixed<FAM, SIG, false, false, true>,
+           k_particles_mixed<FAM, SIG, false, true, true>},
           {k_particles_f64<FAM, SIG, true, false>, k_particles_f64<FAM, SIG, false, false>,
            k_particles_f64<FAM, SIG, false, true>}};
 }
@@ -684,15 +690,25 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
   ag.defer_list = lean ? 1 : 0;
   const dim3 grid_general = G(c, lean ? std::min(tiles, kDeferGrid) : tiles);
   if (c->precision == PIC_MIXED) {
-    const MixConst M = mix_const(K, a);
+    const MixConst M = mix_const(K, a);  // (a captured step computes them on the device)
+    const MixedFn* fm = fns.mixed;
+    if (a.step_dev) {
+      if (full) {
+        c->err = "captured steps do not run the full pass instance";
+        return PIC_EINVAL;
+      }
+      k_step_consts<<<1, 1, 0, c->stream>>>(K, a, c->mixc);
+      LAUNCH_CHECK(c, "pass constants");
+      fm = fns.mixed_dev;
+    }
     const int s = c->cur;
     if (lean) {
-      fns.mixed[2]<<<G(c, tiles), dim3(kTileThreads), 0, c->stream>>>(K, M, a, c->off[s], c->vf[s],
-                                                                      c->asf[s], c->E32);
+      fm[2]<<<G(c, tiles), dim3(kTileThreads), 0, c->stream>>>(K, M, a, c->off[s], c->vf[s],
+                                                              c->asf[s], c->E32);
       LAUNCH_CHECK(c, "particles (mixed, lean)");
     }
-    fns.mixed[which]<<<grid_general, dim3(kTileThreads), 0, c->stream>>>(K, M, ag, c->off[s], c->vf[s],
-                                                                        c->asf[s], c->E32);
+    fm[which]<<<grid_general, dim3(kTileThreads), 0, c->stream>>>(K, M, ag, c->off[s], c->vf[s],
+                                                                c->asf[s], c->E32);
     LAUNCH_CHECK(c, "particles (mixed)");
     return PIC_OK;
   }
@@ -713,14 +729,7 @@ int particle_pass(pic_ctx* c, int mode, int64_t nb, int64_t na) {
   a.mode = mode;
   a.nb = nb;
   a.na = na;
-  if (c->capturing) {  // the step index (and the mixed pass's constants) from the device
-    a.step_dev = 1;
-    a.mixc = c->mixc;
-    if (c->precision == PIC_MIXED) {
-      k_step_consts<<<1, 1, 0, c->stream>>>(c->K, a, c->mixc);
-      LAUNCH_CHECK(c, "step constants");
-    }
-  }
+  if (c->capturing) a.step_dev = 1;  // the step index from the device
   TRY(launch_particles(c, a));
   return PIC_OK;
 }
@@ -780,7 +789,10 @@ int fused_steps(pic_ctx* c, int n_steps) {
   if (n_steps <= 0) return PIC_OK;
   TRY(particle_pass(c, kDoA, 0, c->step));
   int inner = n_steps - 1;
-  if (c->graphs && !c->timing && inner >= 2) {
+  // (runs that need the full pass instance, the angle log, anisotropic
+  // scattering or a coding error, step without graphs)
+  const bool full = c->K.anglog != nullptr || c->K.chi_model != PIC_CHI_ISO || c->K.coding_error != 0;
+  if (c->graphs && !c->timing && !full && inner >= 2) {
     // the device counter starts at the host's; each replay advances both by two
     TRY(fill<long long>(c, c->stepc, (long long)c->step, 1));
     while (inner >= 2) {

@@ -355,7 +355,9 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 // is latency bound, and the extra resident waves outweigh the spills); the
 // paper family's instances (FP64 root solves in the drift and the source) get
 // four (128 VGPRs).
-template <int FAM, int SIG, bool FULL, bool FAST>
+// DEVC: the instances of captured steps, which take the pass's constants
+// from the device (written by k_step_consts) instead of the argument.
+template <int FAM, int SIG, bool FULL, bool FAST, bool DEVC = false>
 __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : (FAST ? PIC_MIXED_LEAN_WAVES : PIC_MIXED_WAVES)) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
@@ -364,7 +366,7 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : (FAST ? PIC_MIXED
   vf = mem(K, vf);
   ash = mem(K, ash);
   E32 = mem(K, E32);
-  if (a.step_dev) {  // a captured step: its step index and constants from the device
+  if constexpr (DEVC) {  // a captured step: its step index and constants from the device
     M = *a.mixc;
     a.nb = *K.stepc;
     a.na = a.nb + 1;

@@ -79,8 +79,8 @@ struct PartArgs {
   // the list when defer_list is set, else through all tiles
   int* defer;
   int ntiles, defer_list;
-  // captured steps: nb = *K.stepc, na = nb + 1, and (mixed form) the pass's
-  // FP32 constants from mixc, written by k_step_consts
+  // captured steps: nb = *K.stepc, na = nb + 1; the mixed pass reads its FP32
+  // constants from mixc, written by k_step_consts before every pass
   int step_dev;
   const struct MixConst* mixc;
   int mode;
@@ -568,9 +568,12 @@ __device__ inline void tile_zero_D(int ns, int st, R* D) {
   for (int j = threadIdx.x; j < ns; j += kTileThreads) D[j] = D[st + j] = D[2 * st + j] = (R)0.0;
 }
 
-// One collision call over the tile (draw, then run; list 0).
+// One collision call over the tile (draw, then run; list 0).  Inlined: as an
+// out-of-line call its frame would give every wave of the pass a large
+// private segment, which slows the whole launch even when no collide-only
+// call runs.
 template <int SIG, class R, bool FULL, class Lds>
-__device__ inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
+__device__ __attribute__((always_inline)) inline void tile_collide(const SimConst& K, const PartArgs& a, int call,
                                     int64_t step, int c0, int ncells, int s0, int ns,
                                     const R* v0, R* u, R* D, int* mark, int* tl, int tagbase,
                                     int st, int stu, Lds& L) {
