@@ -256,6 +256,8 @@ def main():
                     help="second workload timed beside the first (the FP64 form); 'none' to skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads' records (cfg1, 128^3, paper family at 64^3)")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the refinement-ensemble (cfg4) block of the default line")
     ap.add_argument("--levels", default="1,2,3", help="Table 1 levels for --workload table1")
@@ -300,6 +302,19 @@ def main():
         progress("convergence ladder")
         out["convergence"] = convergence_report(pic, W)
         out["convergence"]["paper_ladder"] = paper_ladder_report(pic, W)
+    if not args.no_extra:
+        # the other single-GPU workloads, each as a compact record (20 timed
+        # steps): the 32^3 two-way collisionless FP64 case, the 128^3
+        # single-simulation point and the paper's own functions at 64^3
+        out["more_workloads"] = {}
+        for w in ("cfg1", "cfg3_128", "cfg3_paper", "cfg2_paper"):
+            progress(f"timing {w}")
+            r = run_workload(pic, W, torch, w, min(args.steps, 20), 2)
+            out["more_workloads"][w] = {
+                "value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
+                "dtype": r["dtype"], "config": r["config"], "stages": r["stages"],
+                "roofline": {k: r["roofline"][k] for k in ("kernel", "achieved", "frac",
+                                                           "us_per_step")}}
     if not args.no_ensemble:
         progress("refinement ensemble (cfg4)")
         e = run_ensemble_bench()
@@ -461,7 +476,8 @@ def run_workload(pic, W, torch, workload, steps, warmup):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic (manufactured solution, Philox seed %d)" % seed,
-        "config": {"workload": workload, "mesh": list(disc["nc"]), "particles": disc["np"],
+        "config": {"workload": workload, "family": prob["family"], "mesh": list(disc["nc"]),
+                   "particles": disc["np"],
                    "n_avg": disc["navg"], "dt": disc["dt"], "precision": precision,
                    "collisions": bool(prob["collisions"]), "two_way": bool(prob["particles_to_field"])},
         "roofline": roof,

@@ -113,7 +113,28 @@ CONFIGS = {
     # Mixed-precision form of cfg2.
     "cfg3": {"problem": cfg_problem(two_way=True, collisions=True),
              "disc": cfg_disc(64, 1 << 23, 2.5e-4, 100, 16), "precision": "mixed", "seed": 1},
+    # The single-simulation point at 128^3: 67,108,864 particles (32 per cell),
+    # the cfg3 physics with dt halved.
+    "cfg3_128": {"problem": cfg_problem(two_way=True, collisions=True),
+                 "disc": cfg_disc(128, 1 << 26, 1.25e-4, 100, 16), "precision": "mixed", "seed": 1},
 }
+
+
+def _paper_64(precision):
+    """The paper's own functions and SI constants (Sec. 5.2, L = 1.5 m, T =
+    L / (10 vbar)) at the throughput size: 64^3 cells, 8,388,608 particles,
+    fully coupled and collisional, dt = T / 64 (Table 1's T / dt = N_cell),
+    16 averaged outcomes.  Every drift solves the manufactured positions
+    (eq. mms_sol) by FP64 roots."""
+    n = 64
+    return {"problem": paper_problem(collisions=True),
+            "disc": {"nc": (n, n, n), "np": 1 << 23, "dt": T_PAPER / n, "steps": n, "navg": 16,
+                     "cg_tol": 1e-12, "cg_max_iter": 20000},
+            "precision": precision, "seed": 1}
+
+
+CONFIGS["cfg2_paper"] = _paper_64("fp64")
+CONFIGS["cfg3_paper"] = _paper_64("mixed")
 
 
 def ensemble_levels(n_levels=5):
