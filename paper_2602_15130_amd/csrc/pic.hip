@@ -90,7 +90,7 @@ Layout make_layout(const pic_discretization* d, int precision) {
   b[A_CNT] = kCntCount * 8;
   b[A_CGIT] = 4;
   b[A_CGRR] = 8;
-  b[A_DEFER] = ((np + kTileB - 1) / kTileB + 2) * 4;  // tiles the lean pass leaves to the general one
+  b[A_DEFER] = ((np + kTileB - 1) / kTileB + 1) * 4;  // tiles the lean pass leaves to the general one
   b[A_STEPC] = 8;                   // completed steps, for captured steps
   b[A_MIXC] = sizeof(MixConst);     // the mixed pass's constants of a captured step
   int64_t t = 0;
@@ -703,6 +703,7 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
     }
     const int s = c->cur;
     if (lean) {
+      TRY(fill(c, c->defer, 0, 1));  // an empty deferral list
       fm[2]<<<G(c, tiles), dim3(kTileThreads), 0, c->stream>>>(K, M, a, c->off[s], c->vf[s],
                                                               c->asf[s], c->E32);
       LAUNCH_CHECK(c, "particles (mixed, lean)");
@@ -713,6 +714,7 @@ int launch_particles(pic_ctx* c, const PartArgs& a) {
     return PIC_OK;
   }
   if (lean) {
+    TRY(fill(c, c->defer, 0, 1));  // an empty deferral list
     fns.f64[2]<<<G(c, tiles), kTileThreads, 0, c->stream>>>(K, a);
     LAUNCH_CHECK(c, "particles (lean)");
   }
@@ -1241,7 +1243,7 @@ int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* dis
   auto init = [&]() -> int {
     const SimConst& K = c->K;
     TRY(fill<int>(c, c->flags, 0, kFlagCount));
-    TRY(fill<int>(c, c->defer, 0, 2));
+    TRY(fill<int>(c, c->defer, 0, 1));
     TRY(fill<unsigned long long>(c, c->cnt, 0ull, kCntCount));
     c->count_zero = false;
     TRY(zero_counts(c));

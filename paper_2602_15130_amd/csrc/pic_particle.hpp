@@ -116,37 +116,28 @@ __device__ inline PartArgs member_view(const SimConst& K, PartArgs a) {
 }
 
 // Hands tile b to the general instance (thread 0; the caller returns uniformly).
+// The list is a count, dl[0], and the tiles from dl[1] on; the host clears the
+// count before every lean launch.
 __device__ inline void defer_tile(const PartArgs& a, int b) {
   if (threadIdx.x == 0) {
     const int i = atomicAdd(&a.defer[0], 1);
-    if (i < a.ntiles) a.defer[2 + i] = b;
+    if (i < a.ntiles) a.defer[1 + i] = b;
   }
 }
 
 // The tiles of one launch: the lean instance (FAST) and a plain general launch
 // take tile blockIdx.x; the general instance after a lean one takes the
-// deferred tiles, workgroup-strided, and its last workgroup (per member)
-// empties the list for the next pass.
+// deferred tiles, workgroup-strided.  (Its workgroups only read the list: a
+// last-workgroup reset, one same-address atomic per workgroup, cost more than
+// the whole general launch when nothing was deferred.)
 template <bool FAST, class F>
 __device__ __attribute__((always_inline)) inline void tile_sweep(const PartArgs& a, F&& tile) {
   const bool list = !FAST && a.defer_list;
-  int* dl = a.defer;
-  const int n = list ? min(__hip_atomic_load(&dl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                           a.ntiles)
-                     : (int)blockIdx.x + 1;
+  const int* dl = a.defer;
+  const int n = list ? min(dl[0], a.ntiles) : (int)blockIdx.x + 1;
   for (int i = blockIdx.x; i < n; i += list ? (int)gridDim.x : 1) {
-    tile(list ? dl[2 + i] : i);
+    tile(list ? dl[1 + i] : i);
     if (list) __syncthreads();
-  }
-  if (list) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      if (atomicAdd((unsigned*)&dl[1], 1u) == gridDim.x - 1) {
-        dl[0] = 0;
-        dl[1] = 0;
-      }
-    }
   }
 }
 
