@@ -43,6 +43,9 @@ struct CollideLds {
   int evck[NL][CAP];  // tile-local cell of the event << 16 | its outcome
   int evn[NL][CAP];   // its N_pairs
   int evp[CAP];      // records of the list being run
+  // FP64 passes: the list being run sorted by (cell, outcome), keys and event indices
+  static constexpr int kSorted = sizeof(R) == 8 ? CAP : 1;
+  int skey[kSorted], eord[kSorted];
   int n_evt[NL], overflow[NL], pool_n;
   int need[NL], big[NL];  // pool records the list's outcomes need; an outcome over kSmallPairs
   int pslot[kPool];
@@ -356,15 +359,20 @@ template <int SIG, class R, bool FULL, bool LANE_ONLY, class Lds>
 __device__ __attribute__((always_inline)) inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
                                      int c, int ci, int cs, int n, const R* v0, R* u, R* D,
                                      int* mark, int* tl, int tagbase, int st, int stu,
-                                     const Lds& L, int li, int ne, bool all,
+                                     const Lds& L, int li, int ne, int first, bool all,
                                      unsigned long long& acc, unsigned long long& gmx) {
   const int navg = K.navg;
-  int last = -1;
+  int last = -1, idx = first;
   bool marks_clear = false;  // this cell's marks are reset before its first own outcome
   for (int it = 0; it < navg; ++it) {
     int k, ev = -1;
     if (all) {
       k = it;
+    } else if constexpr (sizeof(R) == 8) {  // next event in the sorted list
+      if (idx >= ne || (L.skey[idx] >> 16) != ci) break;
+      k = L.skey[idx] & 0xffff;
+      ev = L.eord[idx];
+      ++idx;
     } else {  // next event of this cell in increasing outcome order
       k = navg;
       for (int e = 0; e < ne; ++e) {
@@ -505,6 +513,20 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
   unsigned long long acc = 0, gmx = 0;
   // small outcomes, one per lane, into the record pool
   if (!all) {
+    if constexpr (sizeof(R) == 8) {
+      // The FP64 pass sorts the list by (cell, outcome) keys, which are
+      // distinct: each event's rank, on the waves after the first (idle while
+      // the first wave's lanes run the outcomes), so that the cell threads
+      // below find their events by binary search.
+      if (tid >= 64)
+        for (int e = tid - 64; e < ne; e += kTileThreads - 64) {
+          const int key = L.evck[li][e];
+          int rank = 0;
+          for (int f = 0; f < ne; ++f) rank += L.evck[li][f] < key ? 1 : 0;
+          L.skey[rank] = key;
+          L.eord[rank] = e;
+        }
+    }
     for (int e = tid; e < ne; e += kTileThreads) {
       int np_ = L.evn[li][e];
       int start = -1;
@@ -531,14 +553,19 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
     int c = c0 + ci;
     int cs = cell_start(ci) - s0, n = cell_start(ci + 1) - cell_start(ci);
     if (n < 2) continue;
+    int first = 0;  // (FP64) the cell's first event in key order
     if (!all) {  // skip cells without events quickly
-      bool any = false;
-      for (int e = 0; e < ne; ++e) any |= (L.evck[li][e] >> 16) == ci;
-      if (!any) continue;
+      if constexpr (sizeof(R) == 8) {
+        first = lower_bound_i(L.skey, ne, ci << 16);
+        if (first >= ne || (L.skey[first] >> 16) != ci) continue;
+      } else {
+        bool any = false;
+        for (int e = 0; e < ne; ++e) any |= (L.evck[li][e] >> 16) == ci;
+        if (!any) continue;
+      }
     }
     cell_outcomes<SIG, R, FULL, LANE_ONLY>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase,
-                                           st, stu, L,
-                          li, ne, all, acc, gmx);
+                                           st, stu, L, li, ne, first, all, acc, gmx);
   }
   if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
   if (gmx) atomicAdd(&a.counters[kCntGmax], gmx);
