@@ -257,7 +257,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other workloads' records (cfg1, 128^3, paper family at 64^3)")
+                    help="skip the other workloads' records (cfg1, cfg3 without collisions, 128^3, paper family at 64^3)")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the refinement-ensemble (cfg4) block of the default line")
     ap.add_argument("--levels", default="1,2,3", help="Table 1 levels for --workload table1")
@@ -304,10 +304,11 @@ def main():
         out["convergence"]["paper_ladder"] = paper_ladder_report(pic, W)
     if not args.no_extra:
         # the other single-GPU workloads, each as a compact record (20 timed
-        # steps): the 32^3 two-way collisionless FP64 case, the 128^3
-        # single-simulation point and the paper's own functions at 64^3
+        # steps): the 32^3 two-way collisionless FP64 case, the headline
+        # case without collisions, the 128^3 single-simulation point and the
+        # paper's own functions at 64^3
         out["more_workloads"] = {}
-        for w in ("cfg1", "cfg3_128", "cfg3_paper", "cfg2_paper"):
+        for w in ("cfg1", "cfg3_collisionless", "cfg3_128", "cfg3_paper", "cfg2_paper"):
             progress(f"timing {w}")
             r = run_workload(pic, W, torch, w, min(args.steps, 20), 2)
             out["more_workloads"][w] = {

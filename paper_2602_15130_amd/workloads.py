@@ -113,6 +113,11 @@ CONFIGS = {
     # Mixed-precision form of cfg2.
     "cfg3": {"problem": cfg_problem(two_way=True, collisions=True),
              "disc": cfg_disc(64, 1 << 23, 2.5e-4, 100, 16), "precision": "mixed", "seed": 1},
+    # cfg3 without collisions (the collisionless case of the paper's studies):
+    # what the particle pass costs without its two collision calls.
+    "cfg3_collisionless": {"problem": cfg_problem(two_way=True, collisions=False),
+                           "disc": cfg_disc(64, 1 << 23, 2.5e-4, 100, 16), "precision": "mixed",
+                           "seed": 1},
     # The single-simulation point at 128^3: 67,108,864 particles (32 per cell),
     # the cfg3 physics with dt halved.
     "cfg3_128": {"problem": cfg_problem(two_way=True, collisions=True),
