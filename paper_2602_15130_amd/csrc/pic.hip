@@ -676,8 +676,23 @@ constexpr int kDeferGrid = 2048;
 // Fused pass: the lean instance over all tiles, then the general one over the
 // tiles it deferred; or the general (or full) instance alone, for logged runs,
 // collide-only calls and collision loads where most tiles would be deferred.
-int launch_particles(pic_ctx* c, const PartArgs& a) {
+int launch_particles(pic_ctx* c, const PartArgs& a0) {
   const SimConst& K = c->K;
+  PartArgs a = a0;
+  if (K.family == 0 && (a.mode & kDoA) && !(a.mode & kCollideOnly)) {
+    // the paper family's manufactured drift term, into the idle half of the
+    // double-buffered state (the next sort writes it again)
+    const int o = 1 - c->cur;
+    if (c->precision == PIC_MIXED) {
+      a.mdrift32 = c->off[o];
+      k_paper_drift_mixed<<<G(c, grid_for(K.np)), kBlock, 0, c->stream>>>(K, a, c->off[c->cur],
+                                                                         c->off[o]);
+    } else {
+      a.mdrift = c->x[o];
+      k_paper_drift_f64<<<G(c, grid_for(K.np)), kBlock, 0, c->stream>>>(K, a, c->x[o]);
+    }
+    LAUNCH_CHECK(c, "paper drift term");
+  }
   const int tiles = (int)((K.np + kTileB - 1) / kTileB);
   const PassFns fns = select_pass(K);
   // the collision-angle and pair-log recording and the anisotropic polar-angle

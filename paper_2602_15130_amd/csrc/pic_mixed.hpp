@@ -358,7 +358,7 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 // DEVC: the instances of captured steps, which take the pass's constants
 // from the device (written by k_step_consts) instead of the argument.
 template <int FAM, int SIG, bool FULL, bool FAST, bool DEVC = false>
-__global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : (FAST ? PIC_MIXED_LEAN_WAVES : PIC_MIXED_WAVES)) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
+__global__ void __launch_bounds__(kTileThreads, FAST ? PIC_MIXED_LEAN_WAVES : PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
   a = member_view(K, a);
@@ -555,29 +555,11 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : (FAST ? PIC_MIXED
         int c = tk[j];
         int cc[3];
         node_coords(K, c, cc[0], cc[1], cc[2]);
-        // Paper family: the manufactured term of the drift from FP64 root solves
-        // of x^M (eq. mms_sol) started at the particle's own position: dt xdot^M
-        // at t^{n+1/2}, or x^M(t^{n+1}) - x^M(t^n) in isolation mode, in cells.
+        // Paper family: the manufactured term of the drift, in cells, from
+        // k_paper_drift_mixed
         float dman[3] = {0.0f, 0.0f, 0.0f};
-        if constexpr (FAM == 0) {
-          double xq[3], xg[3], disp[3];
-          position_uniforms(K, a.id[p], xq);
-          for (int d = 0; d < 3; ++d) xg[d] = ((double)cc[d] + (double)to[d * st + j]) * K.h[d];
-          const double t0 = (double)a.na * K.dt, th = ((double)a.na + 0.5) * K.dt,
-                       t1 = ((double)a.na + 1.0) * K.dt;
-          if (K.isolate) {
-            double xa[3], xb[3];
-            manufactured_position(K, xq, t0, xg, xa);
-            manufactured_position(K, xq, t1, xa, xb);
-            for (int d = 0; d < 3; ++d) disp[d] = xb[d] - xa[d];
-          } else {
-            double xm[3], xd[3];
-            manufactured_position(K, xq, th, xg, xm);
-            manufactured_xdot(K, xm, th, xd);
-            for (int d = 0; d < 3; ++d) disp[d] = K.dt * xd[d];
-          }
-          for (int d = 0; d < 3; ++d) dman[d] = (float)(disp[d] * K.inv_h[d]);
-        }
+        if constexpr (FAM == 0)
+          for (int d = 0; d < 3; ++d) dman[d] = a.mdrift32[(int64_t)d * NP + p];
         float on[3];
         for (int d = 0; d < 3; ++d) {
           // x += dt (v - v^M) in cell units, v^M = vhat(t^{n+1/2}) a, plus the
@@ -618,6 +600,47 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 4 : (FAST ? PIC_MIXED
     }
   };
   tile_sweep<FAST>(a, tile);
+}
+
+// Paper family: the manufactured term of every particle's drift in step na,
+// in cells (FP32), from FP64 root solves of x^M (eq. mms_sol) started at the
+// particle's position at the start of the pass: dt xdot^M at t^{na+1/2}, or
+// x^M(t^{na+1}) - x^M(t^{na}) in isolation mode.  It depends only on the
+// particle's identity, that position and the time, so it runs before the pass
+// (which then keeps no root solver and its register budget); out is the idle
+// half of the double-buffered offsets.
+__global__ void __launch_bounds__(kBlock) k_paper_drift_mixed(SimConst K, PartArgs a, const float* off,
+                                                              float* out) {
+  a = member_view(K, a);
+  off = mem(K, off);
+  out = mem(K, out);
+  if (a.step_dev) {  // a captured step: its step index from the device
+    a.nb = *K.stepc;
+    a.na = a.nb + 1;
+  }
+  const int64_t NP = K.np;
+  const double t0 = (double)a.na * K.dt, th = ((double)a.na + 0.5) * K.dt,
+               t1 = ((double)a.na + 1.0) * K.dt;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < NP;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    int cc[3];
+    node_coords(K, a.key[p], cc[0], cc[1], cc[2]);
+    double xq[3], xg[3], disp[3];
+    position_uniforms(K, a.id[p], xq);
+    for (int d = 0; d < 3; ++d) xg[d] = ((double)cc[d] + (double)off[d * NP + p]) * K.h[d];
+    if (K.isolate) {
+      double xa[3], xb[3];
+      manufactured_position(K, xq, t0, xg, xa);
+      manufactured_position(K, xq, t1, xa, xb);
+      for (int d = 0; d < 3; ++d) disp[d] = xb[d] - xa[d];
+    } else {
+      double xm[3], xd[3];
+      manufactured_position(K, xq, th, xg, xm);
+      manufactured_xdot(K, xm, th, xd);
+      for (int d = 0; d < 3; ++d) disp[d] = K.dt * xd[d];
+    }
+    for (int d = 0; d < 3; ++d) out[d * NP + p] = (float)(disp[d] * K.inv_h[d]);
+  }
 }
 
 // Positions and velocities exported as FP64 (component-major).

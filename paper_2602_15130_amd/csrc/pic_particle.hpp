@@ -86,6 +86,11 @@ struct PartArgs {
   // constants from mixc, written by k_step_consts before every pass
   int step_dev;
   const struct MixConst* mixc;
+  // paper family: the manufactured displacement of each particle's drift,
+  // [3][np], computed before the pass (k_paper_drift_*; FP64 in position
+  // units, mixed in cells)
+  const double* mdrift;
+  const float* mdrift32;
   int mode;
   int64_t nb, na;       // step index of call B (second half) and of call A (first half)
   int callB, callA;     // random-stream call tags (collide-only mode uses callA)
@@ -115,6 +120,8 @@ __device__ inline PartArgs member_view(const SimConst& K, PartArgs a) {
   a.counters = mem(K, a.counters);
   a.flags = mem(K, a.flags);
   a.defer = mem(K, a.defer);
+  a.mdrift = mem(K, a.mdrift);
+  a.mdrift32 = mem(K, a.mdrift32);
   return a;
 }
 
@@ -763,13 +770,48 @@ __device__ inline void field_acc_f64(const SimConst& K, const double xp[3], cons
   for (int d = 0; d < 3; ++d) acc[d] = K.dt * K.qm * (ep[d] - em[d]);
 }
 
+// Paper family, FP64 form: the manufactured term of every particle's drift in
+// step na (position units), from FP64 root solves of x^M (eq. mms_sol) started
+// at the uniform guess: dt xdot^M at t^{na+1/2}, or x^M(t^{na+1}) - x^M(t^{na})
+// in isolation mode.  It depends only on the particle's identity and the time,
+// so it runs before the pass (which then keeps no root solver); out is the
+// idle half of the double-buffered positions.
+__global__ void __launch_bounds__(kBlock) k_paper_drift_f64(SimConst K, PartArgs a, double* out) {
+  a = member_view(K, a);
+  out = mem(K, out);
+  if (a.step_dev) {  // a captured step: its step index from the device
+    a.nb = *K.stepc;
+    a.na = a.nb + 1;
+  }
+  const int64_t NP = K.np;
+  const double dt = K.dt;
+  const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < NP;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    double xq[3], h[3];
+    position_uniforms(K, a.id[p], xq);
+    if (K.isolate) {
+      double xa[3], xb[3];
+      manufactured_position(K, xq, t0, nullptr, xa);
+      manufactured_position(K, xq, t1, nullptr, xb);
+      for (int d = 0; d < 3; ++d) h[d] = xb[d] - xa[d];
+    } else {
+      double xm[3], xd[3];
+      manufactured_position(K, xq, th, nullptr, xm);
+      manufactured_xdot(K, xm, th, xd);
+      for (int d = 0; d < 3; ++d) h[d] = dt * xd[d];
+    }
+    for (int d = 0; d < 3; ++d) out[d * NP + p] = h[d];
+  }
+}
+
 // Registers are capped for four resident waves per SIMD (128 VGPRs), accepting
 // a few spills: the pass is latency bound and gains more from resident waves
 // than it loses to spill traffic.  The paper family's instances (FP64 root
 // solves of the manufactured positions in the drift and its source terms) need
 // about twice the registers and get two waves per SIMD (256 VGPRs).
 template <int FAM, int SIG, bool FULL, bool FAST>
-__global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : (FAST ? PIC_F64_LEAN_WAVES : PIC_F64_WAVES))
+__global__ void __launch_bounds__(kTileThreads, FAST ? PIC_F64_LEAN_WAVES : PIC_F64_WAVES)
     k_particles_f64(SimConst K, PartArgs a) {
   a = member_view(K, a);
   if (a.step_dev) {  // a captured step: its step index from the device
@@ -941,22 +983,8 @@ __global__ void __launch_bounds__(kTileThreads, FAM == 0 ? 2 : (FAST ? PIC_F64_L
         } else {
           manufactured_velocity(K, aa, th, vm, vdm);
         }
-        if (FAM == 0) {
-          int pid = a.id[p];
-          double xq[3];
-          position_uniforms(K, pid, xq);
-          if (K.isolate) {
-            double xa[3], xb[3];
-            manufactured_position(K, xq, t0, nullptr, xa);
-            manufactured_position(K, xq, t1, nullptr, xb);
-            for (int d = 0; d < 3; ++d) h[d] = xb[d] - xa[d];
-          } else {
-            double xm[3], xd[3];
-            manufactured_position(K, xq, th, nullptr, xm);
-            manufactured_xdot(K, xm, th, xd);
-            for (int d = 0; d < 3; ++d) h[d] = dt * xd[d];
-          }
-        }
+        if (FAM == 0)  // the manufactured displacement, from k_paper_drift_f64
+          for (int d = 0; d < 3; ++d) h[d] = a.mdrift[(int64_t)d * NP + p];
         for (int d = 0; d < 3; ++d) {
           double xn = xp[d] + dt * (vp[d] - vm[d]) + h[d];
           if (xn < 0.0) xn += K.L[d];

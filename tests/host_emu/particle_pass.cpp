@@ -159,6 +159,23 @@ int main(int argc, char** argv) {
 
   const MixConst M = mix_const(K, a);
   std::mt19937_64 rng(h.rng_seed);
+  // paper family: the drift's manufactured term, computed before the pass as
+  // the library does (into a buffer of its own here)
+  std::vector<double> mdrift;
+  std::vector<float> mdrift32;
+  if (K.family == 0 && (a.mode & kDoA) && !(a.mode & kCollideOnly) && h.mode != 2 && h.mode < 5) {
+    const unsigned gp = (unsigned)((np + kBlock - 1) / kBlock);
+    if (h.precision == 0) {
+      mdrift.assign(3 * np, 0.0);
+      a.mdrift = mdrift.data();
+      emu::run_grid(gp, kBlock, [&] { k_paper_drift_f64(K, a, mdrift.data()); }, h.order, rng);
+    } else {
+      mdrift32.assign(3 * np, 0.0f);
+      a.mdrift32 = mdrift32.data();
+      emu::run_grid(gp, kBlock, [&] { k_paper_drift_mixed(K, a, off.data(), mdrift32.data()); },
+                    h.order, rng);
+    }
+  }
   const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
   // full: 1 the full instance alone; 0 the lean instance, then the general
   // one over the tiles it deferred (the library's default); 2 the general
