@@ -349,12 +349,10 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 }
 
 // The mixed-form fused pass, same phases as the FP64 one.  FAM: 0 the paper's
-// manufactured family (time-dependent velocity distribution, manufactured
-// positions by FP64 root solves in every drift), 1 the configuration family.
-// Registers are capped for six waves per SIMD (measured best at 64^3: the pass
-// is latency bound, and the extra resident waves outweigh the spills); the
-// paper family's instances (FP64 root solves in the drift and the source) get
-// four (128 VGPRs).
+// manufactured family (time-dependent velocity distribution; the drift's
+// manufactured term comes from k_paper_drift_mixed), 1 the configuration
+// family.  Registers are capped for six waves per SIMD (measured best at 64^3:
+// the pass is latency bound, and the extra resident waves outweigh the spills).
 // DEVC: the instances of captured steps, which take the pass's constants
 // from the device (written by k_step_consts) instead of the argument.
 template <int FAM, int SIG, bool FULL, bool FAST, bool DEVC = false>

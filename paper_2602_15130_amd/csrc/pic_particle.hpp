@@ -807,9 +807,8 @@ __global__ void __launch_bounds__(kBlock) k_paper_drift_f64(SimConst K, PartArgs
 
 // Registers are capped for four resident waves per SIMD (128 VGPRs), accepting
 // a few spills: the pass is latency bound and gains more from resident waves
-// than it loses to spill traffic.  The paper family's instances (FP64 root
-// solves of the manufactured positions in the drift and its source terms) need
-// about twice the registers and get two waves per SIMD (256 VGPRs).
+// than it loses to spill traffic.  The paper family's instances take the same
+// cap: their drift term's root solves run before the pass (k_paper_drift_f64).
 template <int FAM, int SIG, bool FULL, bool FAST>
 __global__ void __launch_bounds__(kTileThreads, FAST ? PIC_F64_LEAN_WAVES : PIC_F64_WAVES)
     k_particles_f64(SimConst K, PartArgs a) {
