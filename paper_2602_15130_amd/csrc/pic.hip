@@ -1066,10 +1066,10 @@ int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* dis
     // The lean pass runs a tile's outcomes on lanes only, which needs at most
     // kSmallPairs pairs per outcome and kPool records per call; expected pool
     // use per call of a tile is 2 N_pairs-mean N_avg (cells per tile).  Above
-    // half the pool most tiles would be deferred, so the general instance runs
+    // the pool most tiles would be deferred, so the general instance runs
     // alone.  PIC_LEAN_PASS=0/1 overrides.
     const double need = 2.0 * pairs * (double)c->K.navg * ((double)kTileB / std::max(nbar, 1.0));
-    c->lean_pass = !c->K.collisions || need <= 0.5 * kPool;
+    c->lean_pass = !c->K.collisions || need <= kPool;
     if (const char* lp = std::getenv("PIC_LEAN_PASS")) c->lean_pass = lp[0] == '1';
   }
   c->cg_tol = disc->cg_tol;

@@ -27,7 +27,7 @@
 namespace pic {
 
 constexpr int kSmallPairs = 4;    // outcomes with at most this many pairs run one per lane
-constexpr int kPool = 64;         // velocity-change records of those outcomes per tile
+constexpr int kPool = 128;        // velocity-change records of those outcomes per tile
 constexpr int kCellCache = 64;    // cells of a tile whose starts the mixed pass keeps in LDS
 
 // LDS of one collision call over a tile: the events ((cell, outcome) lanes

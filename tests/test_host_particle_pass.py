@@ -205,7 +205,7 @@ def test_lean_pass_with_deferred_tiles_equals_general_pass(harness, precision):
     pool, tiles larger than their LDS slots) to the general instance, which
     works through the list on fewer workgroups; the result equals the general
     instance's alone bit for bit, in every thread and workgroup order."""
-    prob = W.cfg_problem(two_way=True, collisionality=2.0)
+    prob = W.cfg_problem(two_way=True, collisionality=4.0)
     for nc, npart in ((8, 16384), (3, 19000)):
         disc = W.cfg_disc(nc, npart, 1e-3, 1, 8)
         ref, _ = _run(harness, "product", prob, disc, 5, 1, FORWARD, steps_before=1, full=2,
