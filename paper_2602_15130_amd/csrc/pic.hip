@@ -251,6 +251,7 @@ struct pic_ctx {
   float* Df{};
   bool fused = true;
   bool lean_pass = true;        // lean pass instance first, general one for the tiles it defers
+  bool sort_events = false;     // mixed pass instances that sort long event lists
   // Captured steps (pic_use_graphs): two steps per graph, one graph per
   // double-buffer parity, recorded on a private stream and replayed on the
   // context's stream; kernels then take the step from *stepc.
@@ -650,24 +651,29 @@ struct PassFns {
   MixedFn mixed_dev[3];  // (none), general, fast of captured steps
   F64Fn f64[3];
 };
-template <int FAM, int SIG>
+template <int FAM, int SIG, bool S>
 PassFns pass_fns() {
-  return {{k_particles_mixed<FAM, SIG, true, false>, k_particles_mixed<FAM, SIG, false, false>,
-           k_particles_mixed<FAM, SIG, false, true>},
-          {nullptr, k_particles_mixed<FAM, SIG, false, false, true>,
-           k_particles_mixed<FAM, SIG, false, true, true>},
+  return {{k_particles_mixed<FAM, SIG, true, false>, k_particles_mixed<FAM, SIG, false, false, false, S>,
+           k_particles_mixed<FAM, SIG, false, true, false, S>},
+          {nullptr, k_particles_mixed<FAM, SIG, false, false, true, S>,
+           k_particles_mixed<FAM, SIG, false, true, true, S>},
           {k_particles_f64<FAM, SIG, true, false>, k_particles_f64<FAM, SIG, false, false>,
            k_particles_f64<FAM, SIG, false, true>}};
 }
-PassFns select_pass(const SimConst& K) {
+template <int FAM, int SIG>
+PassFns pass_fns(bool sort) {
+  return sort ? pass_fns<FAM, SIG, true>() : pass_fns<FAM, SIG, false>();
+}
+// sort: the mixed instances that sort long event lists (sort_events)
+PassFns select_pass(const SimConst& K, bool sort) {
   const int sig = K.sigma_model == 0 ? kSigPoly : (K.omega == 1.0 ? kSigMaxwell : kSigHS);
   if (K.family == 1) {
-    if (sig == kSigHS) return pass_fns<1, kSigHS>();
-    if (sig == kSigMaxwell) return pass_fns<1, kSigMaxwell>();
-    return pass_fns<1, kSigPoly>();
+    if (sig == kSigHS) return pass_fns<1, kSigHS>(sort);
+    if (sig == kSigMaxwell) return pass_fns<1, kSigMaxwell>(sort);
+    return pass_fns<1, kSigPoly>(sort);
   }
-  if (sig == kSigMaxwell) return pass_fns<0, kSigMaxwell>();
-  return pass_fns<0, kSigPoly>();
+  if (sig == kSigMaxwell) return pass_fns<0, kSigMaxwell>(sort);
+  return pass_fns<0, kSigPoly>(sort);
 }
 
 // Workgroups of the general instance that works through the deferred tiles.
@@ -694,7 +700,7 @@ int launch_particles(pic_ctx* c, const PartArgs& a0) {
     LAUNCH_CHECK(c, "paper drift term");
   }
   const int tiles = (int)((K.np + kTileB - 1) / kTileB);
-  const PassFns fns = select_pass(K);
+  const PassFns fns = select_pass(K, c->sort_events);
   // the collision-angle and pair-log recording and the anisotropic polar-angle
   // samplers are compiled only into the full instances
   const bool full = K.anglog != nullptr || a.pairlog != nullptr || K.chi_model != PIC_CHI_ISO ||
@@ -1071,6 +1077,13 @@ int create(pic_ctx** out, const pic_problem* prob, const pic_discretization* dis
     const double need = 2.0 * pairs * (double)c->K.navg * ((double)kTileB / std::max(nbar, 1.0));
     c->lean_pass = !c->K.collisions || need <= kPool;
     if (const char* lp = std::getenv("PIC_LEAN_PASS")) c->lean_pass = lp[0] == '1';
+    // Events per call of a tile, N_avg (cells per tile) P(N_pairs > 0): the
+    // mixed pass sorts its lists for the cell threads where they are long
+    // (the FP64 pass always does).  PIC_SORT_EVENTS=0/1 overrides.
+    const double events = (double)c->K.navg * ((double)kTileB / std::max(nbar, 1.0)) *
+                          (1.0 - std::exp(-pairs));
+    c->sort_events = c->K.collisions && events > 16.0;
+    if (const char* se = std::getenv("PIC_SORT_EVENTS")) c->sort_events = se[0] == '1';
   }
   c->cg_tol = disc->cg_tol;
   c->cg_max_iter = disc->cg_max_iter;

@@ -354,8 +354,9 @@ __device__ inline void EM_mixed(const MixConst& M, int ci, int cj, int ck, const
 // family.  Registers are capped for six waves per SIMD (measured best at 64^3:
 // the pass is latency bound, and the extra resident waves outweigh the spills).
 // DEVC: the instances of captured steps, which take the pass's constants
-// from the device (written by k_step_consts) instead of the argument.
-template <int FAM, int SIG, bool FULL, bool FAST, bool DEVC = false>
+// from the device (written by k_step_consts) instead of the argument.  SORT:
+// long event lists are sorted for the cell threads (sorted_list).
+template <int FAM, int SIG, bool FULL, bool FAST, bool DEVC = false, bool SORT = true>
 __global__ void __launch_bounds__(kTileThreads, FAST ? PIC_MIXED_LEAN_WAVES : PIC_MIXED_WAVES) k_particles_mixed(SimConst K, MixConst M, PartArgs a,
                                                             float* off, float* vf, const float* ash,
                                                             const float* E32) {
@@ -507,7 +508,7 @@ __global__ void __launch_bounds__(kTileThreads, FAST ? PIC_MIXED_LEAN_WAVES : PI
 
     if (a.mode & kDoB) {  // call B at t^{nb+1/2}, second half kick at t^{nb+1}
       if (K.collisions)
-        tile_run<SIG, float, FULL, FAST>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+        tile_run<SIG, float, FULL, FAST, SORT>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                  NP, cl, few_cells ? lcs : nullptr);
       for (int j = tid; j < ns; j += kTileThreads) {
         float acc[3], sa[3] = {0.0f, 0.0f, 0.0f};
@@ -533,7 +534,7 @@ __global__ void __launch_bounds__(kTileThreads, FAST ? PIC_MIXED_LEAN_WAVES : PI
 
     // call A at t^{na}, first half kick, drift to t^{na+1}
     if (K.collisions)
-      tile_run<SIG, float, FULL, FAST>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+      tile_run<SIG, float, FULL, FAST, SORT>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
                                st, NP, cl, few_cells ? lcs : nullptr);
     for (int base = 0; base < ns; base += kTileThreads) {
       int j = base + tid;

@@ -43,9 +43,9 @@ struct CollideLds {
   int evck[NL][CAP];  // tile-local cell of the event << 16 | its outcome
   int evn[NL][CAP];   // its N_pairs
   int evp[CAP];      // records of the list being run
-  // FP64 passes: the list being run sorted by (cell, outcome), keys and event indices
-  static constexpr int kSorted = sizeof(R) == 8 ? CAP : 1;
-  int skey[kSorted], eord[kSorted];
+  // the list being run sorted by (cell, outcome) when it is (sorted_list):
+  // keys and event indices
+  int skey[CAP], eord[CAP];
   int n_evt[NL], overflow[NL], pool_n;
   int need[NL], big[NL];  // pool records the list's outcomes need; an outcome over kSmallPairs
   int pslot[kPool];
@@ -362,7 +362,16 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
 // is read).  Outcomes already run by a lane contribute their stored changes;
 // the others run here.  Only the particles an outcome changed contribute to
 // the sum; the others would add exact zeros.
-template <int SIG, class R, bool FULL, bool LANE_ONLY, class Lds>
+// Whether a call's event list is sorted for the cell threads: always in the
+// FP64 pass; in the mixed pass (SORT instances, launched where a tile's lists
+// are expected to be long) from kSortEvents events on.  With few events the
+// mixed pass is faster with the plain scan, and faster still in instances
+// compiled without the sort at all.
+constexpr int kSortEvents = 24;
+template <class R, bool SORT>
+__device__ inline bool sorted_list(int ne) { return sizeof(R) == 8 || (SORT && ne > kSortEvents); }
+
+template <int SIG, class R, bool FULL, bool LANE_ONLY, bool SORT, class Lds>
 __device__ __attribute__((always_inline)) inline void cell_outcomes(const SimConst& K, const PartArgs& a, int call, int64_t step,
                                      int c, int ci, int cs, int n, const R* v0, R* u, R* D,
                                      int* mark, int* tl, int tagbase, int st, int stu,
@@ -375,7 +384,7 @@ __device__ __attribute__((always_inline)) inline void cell_outcomes(const SimCon
     int k, ev = -1;
     if (all) {
       k = it;
-    } else if constexpr (sizeof(R) == 8) {  // next event in the sorted list
+    } else if (sorted_list<R, SORT>(ne)) {  // next event in the sorted list
       if (idx >= ne || (L.skey[idx] >> 16) != ci) break;
       k = L.skey[idx] & 0xffff;
       ev = L.eord[idx];
@@ -506,7 +515,7 @@ __device__ inline void tile_draw(const SimConst& K, const PartArgs& a, int lo, i
 // caller has zeroed D[0, ns) and the record pool count before a barrier (each
 // block-wide barrier costs the whole tile its slowest wave, so none is spent
 // on that here).
-template <int SIG, class R, bool FULL, bool LANE_ONLY, class Lds>
+template <int SIG, class R, bool FULL, bool LANE_ONLY, bool SORT, class Lds>
 __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K, const PartArgs& a, int li, int call,
                                 int64_t step, int c0, int ncells, int s0, int ns, const R* v0,
                                 R* u, R* D, int* mark, int* tl, int tagbase, int st, int stu,
@@ -520,11 +529,11 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
   unsigned long long acc = 0, gmx = 0;
   // small outcomes, one per lane, into the record pool
   if (!all) {
-    if constexpr (sizeof(R) == 8) {
-      // The FP64 pass sorts the list by (cell, outcome) keys, which are
-      // distinct: each event's rank, on the waves after the first (idle while
-      // the first wave's lanes run the outcomes), so that the cell threads
-      // below find their events by binary search.
+    if (sorted_list<R, SORT>(ne)) {
+      // The list sorted by (cell, outcome) keys, which are distinct: each
+      // event's rank, on the waves after the first (idle while the first
+      // wave's lanes run the outcomes), so that the cell threads below find
+      // their events by binary search.
       if (tid >= 64)
         for (int e = tid - 64; e < ne; e += kTileThreads - 64) {
           const int key = L.evck[li][e];
@@ -560,9 +569,9 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
     int c = c0 + ci;
     int cs = cell_start(ci) - s0, n = cell_start(ci + 1) - cell_start(ci);
     if (n < 2) continue;
-    int first = 0;  // (FP64) the cell's first event in key order
+    int first = 0;  // (sorted list) the cell's first event in key order
     if (!all) {  // skip cells without events quickly
-      if constexpr (sizeof(R) == 8) {
+      if (sorted_list<R, SORT>(ne)) {
         first = lower_bound_i(L.skey, ne, ci << 16);
         if (first >= ne || (L.skey[first] >> 16) != ci) continue;
       } else {
@@ -571,7 +580,7 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
         if (!any) continue;
       }
     }
-    cell_outcomes<SIG, R, FULL, LANE_ONLY>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase,
+    cell_outcomes<SIG, R, FULL, LANE_ONLY, SORT>(K, a, call, step, c, ci, cs, n, v0, u, D, mark, tl, tagbase,
                                            st, stu, L, li, ne, first, all, acc, gmx);
   }
   if (acc) atomicAdd(&a.counters[kCntAccepted], acc);
@@ -615,7 +624,7 @@ __device__ __attribute__((always_inline)) inline void tile_collide(const SimCons
   const int64_t steps[2] = {step, step};
   tile_draw(K, a, 0, 1, calls, steps, c0, ncells, L);
   __syncthreads();
-  tile_run<SIG, R, FULL, false>(K, a, 0, call, step, c0, ncells, s0, ns, v0, u, D, mark, tl, tagbase, st,
+  tile_run<SIG, R, FULL, false, true>(K, a, 0, call, step, c0, ncells, s0, ns, v0, u, D, mark, tl, tagbase, st,
                          stu, L);
 }
 
@@ -914,7 +923,7 @@ __global__ void __launch_bounds__(kTileThreads, FAST ? PIC_F64_LEAN_WAVES : PIC_
       // collision call B at t^{nb+1/2} on v^{nb+1/2}, then the second half kick at t^{nb+1}
       const double th = ((double)a.nb + 0.5) * dt, t1 = ((double)a.nb + 1.0) * dt;
       if (K.collisions)
-        tile_run<SIG, double, FULL, FAST>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
+        tile_run<SIG, double, FULL, FAST, true>(K, a, 0, a.callB, a.nb, c0, ncells, s0, ns, v0, u, D, mark, tl, 0, st,
                                   NP, cl, few_cells ? lcs : nullptr);
       for (int j = tid; j < ns; j += kTileThreads) {
         int p = s0 + j;
@@ -951,7 +960,7 @@ __global__ void __launch_bounds__(kTileThreads, FAST ? PIC_F64_LEAN_WAVES : PIC_
     // collision call A at t^{na} on v^{na}, first half kick, drift to t^{na+1}
     const double t0 = (double)a.na * dt, th = ((double)a.na + 0.5) * dt, t1 = ((double)a.na + 1.0) * dt;
     if (K.collisions)
-      tile_run<SIG, double, FULL, FAST>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
+      tile_run<SIG, double, FULL, FAST, true>(K, a, 1, a.callA, a.na, c0, ncells, s0, ns, v0, u, D, mark, tl, K.navg,
                                 st, NP, cl, few_cells ? lcs : nullptr);
     for (int base = 0; base < ns; base += kTileThreads) {
       int j = base + tid;
