@@ -378,7 +378,9 @@ __global__ void __launch_bounds__(kTileThreads, FAST ? PIC_MIXED_LEAN_WAVES : PI
       lacc[3 * kLdsSlots];
   __shared__ int lkey[kLdsSlots];
   __shared__ int lcs[kCellCache + 1];  // cell starts of a tile of at most kCellCache cells
-  __shared__ CollideLds<float, 2, 128> cl;  // both calls of the pass drawn up front
+  // (the general instance, which takes the dense tiles, has the larger record
+  // pool; the full one keeps the small pool and its occupancy)
+  __shared__ CollideLds<float, 2, 128, (FAST || FULL) ? kPool : kPoolGeneral> cl;  // both calls drawn up front
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
   const int NP = (int)K.np;

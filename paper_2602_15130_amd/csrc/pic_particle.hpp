@@ -27,7 +27,8 @@
 namespace pic {
 
 constexpr int kSmallPairs = 4;    // outcomes with at most this many pairs run one per lane
-constexpr int kPool = 128;        // velocity-change records of those outcomes per tile
+constexpr int kPool = 128;        // velocity-change records of those outcomes per tile (lean instances)
+constexpr int kPoolGeneral = 512; // the same in the mixed general instances, which take the dense tiles
 constexpr int kCellCache = 64;    // cells of a tile whose starts the mixed pass keeps in LDS
 
 // LDS of one collision call over a tile: the events ((cell, outcome) lanes
@@ -37,9 +38,9 @@ constexpr int kCellCache = 64;    // cells of a tile whose starts the mixed pass
 // NL event lists of CAP (cell, outcome) lanes with pairs each: one list when
 // every call draws just before it runs, two when both calls of a pass draw at
 // the start of the tile (list 0 call B, list 1 call A).
-template <class R, int NL, int CAP>
+template <class R, int NL, int CAP, int POOL = kPool>
 struct CollideLds {
-  static constexpr int kLists = NL, kCap = CAP;
+  static constexpr int kLists = NL, kCap = CAP, kPoolN = POOL;
   int evck[NL][CAP];  // tile-local cell of the event << 16 | its outcome
   int evn[NL][CAP];   // its N_pairs
   int evp[CAP];      // records of the list being run
@@ -48,8 +49,8 @@ struct CollideLds {
   int skey[CAP], eord[CAP];
   int n_evt[NL], overflow[NL], pool_n;
   int need[NL], big[NL];  // pool records the list's outcomes need; an outcome over kSmallPairs
-  int pslot[kPool];
-  R pdv[3 * kPool];
+  int pslot[POOL];
+  R pdv[3 * POOL];  // [3][POOL]
 };
 
 enum { kDoB = 1, kDoA = 2, kCollideOnly = 4 };
@@ -291,7 +292,7 @@ __device__ inline int64_t npairs_of(const SimConst& K, int cell, int64_t step, i
 // records of the pool (slot in pslot, current value in pdv), everything else
 // is read from v0; at the end the records are turned into velocity changes.
 // Same arithmetic as ntc_outcome.  Returns the number of records.
-template <int SIG, class R, bool FULL>
+template <int SIG, class R, bool FULL, int PS>
 __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t step, int call, int k,
                                         int npairs, int n, const R* v0, int st, int* pslot, R* pdv,
                                         long long* pairlog, int64_t cap,
@@ -313,8 +314,8 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
     }
     R up[3], uq[3];
     for (int d = 0; d < 3; ++d) {
-      up[d] = ip >= 0 ? pdv[d * kPool + ip] : v0[d * st + p];
-      uq[d] = iq >= 0 ? pdv[d * kPool + iq] : v0[d * st + q];
+      up[d] = ip >= 0 ? pdv[d * PS + ip] : v0[d * st + p];
+      uq[d] = iq >= 0 ? pdv[d * PS + iq] : v0[d * st + q];
     }
     R dx = up[0] - uq[0], dy = up[1] - uq[1], dz = up[2] - uq[2];
     R g = sqrt(dx * dx + dy * dy + dz * dz);
@@ -339,8 +340,8 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
       R pn[3], qn[3];
       post_collision<R, FULL>(K, up, uq, g, nv, uchi, pn, qn);
       for (int d = 0; d < 3; ++d) {
-        pdv[d * kPool + ip] = pn[d];
-        pdv[d * kPool + iq] = qn[d];
+        pdv[d * PS + ip] = pn[d];
+        pdv[d * PS + iq] = qn[d];
       }
       if constexpr (FULL) record_angles<R>(pn, qn, g, K.anglog, K.angcap, counters);
     }
@@ -353,7 +354,7 @@ __device__ inline int ntc_outcome_small(const SimConst& K, int cell, int64_t ste
     }
   }
   for (int t = 0; t < cnt; ++t)
-    for (int d = 0; d < 3; ++d) pdv[d * kPool + t] = pdv[d * kPool + t] - v0[d * st + pslot[t]];
+    for (int d = 0; d < 3; ++d) pdv[d * PS + t] = pdv[d * PS + t] - v0[d * st + pslot[t]];
   return cnt;
 }
 
@@ -405,7 +406,7 @@ __device__ __attribute__((always_inline)) inline void cell_outcomes(const SimCon
       const int r0 = L.evp[ev] & 0xffff, nr = L.evp[ev] >> 16;
       for (int t = 0; t < nr; ++t) {
         int j = cs + L.pslot[r0 + t];
-        for (int d = 0; d < 3; ++d) D[d * st + j] += L.pdv[d * kPool + r0 + t];
+        for (int d = 0; d < 3; ++d) D[d * st + j] += L.pdv[d * Lds::kPoolN + r0 + t];
       }
       continue;
     }
@@ -548,7 +549,7 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
       int start = -1;
       if (LANE_ONLY || np_ <= kSmallPairs) {
         start = atomicAdd(&L.pool_n, 2 * np_);
-        if (!LANE_ONLY && start + 2 * np_ > kPool) start = -1;
+        if (!LANE_ONLY && start + 2 * np_ > Lds::kPoolN) start = -1;
       }
       if (!LANE_ONLY && start < 0) {
         L.evp[e] = -1;
@@ -557,7 +558,7 @@ __device__ __attribute__((always_inline)) inline void tile_run(const SimConst& K
       int ci = L.evck[li][e] >> 16, k = L.evck[li][e] & 0xffff;
       int c = c0 + ci;
       int cs = cell_start(ci) - s0, n = cell_start(ci + 1) - cell_start(ci);
-      int cnt = ntc_outcome_small<SIG, R, FULL>(K, c, step, call, k, np_, n, v0 + cs, st,
+      int cnt = ntc_outcome_small<SIG, R, FULL, Lds::kPoolN>(K, c, step, call, k, np_, n, v0 + cs, st,
                                           L.pslot + start, L.pdv + start, a.pairlog, a.cap,
                                           a.counters, acc, gmx);
       L.evp[e] = start | (cnt << 16);
@@ -650,7 +651,7 @@ template <class Lds>
 __device__ inline bool tile_lane_only(const Lds& L, int lo, int hi) {
   bool ok = true;
   for (int li = lo; li < hi; ++li)
-    ok = ok && !L.overflow[li] && !L.big[li] && L.need[li] <= kPool;
+    ok = ok && !L.overflow[li] && !L.big[li] && L.need[li] <= Lds::kPoolN;
   return ok;
 }
 
@@ -830,6 +831,8 @@ __global__ void __launch_bounds__(kTileThreads, FAST ? PIC_F64_LEAN_WAVES : PIC_
   __shared__ double lv0[3 * kLdsSlots], lD[3 * kLdsSlots], lacc[3 * kLdsSlots];
   __shared__ int lkey[kLdsSlots];
   __shared__ int lcs[kCellCache + 1];  // cell starts of a tile of at most kCellCache cells
+  // (one pool size for both instances: a larger one in the general instance
+  // cut its occupancy more than it gained)
   __shared__ CollideLds<double, 2, 128> cl;  // both calls of the pass drawn up front
   __shared__ int sh_i[4];
   const int tid = threadIdx.x;
