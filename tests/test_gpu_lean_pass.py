@@ -4,7 +4,8 @@ the tiles it defers (an outcome over the lane-run size, a full record pool, an
 overflowing event list, a tile larger than its LDS slots); with
 PIC_LEAN_PASS=0 the general instance runs alone.  Both give the same state bit
 for bit, in both precision forms, for light, moderate and heavy collision
-loads, large cells and ensembles."""
+loads, large cells and ensembles; and the mixed instances that sort long event
+lists equal those that scan them."""
 import numpy as np
 import pytest
 
@@ -64,3 +65,23 @@ def test_lean_and_general_pass_agree_in_ensembles(monkeypatch):
     for m in range(3):
         for n, x, y in zip(ITEMS, a[m], b[m]):
             np.testing.assert_array_equal(x, y, err_msg=f"member {m} {n}")
+
+
+@pytest.mark.parametrize("lean", [True, False])
+@pytest.mark.parametrize("case", ["moderate", "heavy", "large_cells"])
+def test_sorted_event_lists_change_no_bit(case, lean, monkeypatch):
+    """The mixed instances that sort long event lists for the cell threads
+    (PIC_SORT_EVENTS=1) and those that scan them (=0) give the same state bit
+    for bit: the sort only changes how a cell thread finds its outcomes, not
+    their order."""
+    pk, (nc, npart, navg) = CASES[case]
+    prob = W.cfg_problem(**pk)
+    disc = W.cfg_disc(nc, npart, 1e-3, 1, navg, cg_tol=1e-13)
+    out = {}
+    for srt in ("1", "0"):
+        monkeypatch.setenv("PIC_SORT_EVENTS", srt)
+        out[srt] = _run(monkeypatch, lean, prob, disc, "mixed", 4)
+    (a, na), (b, nb) = out["1"], out["0"]
+    assert na == nb > 0
+    for n, x, y in zip(ITEMS, a[0], b[0]):
+        np.testing.assert_array_equal(x, y, err_msg=f"{case} lean={lean} {n}")
