@@ -19,7 +19,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kTileB = PIC_TILE_B;               // particle slots that start cells in one tile
 constexpr int kTileThreads = PIC_TILE_THREADS;   // threads of the tile kernels
 #ifndef PIC_LDS_SLOTS
-#define PIC_LDS_SLOTS (PIC_TILE_B + PIC_TILE_B / 2)
+#define PIC_LDS_SLOTS (PIC_TILE_B + PIC_TILE_B / 4)
 #endif
 constexpr int kLdsSlots = PIC_LDS_SLOTS;          // LDS-resident slots per tile
 // Minimum resident waves per SIMD requested for the fused particle kernels
