@@ -107,3 +107,15 @@ def test_plain_solver_launch_is_bitwise_equal(members, monkeypatch):
         for m in range(members):
             for n, r in zip(ITEMS, ref[m]):
                 np.testing.assert_array_equal(b.get(m, getattr(P, n)), r, err_msg=f"{m} {n}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_paper_family_members_equal_single_simulations(precision):
+    """The paper's own functions (Sec. 5.2, Table 1 level 1, coupled and
+    collisional): each member's drift term comes from the drift-term kernel
+    launched for all members at once; members equal the single simulations
+    bit for bit."""
+    P = _pic()
+    prob = W.paper_problem(collisions=True)
+    disc = W.paper_level(1)
+    _run_and_compare(P, prob, disc, precision, 2, 1, 3)
