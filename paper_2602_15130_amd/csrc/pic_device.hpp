@@ -303,7 +303,7 @@ __device__ inline void manufactured_velocity(const SimConst& K, const double a[3
   }
 }
 
-__device__ __noinline__ void paper_position(const SimConst& K, const double xp[3], double t,
+__device__ inline void paper_position(const SimConst& K, const double xp[3], double t,
                                              const double* guess, double x[3]) {
   double e = exp(t / K.T);
   for (int d = 0; d < 3; ++d) {
@@ -312,7 +312,7 @@ __device__ __noinline__ void paper_position(const SimConst& K, const double xp[3
   }
 }
 
-__device__ __noinline__ void cfg_position(const SimConst& K, const double xp[3], double x[3]) {
+__device__ inline void cfg_position(const SimConst& K, const double xp[3], double x[3]) {
   x[0] = K.L[0] * xp[0];
   x[1] = K.L[1] * xp[1];
   CfgZCdf F{K.L[2], K.rho_amp * sinpi(2.0 * x[0] / K.L[0]) * sinpi(2.0 * x[1] / K.L[1])};
@@ -327,7 +327,7 @@ __device__ inline void manufactured_position(const SimConst& K, const double xp[
 }
 
 // xdot^M = -(dF/dt)/f at x^M (Sec. 3.2).
-__device__ __noinline__ void manufactured_xdot(const SimConst& K, const double xm[3], double t,
+__device__ inline void manufactured_xdot(const SimConst& K, const double xm[3], double t,
                                          double xd[3]) {
   if (K.family == 1) {
     xd[0] = xd[1] = xd[2] = 0.0;
